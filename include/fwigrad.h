@@ -1,0 +1,185 @@
+/*
+ * libfwigrad -- checkpointed adjoint FWI gradient with lossily compressed
+ * checkpoints, on one AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the paper's statement of the problem (Kukreja et al.,
+ * "Lossy Checkpoint Compression in Full Waveform Inversion", Sec. 2):
+ *   Eq. (1)  m u_tt - Lap u = q_s                 (acoustic wave equation)
+ *   Eq. (2)  d_sim = P_r A(m)^-1 P_s^T q_s          (fwi_forward)
+ *   Eq. (3)  Phi = 1/2 || d_sim - d_obs ||_2^2       (fwi_gradient, *phi)
+ *   Eq. (4)  grad Phi = sum_t u[t] v_tt[t] = J^T dd  (fwi_gradient, fwi_backward)
+ * with checkpointing (Sec. 1.3, Fig. 2) whose checkpoints are compressed by a
+ * fixed-accuracy block codec (Sec. 1.4, Sec. 3; ckpt_compress).
+ *
+ * Discretisation (Sec. 3 "Reference Problem": 2nd order in time, high order
+ * in space, absorbing layer of nbl points on every side):
+ *   row k = 1..nt:  D u^k = (2M + Lap_h) u^{k-1} - B u^{k-2} + P_s^T q^{k-1}
+ *   M = m/dt^2, D = M + eta/(2dt), B = M - eta/(2dt),
+ *   eta = sigma_max * sum_axes (d_axis/nbl)^2 / vmax^2,
+ *   sigma_max = 3 vmax ln(1000) / (2 nbl h),  d_axis = depth into the layer,
+ *   Lap_h = central order-SO stencil per axis, zero outside the grid,
+ *   d_sim[k-1][r] = u^k at receiver r,
+ *   gradient g = -(1/dt^2) sum_k u^k (lam^k - 2 lam^{k+1} + lam^{k+2}),
+ *   lam from the exact discrete adjoint, run backwards in time.
+ *
+ * Conventions
+ *   - Arrays are C order, depth z last (contiguous): (x, z) in 2D, (x, y, z)
+ *     in 3D.  A "computational grid" array has dims n[i] + 2*nbl.
+ *   - Pointers marked [device] are HIP device memory owned by the caller;
+ *     [host] are host memory owned by the caller.  The library owns only its
+ *     workspaces and checkpoint pools (inside a context or a tape).
+ *   - Every call is asynchronous on the stream passed in, except that host
+ *     outputs (*phi, *nbytes, status codes that depend on device results)
+ *     are produced after the call synchronises that stream.
+ *   - Every function returns an int status; 0 is FWI_OK.  On error the
+ *     outputs are undefined and fwi_last_error() describes the failure.  No
+ *     C++ exception crosses this interface.
+ */
+#ifndef FWIGRAD_H
+#define FWIGRAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FWI_OK = 0,
+    FWI_EINVAL = -1,      /* invalid argument (dims, order, atol, indices) */
+    FWI_ENOMEM = -2,      /* device allocation failed */
+    FWI_ECAPACITY = -3,   /* checkpoint pool or output buffer too small */
+    FWI_ECORRUPT = -4,    /* compressed stream fails validation */
+    FWI_ENONFINITE = -5,  /* NaN/Inf handed to the codec */
+    FWI_EUNSTABLE = -6,   /* dt above the leapfrog stability limit */
+    FWI_EHIP = -7         /* HIP runtime error */
+};
+
+typedef struct fwi_ctx fwi_ctx;
+typedef struct fwi_tape fwi_tape;
+
+/* Grid and time discretisation [host].  n = PHYSICAL dims (n[2] unused in
+ * 2D); space_order in {4, 8, 16}; nt = number of time steps; vmax = the
+ * largest velocity of the model (m/s), used by the absorbing layer and by
+ * the stability check dt <= 2h / (vmax sqrt(ndim S)), S the Nyquist value of
+ * the 1D stencil symbol (checked on the host before any launch). */
+typedef struct {
+    int ndim;
+    int n[3];
+    double h;
+    int space_order;
+    int nbl;
+    int nt;
+    double dt;
+    double vmax;
+} fwi_grid;
+
+/* One shot.  src: physical-grid node [host]; wavelet: [device] float32,
+ * nt samples, sample k injected on the step k -> k+1; rec: [host] int32,
+ * nrec x ndim physical-grid nodes (repeats allowed). */
+typedef struct {
+    int src[3];
+    const float *wavelet;
+    int nrec;
+    const int32_t *rec;
+} fwi_shot;
+
+/* Checkpointing.  nslots = Revolve slots (each holds both leapfrog levels);
+ * compress = 0 stores exact copies (the gradient then equals the store-all
+ * gradient bit for bit), 1 stores each level compressed with absolute
+ * tolerance atol; pool_bytes sizes the checkpoint pool of a tape
+ * (fwi_forward_ckpt), 0 = the context's default. */
+typedef struct {
+    int nslots;
+    int compress;
+    double atol;
+    size_t pool_bytes;
+} fwi_ckpt_cfg;
+
+/* Timing and sizes of the last call on a context [host]. */
+typedef struct {
+    double ms_total;          /* whole call, HIP events */
+    double ms_forward;        /* sum of forward-step kernels */
+    double ms_adjoint;        /* sum of adjoint+imaging kernels */
+    double ms_encode;         /* compress: encode + scan + pack */
+    double ms_decode;
+    long long n_forward;      /* forward-step launches */
+    long long n_adjoint;
+    long long n_encode;       /* fields compressed */
+    long long n_decode;       /* fields decompressed */
+    long long ckpt_bytes;     /* sum of stored checkpoint bytes */
+    long long ckpt_raw_bytes; /* raw bytes those checkpoints represent */
+    long long pool_high;      /* high-water mark of the pool (bytes) */
+} fwi_stats;
+
+/* Revolve action (see fwi_revolve_plan). */
+enum { FWI_ADVANCE = 0, FWI_TAKESHOT = 1, FWI_RESTORE = 2, FWI_REVERSE = 3, FWI_FREE = 4 };
+typedef struct { int op; int a; int b; } fwi_action;
+
+/* Context: device ordinal and default checkpoint pool size.  Workspaces are
+ * allocated lazily and reused.  Not thread-safe; one context per thread. */
+int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes);
+int fwi_ctx_destroy(fwi_ctx *ctx);
+/* Collect per-kernel HIP-event timings in later calls (small overhead). */
+int fwi_ctx_set_timing(fwi_ctx *ctx, int on);
+int fwi_ctx_stats(const fwi_ctx *ctx, fwi_stats *out);
+/* Message of the last failure on this thread (static storage). */
+const char *fwi_last_error(void);
+
+/* Eq. (2): d_sim [device, nt x nrec] of model m [device, computational grid,
+ * squared slowness s^2/m^2]. */
+int fwi_forward(fwi_ctx *ctx, const fwi_grid *g, const float *m,
+                const fwi_shot *shot, float *d_sim, hipStream_t stream);
+
+/* Eqs. (3)-(4): Phi [host] and grad [device, computational grid,
+ * overwritten] for observed data d_obs [device, nt x nrec], with the
+ * checkpointing of cfg.  Only the forward wavefield is ever compressed; the
+ * adjoint runs at full precision.  FWI_ECAPACITY if the context's pool
+ * cannot hold the checkpoints (retry with fewer slots). */
+int fwi_gradient(fwi_ctx *ctx, const fwi_grid *g, const float *m,
+                 const fwi_shot *shot, const float *d_obs,
+                 const fwi_ckpt_cfg *cfg, float *grad, double *phi,
+                 hipStream_t stream);
+
+/* Split form for automatic differentiation: the forward sweep writes d_sim
+ * and keeps its checkpoints in a new tape (owns device memory until
+ * fwi_tape_free); fwi_backward then runs the reverse sweep with any
+ * receiver-side adjoint source dd [device, nt x nrec] and writes
+ * grad = J^T dd (Eq. 4).  A tape can be back-propagated once.  The model
+ * and wavelet must stay unchanged and alive until fwi_backward returns. */
+int fwi_forward_ckpt(fwi_ctx *ctx, const fwi_grid *g, const float *m,
+                     const fwi_shot *shot, const fwi_ckpt_cfg *cfg,
+                     float *d_sim, fwi_tape **tape, hipStream_t stream);
+int fwi_backward(fwi_ctx *ctx, fwi_tape *tape, const float *dd, float *grad,
+                 hipStream_t stream);
+int fwi_tape_free(fwi_tape *tape);
+
+/* Codec (Sec. 1.4 / Sec. 3: ZFP-style fixed accuracy).  field [device]
+ * float32, C order, ndim in {2, 3}; every decoded value is within atol of
+ * the input when max|x| over each 4^ndim block is below atol * 2^23.
+ * ckpt_bound: worst-case stream bytes [host].  ckpt_compress writes the
+ * stream to out [device, cap bytes] and its size to *nbytes [host] (after a
+ * stream sync); FWI_ECAPACITY if cap is too small, FWI_ENONFINITE on NaN or
+ * Inf input.  ckpt_decompress validates the header and tables (host copy of
+ * the header) and writes field [device]. */
+int ckpt_bound(int ndim, const int n[3], size_t *max_bytes);
+int ckpt_compress(fwi_ctx *ctx, const float *field, int ndim, const int n[3],
+                  double atol, void *out, size_t cap, size_t *nbytes,
+                  hipStream_t stream);
+int ckpt_decompress(fwi_ctx *ctx, const void *stream_bytes, size_t nbytes,
+                    float *field, int ndim, const int n[3], hipStream_t stream);
+
+/* Host-only binomial checkpoint schedule reversing states N..1 with nslots
+ * slots (minimal forward steps; largest optimal split).  out [host] holds up
+ * to cap actions; *nactions receives the full count (FWI_ECAPACITY if it
+ * exceeds cap).  *nforward [host, may be NULL] receives the number of
+ * forward steps of the schedule. */
+int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
+                     int *nactions, long long *nforward);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FWIGRAD_H */

@@ -1,0 +1,777 @@
+// Fixed-accuracy block codec for float32 wavefields (paper Sec. 1.4 and
+// Sec. 3: ZFP-style compression of checkpoints at absolute tolerance atol).
+//
+// Stream (little endian):
+//   64-byte header | u64 bit offset per super-chunk of 256 chunks |
+//   u32 bit offset per chunk, relative to its super-chunk | pad to 8 bytes |
+//   payload: block bit strings, LSB first in u64 words.
+// A chunk holds K blocks (16 in 3D, 64 in 2D); chunk c = 64 g + l owns the
+// blocks g*64K + j*64 + l, j = 0..K-1, so that the 64 lanes of a wave, one
+// chunk each, touch 64 neighbouring blocks at every step j.
+//
+// Per block (4^d values): block exponent emax; skip bit when the block is
+// below atol; else exact conversion to int32 at Q = 24 fractional bits,
+// a reversible lifting along z, y, x, reorder by total sequency, negabinary,
+// then bit planes from the top non-empty one down to P: refinement bits of
+// the significant prefix, then either 0 (no new significance) or 1 followed
+// by an Elias-gamma code of the extent and the raw bits below its top bit.
+//
+// GPU mapping: one lane encodes/decodes one chunk, block after block, with
+// the whole block in registers.  The 64-coefficient x 32-plane bit matrix is
+// turned into plane masks with an in-register 32x32 bit transpose, so every
+// per-plane step is a handful of vector instructions and no lane ever waits
+// on another.  Encoding writes each chunk to a private scratch slot; a tile
+// scan places the chunks and a pack kernel concatenates them at bit
+// granularity (each output word is assembled by exactly one lane).
+#include <cstring>
+
+#include "internal.hpp"
+
+namespace fwi {
+
+namespace {
+
+constexpr int QB = 24;
+
+// ------------------------------------------------------- sequency tables
+template <int D>
+struct Seq {
+    static constexpr int SZ = D == 3 ? 64 : 16;
+    int perm[SZ];
+    constexpr Seq() : perm()
+    {
+        int s = 0;
+        for (int tot = 0; tot <= 3 * D; ++tot)
+            for (int li = 0; li < SZ; ++li) {
+                int ix = D == 3 ? (li >> 4) : (li >> 2);
+                int iy = D == 3 ? ((li >> 2) & 3) : 0;
+                int iz = li & 3;
+                if (ix + iy + iz == tot) perm[s++] = li;
+            }
+    }
+};
+
+template <int D>
+struct GeomC {
+    static constexpr int SZ = D == 3 ? 64 : 16;
+    static constexpr int TP = D == 3 ? 31 : 29;
+    static constexpr int G = D == 3 ? 5 : 4;
+    static constexpr int K = D == 3 ? 16 : 64;
+};
+
+__device__ __forceinline__ int asr1(uint32_t v) { return (int)v >> 1; }
+
+__device__ __forceinline__ void lift_fwd(int &a0, int &a1, int &a2, int &a3)
+{
+    uint32_t h0 = (uint32_t)a1 - (uint32_t)a0;
+    uint32_t l0 = (uint32_t)a0 + (uint32_t)asr1(h0);
+    uint32_t h1 = (uint32_t)a3 - (uint32_t)a2;
+    uint32_t l1 = (uint32_t)a2 + (uint32_t)asr1(h1);
+    uint32_t H = l1 - l0;
+    uint32_t L = l0 + (uint32_t)asr1(H);
+    h1 -= h0;
+    h0 -= (uint32_t)asr1(H);
+    a0 = (int)L; a1 = (int)H; a2 = (int)h0; a3 = (int)h1;
+}
+
+__device__ __forceinline__ void lift_inv(int &a0, int &a1, int &a2, int &a3)
+{
+    uint32_t L = a0, H = a1, h0 = a2, h1 = a3;
+    h0 += (uint32_t)asr1(H);
+    h1 += h0;
+    uint32_t l0 = L - (uint32_t)asr1(H);
+    uint32_t l1 = H + l0;
+    uint32_t x0 = l0 - (uint32_t)asr1(h0);
+    uint32_t x1 = h0 + x0;
+    uint32_t x2 = l1 - (uint32_t)asr1(h1);
+    uint32_t x3 = h1 + x2;
+    a0 = (int)x0; a1 = (int)x1; a2 = (int)x2; a3 = (int)x3;
+}
+
+template <int D>
+__device__ __forceinline__ void block_fwd(int *c)
+{
+    if (D == 3) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lift_fwd(c[4 * i], c[4 * i + 1], c[4 * i + 2], c[4 * i + 3]);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int z = 0; z < 4; ++z) {
+                int b = 16 * x + z;
+                lift_fwd(c[b], c[b + 4], c[b + 8], c[b + 12]);
+            }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lift_fwd(c[i], c[i + 16], c[i + 32], c[i + 48]);
+    } else {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) lift_fwd(c[4 * x], c[4 * x + 1], c[4 * x + 2], c[4 * x + 3]);
+#pragma unroll
+        for (int z = 0; z < 4; ++z) lift_fwd(c[z], c[z + 4], c[z + 8], c[z + 12]);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void block_inv(int *c)
+{
+    if (D == 3) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lift_inv(c[i], c[i + 16], c[i + 32], c[i + 48]);
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int z = 0; z < 4; ++z) {
+                int b = 16 * x + z;
+                lift_inv(c[b], c[b + 4], c[b + 8], c[b + 12]);
+            }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) lift_inv(c[4 * i], c[4 * i + 1], c[4 * i + 2], c[4 * i + 3]);
+    } else {
+#pragma unroll
+        for (int z = 0; z < 4; ++z) lift_inv(c[z], c[z + 4], c[z + 8], c[z + 12]);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) lift_inv(c[4 * x], c[4 * x + 1], c[4 * x + 2], c[4 * x + 3]);
+    }
+}
+
+// 32x32 bit-matrix transpose in place: afterwards bit c of a[r] is the
+// former bit r of a[c].  Five rounds of block swaps.
+__device__ __forceinline__ void transpose32(uint32_t *a)
+{
+#pragma unroll
+    for (int j = 16, round = 0; round < 5; j >>= 1, ++round) {
+        const uint32_t m = j == 16 ? 0x0000FFFFu : j == 8 ? 0x00FF00FFu : j == 4 ? 0x0F0F0F0Fu
+                         : j == 2 ? 0x33333333u : 0x55555555u;
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            if (k & j) continue;
+            uint32_t t = ((a[k] >> j) ^ a[k + j]) & m;
+            a[k] ^= t << j;
+            a[k + j] ^= t;
+        }
+    }
+}
+
+__device__ __forceinline__ uint32_t lowmask32(int n)
+{
+    return n >= 32 ? 0xFFFFFFFFu : ((1u << n) - 1u);
+}
+
+__device__ __forceinline__ unsigned long long lowmask64(int n)
+{
+    return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+}
+
+struct BitWriter {
+    unsigned long long acc;
+    int fill;
+    unsigned long long *out;
+    long w;
+    __device__ __forceinline__ void put(uint32_t v, int n)    // v < 2^n, n <= 32
+    {
+        if (n <= 0) return;
+        acc |= (unsigned long long)v << fill;
+        fill += n;
+        if (fill >= 64) {
+            out[w++] = acc;
+            fill -= 64;
+            acc = fill ? ((unsigned long long)v >> (n - fill)) : 0ull;
+        }
+    }
+    __device__ __forceinline__ void put64(unsigned long long v, int n)   // v < 2^n, n <= 64
+    {
+        if (n > 32) {
+            put((uint32_t)v, 32);
+            put((uint32_t)(v >> 32), n - 32);
+        } else {
+            put((uint32_t)v, n);
+        }
+    }
+};
+
+struct BitReader {
+    const unsigned long long *w;
+    long nw;
+    long idx;                       // word index of lo
+    unsigned long long lo, hi;
+    unsigned long long pos;         // absolute bit position
+    __device__ __forceinline__ unsigned long long ld(long i) const { return i < nw && i >= 0 ? w[i] : 0ull; }
+    __device__ __forceinline__ void seek(unsigned long long p)
+    {
+        pos = p;
+        idx = (long)(p >> 6);
+        lo = ld(idx);
+        hi = ld(idx + 1);
+    }
+    __device__ __forceinline__ uint32_t peek32() const
+    {
+        int sh = (int)(pos & 63);
+        unsigned long long v = sh ? ((lo >> sh) | (hi << (64 - sh))) : lo;
+        return (uint32_t)v;
+    }
+    __device__ __forceinline__ void skip(int n)
+    {
+        pos += (unsigned long long)n;
+        long ni = (long)(pos >> 6);
+        if (ni != idx) {
+            if (ni == idx + 1) {
+                lo = hi;
+                hi = ld(ni + 1);
+            } else {
+                lo = ld(ni);
+                hi = ld(ni + 1);
+            }
+            idx = ni;
+        }
+    }
+    __device__ __forceinline__ uint32_t get(int n)     // n <= 32
+    {
+        if (n <= 0) return 0u;
+        uint32_t v = peek32() & lowmask32(n);
+        skip(n);
+        return v;
+    }
+    __device__ __forceinline__ unsigned long long get64(int n)
+    {
+        if (n > 32) {
+            unsigned long long a = get(32);
+            return a | ((unsigned long long)get(n - 32) << 32);
+        }
+        return get(n);
+    }
+};
+
+__device__ __forceinline__ long chunk_block(long c, int j, int K, long nblocks)
+{
+    long b = (c >> 6) * 64L * K + (long)j * 64 + (c & 63);
+    return b < nblocks ? b : -1;
+}
+
+__device__ __forceinline__ void block_coords(long b, const long *nb, long &bx, long &by, long &bz)
+{
+    bz = b % nb[2];
+    long r = b / nb[2];
+    by = r % nb[1];
+    bx = r / nb[1];
+}
+
+// ------------------------------------------------------------------ encode
+template <int D>
+__global__ __launch_bounds__(64)
+void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, long nblocks,
+                   long nchunks, int minexp, unsigned long long *scratch, long chunk_words,
+                   unsigned long long *chunk_bits, unsigned int *flags)
+{
+    using GC = GeomC<D>;
+    constexpr int SZ = GC::SZ;
+    constexpr Seq<D> seq{};
+    const long c = (long)blockIdx.x * 64 + threadIdx.x;
+    if (c >= nchunks) return;
+    const long nb[3] = {nb0, nb1, nb2};
+    BitWriter bw{0ull, 0, scratch + c * chunk_words, 0};
+    bool nonfinite = false;
+    for (int j = 0; j < GC::K; ++j) {
+        const long b = chunk_block(c, j, GC::K, nblocks);
+        if (b < 0) break;
+        long bx, by, bz;
+        block_coords(b, nb, bx, by, bz);
+        uint32_t w[SZ];
+#pragma unroll
+        for (int li = 0; li < SZ; ++li) {
+            const int ix = D == 3 ? (li >> 4) : (li >> 2);
+            const int iy = D == 3 ? ((li >> 2) & 3) : 0;
+            const int iz = li & 3;
+            long x = 4 * bx + ix, y = 4 * by + iy, z = 4 * bz + iz;
+            x = x < f.n[0] ? x : f.n[0] - 1;
+            y = y < f.n[1] ? y : f.n[1] - 1;
+            z = z < f.n[2] ? z : f.n[2] - 1;
+            w[li] = __float_as_uint(src[x * f.sx + y * f.sy + z]);
+        }
+        int Emax = 0;
+#pragma unroll
+        for (int li = 0; li < SZ; ++li) {
+            const int E = (int)((w[li] >> 23) & 0xFFu);
+            nonfinite |= (E == 0xFF);
+            Emax = E > Emax ? E : Emax;
+        }
+        const int emax = Emax - 126;
+        if (Emax == 0 || emax <= minexp) {
+            bw.put(0u, 1);
+            continue;
+        }
+        int ci[SZ];
+#pragma unroll
+        for (int li = 0; li < SZ; ++li) {
+            const int E = (int)((w[li] >> 23) & 0xFFu);
+            const uint32_t mant = (w[li] & 0x7FFFFFu) | 0x800000u;
+            const int sh = Emax - E;
+            uint32_t mag = sh >= 32 ? 0u : (mant >> sh);
+            mag = E == 0 ? 0u : mag;
+            ci[li] = (w[li] >> 31) ? -(int)mag : (int)mag;
+        }
+        block_fwd<D>(ci);
+        uint32_t lo[32], hi[32];
+#pragma unroll
+        for (int s = 0; s < 32; ++s) {
+            lo[s] = s < SZ ? (((uint32_t)ci[seq.perm[s]] + 0xAAAAAAAAu) ^ 0xAAAAAAAAu) : 0u;
+            hi[s] = (D == 3) ? (((uint32_t)ci[seq.perm[32 + (s & 31)]] + 0xAAAAAAAAu) ^ 0xAAAAAAAAu) : 0u;
+        }
+        transpose32(lo);
+        if (D == 3) transpose32(hi);
+        int P = minexp - emax + QB - GC::G;
+        P = P < 0 ? 0 : P;
+        int fp = -1;
+#pragma unroll
+        for (int p = 0; p < 32; ++p)
+            if (p >= P && (lo[p] | hi[p])) fp = p;
+        const int zs = (fp < 0 || GC::TP - fp > 7) ? 7 : GC::TP - fp;
+        const int S = GC::TP - zs;
+        bw.put(1u, 1);
+        bw.put((uint32_t)(emax + 127), 8);
+        bw.put((uint32_t)zs, 3);
+        int n = 0;
+#pragma unroll
+        for (int p = 31; p >= 0; --p) {
+            if (p > S || p < P) continue;
+            const unsigned long long xp = ((unsigned long long)hi[p] << 32) | lo[p];
+            bw.put64(xp & lowmask64(n), n);
+            if (n < SZ) {
+                const unsigned long long xr = xp >> n;
+                if (xr == 0ull) {
+                    bw.put(0u, 1);
+                } else {
+                    const int t = 63 - __clzll((long long)xr);
+                    const uint32_t v = (uint32_t)t + 1u;
+                    const int L = 31 - __clz((int)v);
+                    // 1, then L zeros, a one and the L low bits of v
+                    bw.put(1u, 1);
+                    bw.put((1u << L) | ((v & lowmask32(L)) << (L + 1)), 2 * L + 1);
+                    bw.put64(xr & lowmask64(t), t);
+                    n += t + 1;
+                }
+            }
+        }
+    }
+    if (bw.fill) bw.out[bw.w] = bw.acc;
+    chunk_bits[c] = (unsigned long long)bw.w * 64ull + (unsigned long long)bw.fill;
+    if (nonfinite) atomicOr(flags, 1u);
+}
+
+// --------------------------------------------------------------- placement
+constexpr int TILE = 1024;
+
+__global__ __launch_bounds__(TILE)
+void tile_sum_kernel(const unsigned long long *chunk_bits, long nchunks, unsigned long long *tile_sum)
+{
+    __shared__ unsigned long long red[TILE];
+    const long c = (long)blockIdx.x * TILE + threadIdx.x;
+    red[threadIdx.x] = c < nchunks ? chunk_bits[c] : 0ull;
+    __syncthreads();
+    for (int s = TILE / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = red[0];
+}
+
+struct PlanArgs {
+    int ndim;
+    unsigned int dims[3];
+    double atol;
+    int minexp, guard, tp, log2k;
+    long nblocks, nchunks, nsuper;
+    long table_bytes;
+    int ntiles;
+    unsigned long long *tile_sum;     // in: sums, out: exclusive prefix
+    unsigned char *dst;               // fixed destination or nullptr
+    unsigned long long cap;
+    unsigned char *pool;
+    unsigned long long pool_cap;
+    StreamSlot *slots;
+    int slot_index, prev_index;
+    unsigned long long *out_bytes;
+    unsigned long long *dst_offset;   // device scratch: byte offset of dst in pool (or 0)
+    unsigned int *flags;
+    unsigned long long *pool_high;
+    unsigned long long *total_bytes;
+};
+
+__device__ __forceinline__ void st64(unsigned char *p, unsigned long long v)
+{
+    for (int i = 0; i < 8; ++i) p[i] = (unsigned char)(v >> (8 * i));
+}
+
+__device__ __forceinline__ void st32(unsigned char *p, unsigned int v)
+{
+    for (int i = 0; i < 4; ++i) p[i] = (unsigned char)(v >> (8 * i));
+}
+
+__global__ __launch_bounds__(256)
+void plan_kernel(PlanArgs a)
+{
+    __shared__ unsigned long long sc[256];
+    __shared__ unsigned long long carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < a.ntiles; base += 256) {
+        const int t = base + threadIdx.x;
+        unsigned long long v = t < a.ntiles ? a.tile_sum[t] : 0ull;
+        sc[threadIdx.x] = v;
+        __syncthreads();
+        for (int s = 1; s < 256; s <<= 1) {
+            unsigned long long add = (int)threadIdx.x >= s ? sc[threadIdx.x - s] : 0ull;
+            __syncthreads();
+            sc[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (t < a.ntiles) a.tile_sum[t] = carry + sc[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 255) carry += sc[255];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const unsigned long long total_bits = carry;
+    const unsigned long long bytes = 64ull + (unsigned long long)a.table_bytes + 8ull * ((total_bits + 63ull) / 64ull);
+    *a.out_bytes = bytes;
+    *a.total_bytes += bytes;
+    unsigned char *dst = a.dst;
+    unsigned long long off = 0;
+    bool ok = true;
+    if (dst) {
+        ok = bytes <= a.cap;
+    } else {
+        unsigned long long start = 0;
+        if (a.prev_index >= 0) {
+            const StreamSlot &p = a.slots[a.prev_index];
+            start = (p.offset + p.bytes + 255ull) & ~255ull;
+        }
+        off = start;
+        // 8 bytes of slack so readers may fetch one word past the end
+        ok = start + bytes + 8ull <= a.pool_cap;
+        StreamSlot s;
+        s.offset = start;
+        s.bytes = ok ? bytes : 0ull;
+        s.valid = ok ? 1 : 0;
+        s.pad = 0;
+        a.slots[a.slot_index] = s;
+        if (ok) {
+            dst = a.pool + start;
+            unsigned long long end = start + bytes;
+            if (end > *a.pool_high) *a.pool_high = end;
+        }
+    }
+    *a.dst_offset = off;
+    if (!ok) {
+        atomicOr(a.flags, 2u);
+        return;
+    }
+    // header
+    unsigned char *h = dst;
+    h[0] = 'F'; h[1] = 'W'; h[2] = 'Z'; h[3] = '1';
+    h[4] = 1; h[5] = 0; h[6] = (unsigned char)a.ndim; h[7] = QB;
+    st32(h + 8, a.dims[0]); st32(h + 12, a.dims[1]); st32(h + 16, a.dims[2]);
+    h[20] = (unsigned char)a.guard; h[21] = (unsigned char)a.log2k;
+    h[22] = (unsigned char)a.tp; h[23] = 0;
+    st64(h + 24, (unsigned long long)__double_as_longlong(a.atol));
+    st32(h + 32, (unsigned int)a.minexp);
+    st32(h + 36, (unsigned int)a.nchunks);
+    st64(h + 40, (unsigned long long)a.nblocks);
+    st64(h + 48, total_bits);
+    st64(h + 56, bytes);
+}
+
+struct PackArgs {
+    const unsigned long long *scratch;
+    long chunk_words;
+    const unsigned long long *chunk_bits;
+    long nchunks, nsuper;
+    long table_bytes;
+    const unsigned long long *tile_prefix;
+    unsigned char *dst;          // fixed destination, or nullptr (pool + *dst_offset)
+    unsigned char *pool;
+    const unsigned long long *dst_offset;
+    const unsigned int *flags;
+};
+
+__global__ __launch_bounds__(TILE)
+void pack_kernel(PackArgs a)
+{
+    __shared__ unsigned long long sc[TILE];
+    if (*a.flags & 2u) return;
+    unsigned char *dst = a.dst ? a.dst : a.pool + *a.dst_offset;
+    const long c = (long)blockIdx.x * TILE + threadIdx.x;
+    const unsigned long long len = c < a.nchunks ? a.chunk_bits[c] : 0ull;
+    sc[threadIdx.x] = len;
+    __syncthreads();
+    for (int s = 1; s < TILE; s <<= 1) {
+        unsigned long long add = (int)threadIdx.x >= s ? sc[threadIdx.x - s] : 0ull;
+        __syncthreads();
+        sc[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (c >= a.nchunks) return;
+    const unsigned long long off = a.tile_prefix[blockIdx.x] + sc[threadIdx.x] - len;
+    // tables: super-chunk base (the first chunk of each super-chunk) and
+    // relative chunk offsets (a super-chunk of 256 lies inside one tile)
+    unsigned char *tab = dst + 64;
+    const long sup0 = (c / 256) * 256 - (long)blockIdx.x * TILE;   // in-tile index of the super-chunk head
+    const unsigned long long head = a.tile_prefix[blockIdx.x] + (sup0 > 0 ? sc[sup0 - 1] : 0ull);
+    if ((c & 255) == 0) st64(tab + 8 * (c / 256), off);
+    st32(tab + 8 * a.nsuper + 4 * c, (unsigned int)(off - head));
+    // payload words whose first bit lies in this chunk
+    unsigned long long *out = (unsigned long long *)(dst + 64 + a.table_bytes);
+    if (len == 0) return;
+    const unsigned long long end = off + len;
+    for (unsigned long long wb = (off + 63ull) & ~63ull; wb < end; wb += 64ull) {
+        unsigned long long word = 0ull;
+        int got = 0;
+        long cc = c;
+        unsigned long long cstart = off, clen = len;
+        unsigned long long pos = wb;
+        while (got < 64) {
+            if (pos >= cstart + clen) {
+                // next non-empty chunk
+                ++cc;
+                if (cc >= a.nchunks) break;
+                cstart += clen;
+                clen = a.chunk_bits[cc];
+                continue;
+            }
+            const unsigned long long lb = pos - cstart;       // local bit in chunk cc
+            const unsigned long long *src = a.scratch + cc * a.chunk_words;
+            const long wi = (long)(lb >> 6);
+            const int sh = (int)(lb & 63);
+            unsigned long long v = src[wi] >> sh;
+            int avail = 64 - sh;
+            if ((unsigned long long)avail > clen - lb) avail = (int)(clen - lb);
+            int take = avail < 64 - got ? avail : 64 - got;
+            v &= lowmask64(take);
+            word |= v << got;
+            got += take;
+            pos += (unsigned long long)take;
+        }
+        out[wb >> 6] = word;
+    }
+}
+
+// ------------------------------------------------------------------ decode
+template <int D>
+__global__ __launch_bounds__(64)
+void decode_kernel(FieldView f, float *dst, const unsigned char *stream, const unsigned char *pool,
+                   const StreamSlot *slots, int slot_index, long nb0, long nb1, long nb2,
+                   long nblocks, long nchunks, long nsuper, long table_bytes, unsigned int *flags)
+{
+    using GC = GeomC<D>;
+    constexpr int SZ = GC::SZ;
+    constexpr Seq<D> seq{};
+    const long c = (long)blockIdx.x * 64 + threadIdx.x;
+    if (c >= nchunks) return;
+    const unsigned char *s = stream;
+    if (!s) {
+        const StreamSlot sl = slots[slot_index];
+        if (!sl.valid) return;
+        s = pool + sl.offset;
+    }
+    const long nb[3] = {nb0, nb1, nb2};
+    unsigned long long pbits = 0, sup = 0;
+    unsigned int rel = 0;
+    for (int i = 0; i < 8; ++i) pbits |= (unsigned long long)s[48 + i] << (8 * i);
+    for (int i = 0; i < 8; ++i) sup |= (unsigned long long)s[64 + 8 * (c / 256) + i] << (8 * i);
+    for (int i = 0; i < 4; ++i) rel |= (unsigned int)s[64 + 8 * nsuper + 4 * c + i] << (8 * i);
+    const int minexp = (int)((unsigned int)s[32] | ((unsigned int)s[33] << 8) |
+                             ((unsigned int)s[34] << 16) | ((unsigned int)s[35] << 24));
+    BitReader br;
+    br.w = (const unsigned long long *)(s + 64 + table_bytes);
+    br.nw = (long)((pbits + 63) / 64);
+    br.seek(sup + rel);
+    for (int j = 0; j < GC::K; ++j) {
+        const long b = chunk_block(c, j, GC::K, nblocks);
+        if (b < 0) break;
+        float vals[SZ];
+        if (br.pos >= pbits) { atomicOr(flags, 4u); return; }
+        if (!br.get(1)) {
+#pragma unroll
+            for (int li = 0; li < SZ; ++li) vals[li] = 0.0f;
+        } else {
+            const int emax = (int)br.get(8) - 127;
+            const int zs = (int)br.get(3);
+            const int S = GC::TP - zs;
+            int P = minexp - emax + QB - GC::G;
+            P = P < 0 ? 0 : P;
+            uint32_t lo[32], hi[32];
+            int n = 0;
+            bool bad = false;
+#pragma unroll
+            for (int p = 31; p >= 0; --p) {
+                lo[p] = 0u;
+                hi[p] = 0u;
+                if (p > S || p < P || bad) continue;
+                unsigned long long xp = br.get64(n);
+                if (n < SZ && br.get(1)) {
+                    const uint32_t pk = br.peek32();
+                    const int L = pk ? __ffs((int)pk) - 1 : 32;
+                    if (L > 6) { bad = true; continue; }
+                    br.skip(L + 1);
+                    const int t = (int)(((1u << L) | br.get(L)) - 1u);
+                    if (t > SZ - 1 - n) { bad = true; continue; }
+                    const unsigned long long raw = br.get64(t);
+                    xp |= ((1ull << t) | raw) << n;
+                    n += t + 1;
+                }
+                lo[p] = (uint32_t)xp;
+                hi[p] = (uint32_t)(xp >> 32);
+            }
+            if (bad || br.pos > pbits) { atomicOr(flags, 4u); return; }
+            transpose32(lo);
+            if (D == 3) transpose32(hi);
+            int ci[SZ];
+#pragma unroll
+            for (int s2 = 0; s2 < SZ; ++s2) {
+                const uint32_t u = s2 < 32 ? lo[s2] : hi[s2 & 31];
+                ci[seq.perm[s2]] = (int)((u ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
+            }
+            block_inv<D>(ci);
+#pragma unroll
+            for (int li = 0; li < SZ; ++li) {
+                const int iv = ci[li];
+                float fv = (float)iv;
+                uint32_t bits = __float_as_uint(fv);
+                const int E = (int)((bits >> 23) & 0xFFu) + emax - QB;
+                if (iv == 0 || E <= 0) bits = 0u;
+                else if (E >= 255) bits = (bits & 0x80000000u) | 0x7F7FFFFFu;
+                else bits = (bits & ~(0xFFu << 23)) | ((uint32_t)E << 23);
+                vals[li] = __uint_as_float(bits);
+            }
+        }
+        long bx, by, bz;
+        block_coords(b, nb, bx, by, bz);
+#pragma unroll
+        for (int li = 0; li < SZ; ++li) {
+            const int ix = D == 3 ? (li >> 4) : (li >> 2);
+            const int iy = D == 3 ? ((li >> 2) & 3) : 0;
+            const int iz = li & 3;
+            const long x = 4 * bx + ix, y = 4 * by + iy, z = 4 * bz + iz;
+            if (x < f.n[0] && y < f.n[1] && z < f.n[2]) dst[x * f.sx + y * f.sy + z] = vals[li];
+        }
+    }
+}
+
+int minexp_of(double atol)
+{
+    unsigned long long bits;
+    memcpy(&bits, &atol, 8);
+    return (int)((bits >> 52) & 0x7FF) - 1023;
+}
+
+}  // namespace
+
+CodecGeom codec_geom(int ndim, const long n[3])
+{
+    CodecGeom g;
+    g.ndim = ndim;
+    g.nblocks = 1;
+    for (int d = 0; d < 3; ++d) {
+        g.nb[d] = (n[d] + 3) / 4;
+        g.nblocks *= g.nb[d];
+    }
+    g.kblk = ndim == 3 ? 16 : 64;
+    g.size = ndim == 3 ? 64 : 16;
+    g.tp = ndim == 3 ? 31 : 29;
+    g.guard = ndim == 3 ? 5 : 4;
+    const long per_group = 64L * g.kblk;
+    g.nchunks = 64L * ((g.nblocks + per_group - 1) / per_group);
+    g.nsuper = (g.nchunks + 255) / 256;
+    g.table_bytes = ((8 * g.nsuper + 4 * g.nchunks) + 7) & ~7L;
+    const int lg = ndim == 3 ? 6 : 4;
+    const long block_bits = 12 + (long)(g.tp + 1) * (g.size + 1 + 2 * lg);
+    g.max_chunk_words = (g.kblk * block_bits + 63) / 64;
+    return g;
+}
+
+long codec_bound(const CodecGeom &g)
+{
+    const int lg = g.ndim == 3 ? 6 : 4;
+    const long block_bits = 12 + (long)(g.tp + 1) * (g.size + 1 + 2 * lg);
+    return 64 + g.table_bytes + 8 * ((g.nblocks * block_bits + 63) / 64);
+}
+
+// Encode pipeline: encode (lane per chunk) -> tile sums -> plan (placement,
+// header) -> pack (tables + payload).  Scratch layout: scratch words
+// (nchunks * max_chunk_words), chunk_bits (nchunks), tile sums.
+void codec_encode(const EncodeArgs &e, hipStream_t st)
+{
+    CodecGeom g = codec_geom(e.f.ndim, e.f.n);
+    const int minexp = minexp_of(e.atol);
+    const int nwaves = (int)(g.nchunks / 64);
+    if (e.f.ndim == 3)
+        hipLaunchKernelGGL(encode_kernel<3>, dim3(nwaves), dim3(64), 0, st, e.f, e.src, g.nb[0], g.nb[1],
+                           g.nb[2], g.nblocks, g.nchunks, minexp, e.scratch, g.max_chunk_words,
+                           e.chunk_bits, e.flags);
+    else
+        hipLaunchKernelGGL(encode_kernel<2>, dim3(nwaves), dim3(64), 0, st, e.f, e.src, g.nb[0], g.nb[1],
+                           g.nb[2], g.nblocks, g.nchunks, minexp, e.scratch, g.max_chunk_words,
+                           e.chunk_bits, e.flags);
+    const int ntiles = (int)((g.nchunks + TILE - 1) / TILE);
+    unsigned long long *tile = e.chunk_off;   // ntiles entries
+    hipLaunchKernelGGL(tile_sum_kernel, dim3(ntiles), dim3(TILE), 0, st, e.chunk_bits, g.nchunks, tile);
+    PlanArgs pa;
+    pa.ndim = e.f.ndim;
+    if (e.f.ndim == 3) {
+        pa.dims[0] = (unsigned)e.f.n[0]; pa.dims[1] = (unsigned)e.f.n[1]; pa.dims[2] = (unsigned)e.f.n[2];
+    } else {
+        pa.dims[0] = (unsigned)e.f.n[0]; pa.dims[1] = (unsigned)e.f.n[2]; pa.dims[2] = 1u;
+    }
+    pa.atol = e.atol;
+    pa.minexp = minexp;
+    pa.guard = g.guard;
+    pa.tp = g.tp;
+    pa.log2k = e.f.ndim == 3 ? 4 : 6;
+    pa.nblocks = g.nblocks;
+    pa.nchunks = g.nchunks;
+    pa.nsuper = g.nsuper;
+    pa.table_bytes = g.table_bytes;
+    pa.ntiles = ntiles;
+    pa.tile_sum = tile;
+    pa.dst = e.dst;
+    pa.cap = e.cap;
+    pa.pool = e.pool;
+    pa.pool_cap = e.pool_cap;
+    pa.slots = e.slots;
+    pa.slot_index = e.slot_index;
+    pa.prev_index = e.prev_index;
+    pa.out_bytes = e.out_bytes;
+    pa.dst_offset = e.chunk_off + ntiles;
+    pa.flags = e.flags;
+    pa.pool_high = e.pool_high;
+    pa.total_bytes = e.total_bytes;
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, pa);
+    PackArgs ka;
+    ka.scratch = e.scratch;
+    ka.chunk_words = g.max_chunk_words;
+    ka.chunk_bits = e.chunk_bits;
+    ka.nchunks = g.nchunks;
+    ka.nsuper = g.nsuper;
+    ka.table_bytes = g.table_bytes;
+    ka.tile_prefix = tile;
+    ka.dst = e.dst;
+    ka.pool = e.pool;
+    ka.dst_offset = e.chunk_off + ntiles;
+    ka.flags = e.flags;
+    hipLaunchKernelGGL(pack_kernel, dim3(ntiles), dim3(TILE), 0, st, ka);
+}
+
+void codec_decode(const DecodeArgs &d, hipStream_t st)
+{
+    CodecGeom g = codec_geom(d.f.ndim, d.f.n);
+    const int nwaves = (int)(g.nchunks / 64);
+    if (d.f.ndim == 3)
+        hipLaunchKernelGGL(decode_kernel<3>, dim3(nwaves), dim3(64), 0, st, d.f, d.dst, d.stream, d.pool,
+                           d.slots, d.slot_index, g.nb[0], g.nb[1], g.nb[2], g.nblocks, g.nchunks,
+                           g.nsuper, g.table_bytes, d.flags);
+    else
+        hipLaunchKernelGGL(decode_kernel<2>, dim3(nwaves), dim3(64), 0, st, d.f, d.dst, d.stream, d.pool,
+                           d.slots, d.slot_index, g.nb[0], g.nb[1], g.nb[2], g.nblocks, g.nchunks,
+                           g.nsuper, g.table_bytes, d.flags);
+}
+
+}  // namespace fwi

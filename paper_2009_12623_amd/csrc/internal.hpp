@@ -1,0 +1,144 @@
+// Internal declarations of libfwigrad (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace fwi {
+
+// Working wavefields live in padded buffers so the stencil needs no bounds
+// checks: PAD_X/PAD_Y points before and after x/y, PAD_Z0 before z (keeps
+// interior rows 64-byte aligned) and tile slack after z.  The pads are
+// zero and never written.
+constexpr int PAD_X = 8;
+constexpr int PAD_Y = 8;
+constexpr int PAD_Z0 = 16;
+constexpr int TILE_Z = 64;     // one wave64 along z
+constexpr int TILE_Y = 8;      // waves along y in the 3D stencil
+constexpr int TILE_Z2 = 256;   // z extent of a 2D stencil workgroup
+
+struct Padded {
+    int ndim = 0;
+    int nx = 0, ny = 1, nz = 0;     // computational dims (ny = 1 in 2D)
+    long px = 0, py = 0, pz = 0;    // padded dims
+    long sx = 0, sy = 0;            // padded strides (z stride 1)
+    long origin = 0;                // offset of interior (0,0,0)
+    size_t elems() const { return (size_t)px * py * pz; }
+};
+
+Padded make_padded(int ndim, const int *comp);
+
+// ------------------------------------------------------------------ stencil
+struct StepParams {
+    const float *u1;        // level k-1 (forward) or k+1 (adjoint); padded, at origin
+    const float *u2;        // level k-2 / k+2; padded, at origin
+    float *out;             // new level; padded, at origin; may equal u2
+    const float *b;         // dt^2/m, computational grid (unpadded)
+    const float *uk;        // adjoint only: forward state u^k, padded, at origin
+    float *g;               // adjoint only: gradient, unpadded
+    long psx, psy;          // padded strides
+    long sx, sy;            // unpadded strides
+    int nx, ny, nz, nbl;
+    float kappa;            // e = kappa * b * sum(d_axis^2)
+    float inv_dt2;
+    float w[9];             // a_k / h^2, k = 0..R
+    long src;               // unpadded index of the source node, -1 if none
+    const float *wav;       // wavelet (device)
+    int step;               // wavelet sample injected by this step
+    int xchunk;             // x planes per workgroup
+};
+
+void launch_step(const StepParams &p, int ndim, int radius, bool adjoint,
+                 hipStream_t st);
+
+void launch_coef(const float *m, float *b, size_t n, double dt, hipStream_t st);
+void launch_gather(const float *field_origin, const long *rec_off, int nrec,
+                   float *out_row, hipStream_t st);
+void launch_residual(const float *d_sim, const float *d_obs, float *res,
+                     size_t n, double *partials, int nparts, double *phi,
+                     hipStream_t st);
+
+// adjoint receiver injection at unique nodes (CSR over receivers)
+struct InjectParams {
+    float *lam;             // new adjoint level, padded, at origin
+    float *g;               // unpadded gradient
+    const float *uk;        // forward state, padded, at origin
+    const float *b;         // unpadded
+    const float *res_row;   // residual row of this step (nrec)
+    const long *node_pad;   // padded offset of unique node j
+    const long *node_unp;   // unpadded offset
+    const int *node_xyz;    // 3 ints per node (computational coords)
+    const int *rec_ptr;     // CSR: receivers of node j = rec_idx[rec_ptr[j]..rec_ptr[j+1])
+    const int *rec_idx;
+    int nnode;
+    int nx, ny, nz, nbl, ndim;
+    float kappa, inv_dt2;
+};
+void launch_inject(const InjectParams &p, hipStream_t st);
+
+// -------------------------------------------------------------------- codec
+struct FieldView {
+    int ndim;
+    long n[3];          // (x, y, z); 2D fields are (nx, 1, nz)
+    long sx, sy;        // element strides of x and y (z contiguous)
+};
+
+struct CodecGeom {
+    int ndim;
+    long nb[3];
+    long nblocks, nchunks, nsuper;
+    int kblk, size, tp, guard;
+    long table_bytes;   // super-chunk + chunk tables, 8-byte padded
+    long max_chunk_words;
+};
+CodecGeom codec_geom(int ndim, const long n[3]);
+long codec_bound(const CodecGeom &g);
+
+// Device-side descriptor of one stored stream (pool bookkeeping).
+struct StreamSlot {
+    unsigned long long offset;   // byte offset in the pool
+    unsigned long long bytes;    // stream bytes
+    int valid;
+    int pad;
+};
+
+// Encode `f` into stream bytes.  Scratch: chunk_words per chunk (u64),
+// chunk_bits[nchunks] (u64), chunk_off[nchunks] (u64).  The destination is
+// either fixed (dst != nullptr, capacity cap) or a slot of the pool stack
+// (dst == nullptr: pool/pool_cap/slots/slot_index/prev_index).  Status flags
+// go to `flags` (bit0 non-finite, bit1 capacity).
+struct EncodeArgs {
+    FieldView f;
+    const float *src;            // field origin
+    double atol;
+    unsigned long long *scratch;
+    unsigned long long *chunk_bits;
+    unsigned long long *chunk_off;
+    unsigned char *dst;          // fixed destination or nullptr
+    unsigned long long cap;
+    unsigned char *pool;
+    unsigned long long pool_cap;
+    StreamSlot *slots;
+    int slot_index;              // slot table entry written
+    int prev_index;              // entry whose end is this stream's start, -1 = 0
+    unsigned long long *out_bytes;   // device: stream bytes
+    unsigned int *flags;
+    unsigned long long *pool_high;
+    unsigned long long *total_bytes; // device: running sum of stream bytes
+};
+void codec_encode(const EncodeArgs &a, hipStream_t st);
+
+struct DecodeArgs {
+    FieldView f;
+    float *dst;                  // field origin
+    const unsigned char *stream; // fixed stream, or nullptr: pool slot
+    const unsigned char *pool;
+    const StreamSlot *slots;
+    int slot_index;
+    unsigned long long nbytes;   // fixed stream bytes
+    unsigned int *flags;         // bit2: corrupt
+};
+void codec_decode(const DecodeArgs &a, hipStream_t st);
+
+}  // namespace fwi

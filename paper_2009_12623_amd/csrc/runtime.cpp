@@ -1,0 +1,1016 @@
+// Host runtime of libfwigrad: argument validation, workspaces, checkpoint
+// pools, the Revolve action executor and the C ABI (include/fwigrad.h).
+//
+// One gradient (paper Fig. 1 and Fig. 2) is a walk over the action list:
+//   ADVANCE a->b  forward steps (first sweep: receivers sampled, Eq. 2)
+//   TAKESHOT s,k  store x_k = (u^k, u^{k-1}) in slot s (compressed: two
+//                 codec streams placed on the device-side pool stack)
+//   RESTORE s,k   working state <- slot s (exact copies are read in place;
+//                 compressed ones are decoded, only u^k when the next action
+//                 is the reverse step that needs nothing else)
+//   REVERSE k     adjoint row k fused with the imaging condition (Eq. 4);
+//                 the first one forms the residual and Phi (Eq. 3)
+//   FREE s        pop the slot
+// Everything runs asynchronously on the caller's stream; the host only
+// waits at the end for Phi, the pool status and optional timings.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/fwigrad.h"
+#include "internal.hpp"
+
+namespace fwi {
+std::vector<fwi_action> revolve_plan(int nsteps, int nslots);
+long long revolve_min_steps(int nsteps, int nslots);
+}
+
+using namespace fwi;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define HIPCHK(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            throw Error{FWI_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)};         \
+    } while (0)
+
+template <class T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    void ensure(size_t want, bool zero = false)
+    {
+        if (want <= n && p) return;
+        release();
+        if (want == 0) want = 1;
+        if (hipMalloc(&p, want * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            n = 0;
+            (void)hipGetLastError();
+            throw Error{FWI_ENOMEM, "device allocation of " + std::to_string(want * sizeof(T)) +
+                                        " bytes failed"};
+        }
+        n = want;
+        if (zero) HIPCHK(hipMemset(p, 0, want * sizeof(T)));
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+};
+
+enum Kind { K_FWD = 0, K_ADJ = 1, K_ENC = 2, K_DEC = 3, K_NKIND = 4 };
+
+}  // namespace
+
+struct fwi_ctx {
+    int device = 0;
+    size_t pool_default = 0;
+    DevBuf<unsigned char> pool;
+    // working fields (padded) and coefficient b = dt^2/m (unpadded)
+    DevBuf<float> fa, fb, la, lb, coef;
+    size_t padded_elems = 0;
+    // codec scratch
+    DevBuf<unsigned long long> scratch, chunk_bits, chunk_off, misc;
+    DevBuf<StreamSlot> slots;
+    DevBuf<unsigned int> flags;
+    DevBuf<double> partials, phi;
+    // receivers
+    DevBuf<long> rec_off, node_pad, node_unp;
+    DevBuf<int> node_xyz, rec_ptr, rec_idx;
+    DevBuf<float> dsim, res;
+    // timing
+    bool timing = false;
+    fwi_stats stats{};
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    struct Iv {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Iv> ivs;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    std::map<std::pair<int, int>, std::vector<fwi_action>> plans;
+
+    hipEvent_t ev()
+    {
+        if (evused == evpool.size()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            evpool.push_back(e);
+        }
+        return evpool[evused++];
+    }
+};
+
+struct fwi_tape {
+    fwi_ctx *ctx = nullptr;
+    fwi_grid grid{};
+    fwi_shot shot{};
+    std::vector<int32_t> rec;
+    const float *m = nullptr;
+    fwi_ckpt_cfg cfg{};
+    std::vector<fwi_action> acts;
+    size_t next = 0;
+    DevBuf<unsigned char> pool;
+    DevBuf<StreamSlot> slots;
+    DevBuf<float> xcur, xprev;
+    bool used = false;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- set-up
+struct Setup {
+    int ndim = 0, R = 0, nt = 0, nbl = 0;
+    int comp[3] = {1, 1, 1};
+    Padded pad;
+    long usx = 0, usy = 0;
+    size_t ncomp = 0;
+    double dt = 0, h = 0;
+    float w[9] = {0};
+    float kappa = 0, inv_dt2 = 0;
+    long src_unp = -1;
+    int nrec = 0;
+    std::vector<long> rec_pad;
+    std::vector<long> node_pad, node_unp;
+    std::vector<int> node_xyz, rec_ptr, rec_idx;
+};
+
+// a_k of the central order-2M second derivative:
+// a_k = 2 (-1)^{k+1} (M!)^2 / (k^2 (M-k)! (M+k)!),  a_0 = -2 sum a_k
+void stencil_weights(int so, double *a)
+{
+    const int M = so / 2;
+    auto fact = [](int n) {
+        double f = 1.0;
+        for (int i = 2; i <= n; ++i) f *= i;
+        return f;
+    };
+    double sum = 0.0;
+    for (int k = 1; k <= M; ++k) {
+        double v = 2.0 * fact(M) * fact(M) / ((double)k * k * fact(M - k) * fact(M + k));
+        a[k] = (k & 1) ? v : -v;
+        sum += a[k];
+    }
+    a[0] = -2.0 * sum;
+}
+
+void validate_grid(const fwi_grid *g)
+{
+    if (!g) throw Error{FWI_EINVAL, "grid is null"};
+    if (g->ndim != 2 && g->ndim != 3) throw Error{FWI_EINVAL, "ndim must be 2 or 3"};
+    for (int d = 0; d < g->ndim; ++d)
+        if (g->n[d] < 1) throw Error{FWI_EINVAL, "physical dims must be >= 1"};
+    if (g->space_order != 4 && g->space_order != 8 && g->space_order != 16)
+        throw Error{FWI_EINVAL, "space_order must be 4, 8 or 16"};
+    if (g->nbl < 0) throw Error{FWI_EINVAL, "nbl must be >= 0"};
+    if (g->nt < 1) throw Error{FWI_EINVAL, "nt must be >= 1"};
+    if (!(g->h > 0) || !std::isfinite(g->h)) throw Error{FWI_EINVAL, "h must be positive"};
+    if (!(g->dt > 0) || !std::isfinite(g->dt)) throw Error{FWI_EINVAL, "dt must be positive"};
+    if (!(g->vmax > 0) || !std::isfinite(g->vmax)) throw Error{FWI_EINVAL, "vmax must be positive"};
+    double a[9];
+    stencil_weights(g->space_order, a);
+    double S = -a[0];
+    for (int k = 1; k <= g->space_order / 2; ++k) S -= 2.0 * a[k] * ((k & 1) ? -1.0 : 1.0);
+    const double dtmax = 2.0 * g->h / (g->vmax * std::sqrt(g->ndim * S));
+    if (g->dt > dtmax)
+        throw Error{FWI_EUNSTABLE, "dt " + std::to_string(g->dt) + " exceeds the stability limit " +
+                                       std::to_string(dtmax)};
+    for (int d = 0; d < g->ndim; ++d)
+        if ((long)g->n[d] + 2L * g->nbl > (1L << 30)) throw Error{FWI_EINVAL, "grid too large"};
+}
+
+Setup make_setup(const fwi_grid *g, const fwi_shot *shot, bool need_src)
+{
+    validate_grid(g);
+    if (!shot) throw Error{FWI_EINVAL, "shot is null"};
+    Setup s;
+    s.ndim = g->ndim;
+    s.R = g->space_order / 2;
+    s.nt = g->nt;
+    s.nbl = g->nbl;
+    s.dt = g->dt;
+    s.h = g->h;
+    for (int d = 0; d < g->ndim; ++d) s.comp[d] = g->n[d] + 2 * g->nbl;
+    s.pad = make_padded(g->ndim, s.comp);
+    const int nx = s.pad.nx, ny = s.pad.ny, nz = s.pad.nz;
+    s.ncomp = (size_t)nx * ny * nz;
+    s.usx = (long)ny * nz;
+    s.usy = nz;
+    double a[9];
+    stencil_weights(g->space_order, a);
+    for (int k = 0; k <= s.R; ++k) s.w[k] = (float)(a[k] / (g->h * g->h));
+    if (g->nbl > 0) {
+        const double smax = 3.0 * g->vmax * std::log(1000.0) / (2.0 * g->nbl * g->h);
+        s.kappa = (float)(smax / (2.0 * g->dt * g->vmax * g->vmax * (double)g->nbl * g->nbl));
+    }
+    s.inv_dt2 = (float)(1.0 / (g->dt * g->dt));
+    auto coords = [&](const int *p, int out[3]) {
+        out[0] = p[0] + g->nbl;
+        out[1] = g->ndim == 3 ? p[1] + g->nbl : 0;
+        out[2] = (g->ndim == 3 ? p[2] : p[1]) + g->nbl;
+    };
+    auto inside = [&](const int *p) {
+        for (int d = 0; d < g->ndim; ++d)
+            if (p[d] < 0 || p[d] >= g->n[d]) return false;
+        return true;
+    };
+    if (need_src) {
+        if (!shot->wavelet) throw Error{FWI_EINVAL, "wavelet is null"};
+        if (!inside(shot->src)) throw Error{FWI_EINVAL, "source outside the physical grid"};
+        int c[3];
+        coords(shot->src, c);
+        s.src_unp = (long)c[0] * s.usx + (long)c[1] * s.usy + c[2];
+    }
+    if (shot->nrec < 0) throw Error{FWI_EINVAL, "nrec must be >= 0"};
+    if (shot->nrec > 0 && !shot->rec) throw Error{FWI_EINVAL, "receiver list is null"};
+    s.nrec = shot->nrec;
+    s.rec_pad.resize(s.nrec);
+    std::map<long, std::vector<int>> nodes;
+    for (int r = 0; r < s.nrec; ++r) {
+        const int *p = shot->rec + (size_t)r * g->ndim;
+        if (!inside(p)) throw Error{FWI_EINVAL, "receiver " + std::to_string(r) + " outside the physical grid"};
+        int c[3];
+        coords(p, c);
+        s.rec_pad[r] = (long)c[0] * s.pad.sx + (long)c[1] * s.pad.sy + c[2];
+        nodes[(long)c[0] * s.usx + (long)c[1] * s.usy + c[2]].push_back(r);
+    }
+    s.rec_ptr.push_back(0);
+    for (auto &kv : nodes) {
+        const long u = kv.first;
+        const int cx = (int)(u / s.usx), cy = (int)((u / s.usy) % ny), cz = (int)(u % nz);
+        s.node_unp.push_back(u);
+        s.node_pad.push_back((long)cx * s.pad.sx + (long)cy * s.pad.sy + cz);
+        s.node_xyz.push_back(cx);
+        s.node_xyz.push_back(cy);
+        s.node_xyz.push_back(cz);
+        for (int r : kv.second) s.rec_idx.push_back(r);
+        s.rec_ptr.push_back((int)s.rec_idx.size());
+    }
+    return s;
+}
+
+template <class T>
+void upload(DevBuf<T> &b, const std::vector<T> &v, hipStream_t st)
+{
+    b.ensure(v.size());
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+void ensure_fields(fwi_ctx *c, const Setup &s)
+{
+    const size_t pe = s.pad.elems();
+    if (pe != c->padded_elems) {
+        c->fa.release(); c->fb.release(); c->la.release(); c->lb.release();
+        c->fa.ensure(pe, true);
+        c->fb.ensure(pe, true);
+        c->la.ensure(pe, true);
+        c->lb.ensure(pe, true);
+        c->padded_elems = pe;
+    }
+    c->coef.ensure(s.ncomp);
+}
+
+FieldView padded_view(const Setup &s)
+{
+    FieldView f;
+    f.ndim = s.ndim;
+    f.n[0] = s.pad.nx;
+    f.n[1] = s.pad.ny;
+    f.n[2] = s.pad.nz;
+    f.sx = s.pad.sx;
+    f.sy = s.ndim == 3 ? s.pad.sy : 0;
+    return f;
+}
+
+void ensure_codec(fwi_ctx *c, const FieldView &f, int nslot_entries)
+{
+    CodecGeom g = codec_geom(f.ndim, f.n);
+    c->scratch.ensure((size_t)g.nchunks * g.max_chunk_words);
+    c->chunk_bits.ensure((size_t)g.nchunks);
+    c->chunk_off.ensure((size_t)((g.nchunks + 1023) / 1024) + 2);
+    c->misc.ensure(4);
+    c->flags.ensure(1);
+    c->slots.ensure((size_t)std::max(nslot_entries, 1));
+}
+
+// ---------------------------------------------------------------- timing
+struct Timer {
+    fwi_ctx *c;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    int kind;
+    Timer(fwi_ctx *c_, hipStream_t st_, int k) : c(c_), st(st_), kind(k)
+    {
+        if (c->timing) {
+            a = c->ev();
+            HIPCHK(hipEventRecord(a, st));
+        }
+    }
+    ~Timer()
+    {
+        if (a) {
+            hipEvent_t b = c->ev();
+            (void)hipEventRecord(b, st);
+            c->ivs.push_back({kind, a, b});
+        }
+    }
+};
+
+void begin_call(fwi_ctx *c, hipStream_t st)
+{
+    HIPCHK(hipSetDevice(c->device));
+    c->stats = fwi_stats{};
+    c->ivs.clear();
+    c->evused = 0;
+    if (c->timing) {
+        if (!c->t0) {
+            HIPCHK(hipEventCreate(&c->t0));
+            HIPCHK(hipEventCreate(&c->t1));
+        }
+        HIPCHK(hipEventRecord(c->t0, st));
+    }
+}
+
+void end_call(fwi_ctx *c, hipStream_t st)
+{
+    if (!c->timing) return;
+    HIPCHK(hipEventRecord(c->t1, st));
+    HIPCHK(hipEventSynchronize(c->t1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, c->t0, c->t1));
+    c->stats.ms_total = ms;
+    double acc[K_NKIND] = {0, 0, 0, 0};
+    for (auto &iv : c->ivs) {
+        float t = 0;
+        HIPCHK(hipEventElapsedTime(&t, iv.a, iv.b));
+        acc[iv.kind] += t;
+    }
+    c->stats.ms_forward = acc[K_FWD];
+    c->stats.ms_adjoint = acc[K_ADJ];
+    c->stats.ms_encode = acc[K_ENC];
+    c->stats.ms_decode = acc[K_DEC];
+}
+
+// -------------------------------------------------------------- executor
+struct Exec {
+    fwi_ctx *c;
+    Setup S;
+    hipStream_t st;
+    const float *m;
+    const fwi_shot *shot;
+    float *cur = nullptr, *prev = nullptr;
+    bool prev_valid = true;
+    int work = 0;
+    float *l1 = nullptr, *l2 = nullptr;
+    int reached = 0;
+    float *dsim = nullptr;           // nt x nrec, recorded in the first sweep
+    const float *adj_src = nullptr;  // residual or dd
+    const float *d_obs = nullptr;
+    bool have_src = false;
+    float *grad = nullptr;
+    // checkpoints
+    bool compress = false;
+    double atol = 0;
+    unsigned char *pool = nullptr;
+    size_t pool_cap = 0;
+    StreamSlot *slots = nullptr;
+    size_t raw_bytes = 0;            // uncompressed: bytes of one padded level
+
+    float *origin(float *base) const { return base + S.pad.origin; }
+    float *W0() const { return origin(c->fa.p); }
+    float *W1() const { return origin(c->fb.p); }
+    bool in_w(const float *p) const { return p == W0() || p == W1(); }
+
+    void init_fields()
+    {
+        launch_coef(m, c->coef.p, S.ncomp, S.dt, st);
+        HIPCHK(hipMemsetAsync(c->fa.p, 0, c->padded_elems * sizeof(float), st));
+        HIPCHK(hipMemsetAsync(c->fb.p, 0, c->padded_elems * sizeof(float), st));
+        cur = W0();
+        prev = W1();
+        work = 0;
+        upload(c->rec_off, S.rec_pad, st);
+    }
+
+    void init_adjoint()
+    {
+        HIPCHK(hipMemsetAsync(c->la.p, 0, c->padded_elems * sizeof(float), st));
+        HIPCHK(hipMemsetAsync(c->lb.p, 0, c->padded_elems * sizeof(float), st));
+        l1 = origin(c->la.p);
+        l2 = origin(c->lb.p);
+        HIPCHK(hipMemsetAsync(grad, 0, S.ncomp * sizeof(float), st));
+        upload(c->node_pad, S.node_pad, st);
+        upload(c->node_unp, S.node_unp, st);
+        upload(c->node_xyz, S.node_xyz, st);
+        upload(c->rec_ptr, S.rec_ptr, st);
+        upload(c->rec_idx, S.rec_idx, st);
+    }
+
+    StepParams params() const
+    {
+        StepParams p{};
+        p.b = c->coef.p;
+        p.psx = S.pad.sx;
+        p.psy = S.ndim == 3 ? S.pad.sy : 0;
+        p.sx = S.usx;
+        p.sy = S.ndim == 3 ? S.usy : 0;
+        p.nx = S.pad.nx;
+        p.ny = S.pad.ny;
+        p.nz = S.pad.nz;
+        p.nbl = S.nbl;
+        p.kappa = S.kappa;
+        p.inv_dt2 = S.inv_dt2;
+        for (int k = 0; k < 9; ++k) p.w[k] = S.w[k];
+        p.src = -1;
+        p.xchunk = S.ndim == 3 ? 32 : 16;
+        return p;
+    }
+
+    void advance(int a, int b, bool record)
+    {
+        if (work != a) throw Error{FWI_EINVAL, "internal: advance from a state not held"};
+        if (!prev_valid) throw Error{FWI_EINVAL, "internal: advance without the older level"};
+        Timer tm(c, st, K_FWD);
+        StepParams p = params();
+        p.src = S.src_unp;
+        p.wav = shot->wavelet;
+        for (int k = a + 1; k <= b; ++k) {
+            float *out = in_w(prev) ? prev : (cur == W0() ? W1() : W0());
+            p.u1 = cur;
+            p.u2 = prev;
+            p.out = out;
+            p.step = k - 1;
+            launch_step(p, S.ndim, S.R, false, st);
+            prev = cur;
+            cur = out;
+            if (record && k > reached) {
+                launch_gather(cur, c->rec_off.p, S.nrec, dsim + (size_t)(k - 1) * S.nrec, st);
+                reached = k;
+            }
+        }
+        c->stats.n_forward += b - a;
+        work = b;
+    }
+
+    void takeshot(int slot, int k)
+    {
+        if (work != k) throw Error{FWI_EINVAL, "internal: takeshot of a state not held"};
+        c->stats.ckpt_raw_bytes += 2LL * (long long)S.ncomp * 4;
+        if (!compress) {
+            const size_t off = (size_t)(2 * slot) * raw_bytes;
+            HIPCHK(hipMemcpyAsync(pool + off, cur - S.pad.origin, raw_bytes, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(pool + off + raw_bytes, prev - S.pad.origin, raw_bytes,
+                                  hipMemcpyDeviceToDevice, st));
+            c->stats.ckpt_bytes += 2LL * (long long)raw_bytes;
+            return;
+        }
+        for (int lev = 0; lev < 2; ++lev) {
+            Timer tm(c, st, K_ENC);
+            EncodeArgs e{};
+            e.f = padded_view(S);
+            e.src = lev == 0 ? cur : prev;
+            e.atol = atol;
+            e.scratch = c->scratch.p;
+            e.chunk_bits = c->chunk_bits.p;
+            e.chunk_off = c->chunk_off.p;
+            e.dst = nullptr;
+            e.pool = pool;
+            e.pool_cap = pool_cap;
+            e.slots = slots;
+            e.slot_index = 2 * slot + lev;
+            e.prev_index = lev == 1 ? 2 * slot : (slot == 0 ? -1 : 2 * slot - 1);
+            e.out_bytes = c->misc.p + 0;
+            e.pool_high = c->misc.p + 1;
+            e.total_bytes = c->misc.p + 2;
+            e.flags = c->flags.p;
+            codec_encode(e, st);
+            c->stats.n_encode += 1;
+        }
+    }
+
+    void restore(int slot, int k, bool only_cur)
+    {
+        if (slot < 0) {
+            HIPCHK(hipMemsetAsync(c->fa.p, 0, c->padded_elems * sizeof(float), st));
+            HIPCHK(hipMemsetAsync(c->fb.p, 0, c->padded_elems * sizeof(float), st));
+            cur = W0();
+            prev = W1();
+            prev_valid = true;
+        } else if (!compress) {
+            const size_t off = (size_t)(2 * slot) * raw_bytes;
+            cur = origin((float *)(pool + off));
+            prev = origin((float *)(pool + off + raw_bytes));
+            prev_valid = true;
+        } else {
+            for (int lev = 0; lev < (only_cur ? 1 : 2); ++lev) {
+                Timer tm(c, st, K_DEC);
+                DecodeArgs d{};
+                d.f = padded_view(S);
+                d.dst = lev == 0 ? W0() : W1();
+                d.stream = nullptr;
+                d.pool = pool;
+                d.slots = slots;
+                d.slot_index = 2 * slot + lev;
+                d.flags = c->flags.p;
+                codec_decode(d, st);
+                c->stats.n_decode += 1;
+            }
+            cur = W0();
+            prev = W1();
+            prev_valid = !only_cur;
+        }
+        work = k;
+    }
+
+    void reverse(int k)
+    {
+        if (work != k) throw Error{FWI_EINVAL, "internal: reverse without its state"};
+        if (!adj_src) {
+            const size_t n = (size_t)S.nt * S.nrec;
+            launch_residual(dsim, d_obs, c->res.p, n, c->partials.p, (int)c->partials.n, c->phi.p, st);
+            adj_src = c->res.p;
+        }
+        Timer tm(c, st, K_ADJ);
+        StepParams p = params();
+        p.u1 = l1;
+        p.u2 = l2;
+        p.out = l2;
+        p.uk = cur;
+        p.g = grad;
+        launch_step(p, S.ndim, S.R, true, st);
+        InjectParams ip{};
+        ip.lam = l2;
+        ip.g = grad;
+        ip.uk = cur;
+        ip.b = c->coef.p;
+        ip.res_row = adj_src + (size_t)(k - 1) * S.nrec;
+        ip.node_pad = c->node_pad.p;
+        ip.node_unp = c->node_unp.p;
+        ip.node_xyz = c->node_xyz.p;
+        ip.rec_ptr = c->rec_ptr.p;
+        ip.rec_idx = c->rec_idx.p;
+        ip.nnode = (int)S.node_unp.size();
+        ip.nx = S.pad.nx;
+        ip.ny = S.pad.ny;
+        ip.nz = S.pad.nz;
+        ip.nbl = S.nbl;
+        ip.ndim = S.ndim;
+        ip.kappa = S.kappa;
+        ip.inv_dt2 = S.inv_dt2;
+        launch_inject(ip, st);
+        std::swap(l1, l2);
+        c->stats.n_adjoint += 1;
+    }
+
+    // run acts[from, to); stops before the first REVERSE if stop_at_reverse
+    size_t run(const std::vector<fwi_action> &acts, size_t from, bool stop_at_reverse)
+    {
+        size_t i = from;
+        for (; i < acts.size(); ++i) {
+            const fwi_action &a = acts[i];
+            switch (a.op) {
+            case FWI_ADVANCE: advance(a.a, a.b, true); break;
+            case FWI_TAKESHOT: takeshot(a.a, a.b); break;
+            case FWI_RESTORE: {
+                const bool only = compress && i + 1 < acts.size() && acts[i + 1].op == FWI_REVERSE;
+                restore(a.a, a.b, only);
+                break;
+            }
+            case FWI_REVERSE:
+                if (stop_at_reverse) return i;
+                reverse(a.a);
+                break;
+            case FWI_FREE: break;
+            default: throw Error{FWI_EINVAL, "internal: bad action"};
+            }
+        }
+        return i;
+    }
+};
+
+const std::vector<fwi_action> &plan_for(fwi_ctx *c, int nt, int nslots)
+{
+    auto key = std::make_pair(nt, std::min(nslots, nt));
+    auto it = c->plans.find(key);
+    if (it == c->plans.end()) it = c->plans.emplace(key, revolve_plan(nt, nslots)).first;
+    return it->second;
+}
+
+void check_cfg(const fwi_ckpt_cfg *cfg)
+{
+    if (!cfg) throw Error{FWI_EINVAL, "checkpoint config is null"};
+    if (cfg->nslots < 0) throw Error{FWI_EINVAL, "nslots must be >= 0"};
+    if (cfg->compress) {
+        if (!(cfg->atol >= 2.2250738585072014e-308) || !std::isfinite(cfg->atol))
+            throw Error{FWI_EINVAL, "atol must be a positive normal number"};
+    }
+}
+
+int max_slot_used(const std::vector<fwi_action> &acts)
+{
+    int m = -1;
+    for (auto &a : acts)
+        if (a.op == FWI_TAKESHOT) m = std::max(m, a.a);
+    return m + 1;
+}
+
+// prepare the checkpoint storage of an executor
+void setup_ckpt(Exec &ex, const fwi_ckpt_cfg *cfg, unsigned char *pool, size_t cap, StreamSlot *slots,
+                int nslots_used)
+{
+    ex.compress = cfg->compress != 0;
+    ex.atol = cfg->atol;
+    ex.pool = pool;
+    ex.pool_cap = cap;
+    ex.slots = slots;
+    ex.raw_bytes = ex.c->padded_elems * sizeof(float);
+    if (!ex.compress && (size_t)nslots_used * 2 * ex.raw_bytes > cap)
+        throw Error{FWI_ECAPACITY, "pool of " + std::to_string(cap) + " bytes cannot hold " +
+                                       std::to_string(nslots_used) + " exact checkpoints"};
+}
+
+void finish_status(fwi_ctx *c, hipStream_t st)
+{
+    unsigned int fl = 0;
+    unsigned long long misc[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(&fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(misc, c->misc.p, sizeof(misc), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    c->stats.pool_high = (long long)misc[1];
+    if (misc[2]) c->stats.ckpt_bytes = (long long)misc[2];
+    if (fl & 1u) throw Error{FWI_ENONFINITE, "non-finite wavefield reached the codec"};
+    if (fl & 2u) throw Error{FWI_ECAPACITY, "checkpoint pool overflow (use fewer slots or a larger pool)"};
+    if (fl & 4u) throw Error{FWI_ECORRUPT, "checkpoint stream failed to decode"};
+}
+
+void reset_status(fwi_ctx *c, hipStream_t st)
+{
+    c->flags.ensure(1);
+    c->misc.ensure(4);
+    HIPCHK(hipMemsetAsync(c->flags.p, 0, sizeof(unsigned int), st));
+    HIPCHK(hipMemsetAsync(c->misc.p, 0, 4 * sizeof(unsigned long long), st));
+}
+
+template <class F>
+int guarded(F &&f)
+{
+    try {
+        f();
+        return FWI_OK;
+    } catch (const Error &e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::exception &e) {
+        g_err = e.what();
+        return FWI_EINVAL;
+    } catch (...) {
+        g_err = "unknown failure";
+        return FWI_EINVAL;
+    }
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+extern "C" {
+
+const char *fwi_last_error(void) { return g_err.c_str(); }
+
+int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
+{
+    return guarded([&] {
+        if (!ctx) throw Error{FWI_EINVAL, "ctx is null"};
+        int n = 0;
+        HIPCHK(hipGetDeviceCount(&n));
+        if (device < 0 || device >= n) throw Error{FWI_EINVAL, "no such device"};
+        fwi_ctx *c = new fwi_ctx();
+        c->device = device;
+        c->pool_default = pool_bytes;
+        *ctx = c;
+    });
+}
+
+int fwi_ctx_destroy(fwi_ctx *c)
+{
+    return guarded([&] {
+        if (!c) return;
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        for (auto e : c->evpool) (void)hipEventDestroy(e);
+        if (c->t0) (void)hipEventDestroy(c->t0);
+        if (c->t1) (void)hipEventDestroy(c->t1);
+        c->pool.release(); c->fa.release(); c->fb.release(); c->la.release(); c->lb.release();
+        c->coef.release(); c->scratch.release(); c->chunk_bits.release(); c->chunk_off.release();
+        c->misc.release(); c->slots.release(); c->flags.release(); c->partials.release();
+        c->phi.release(); c->rec_off.release(); c->node_pad.release(); c->node_unp.release();
+        c->node_xyz.release(); c->rec_ptr.release(); c->rec_idx.release(); c->dsim.release();
+        c->res.release();
+        delete c;
+    });
+}
+
+int fwi_ctx_set_timing(fwi_ctx *c, int on)
+{
+    return guarded([&] {
+        if (!c) throw Error{FWI_EINVAL, "ctx is null"};
+        c->timing = on != 0;
+    });
+}
+
+int fwi_ctx_stats(const fwi_ctx *c, fwi_stats *out)
+{
+    return guarded([&] {
+        if (!c || !out) throw Error{FWI_EINVAL, "null argument"};
+        *out = c->stats;
+    });
+}
+
+int fwi_forward(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot, float *d_sim,
+                hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !m || (!d_sim && shot && shot->nrec > 0)) throw Error{FWI_EINVAL, "null argument"};
+        begin_call(c, st);
+        Exec ex{c, make_setup(g, shot, true), st, m, shot};
+        ensure_fields(c, ex.S);
+        ex.dsim = d_sim;
+        ex.init_fields();
+        ex.advance(0, ex.S.nt, true);
+        HIPCHK(hipGetLastError());
+        end_call(c, st);
+    });
+}
+
+int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot,
+                 const float *d_obs, const fwi_ckpt_cfg *cfg, float *grad, double *phi,
+                 hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !m || !grad || !phi || (!d_obs && shot && shot->nrec > 0))
+            throw Error{FWI_EINVAL, "null argument"};
+        check_cfg(cfg);
+        begin_call(c, st);
+        Exec ex{c, make_setup(g, shot, true), st, m, shot};
+        ensure_fields(c, ex.S);
+        const auto &acts = plan_for(c, ex.S.nt, cfg->nslots);
+        const int used = max_slot_used(acts);
+        FieldView fv = padded_view(ex.S);
+        if (cfg->compress) ensure_codec(c, fv, 2 * used);
+        if (c->pool.n < c->pool_default) c->pool.ensure(c->pool_default);
+        reset_status(c, st);
+        setup_ckpt(ex, cfg, c->pool.p, c->pool_default, c->slots.p, used);
+        const size_t nd = (size_t)ex.S.nt * ex.S.nrec;
+        c->dsim.ensure(std::max<size_t>(nd, 1));
+        c->res.ensure(std::max<size_t>(nd, 1));
+        c->partials.ensure(256);
+        c->phi.ensure(1);
+        HIPCHK(hipMemsetAsync(c->phi.p, 0, sizeof(double), st));
+        ex.dsim = c->dsim.p;
+        ex.d_obs = d_obs;
+        ex.grad = grad;
+        ex.init_fields();
+        ex.init_adjoint();
+        ex.run(acts, 0, false);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(phi, c->phi.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        finish_status(c, st);
+        end_call(c, st);
+    });
+}
+
+int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot,
+                     const fwi_ckpt_cfg *cfg, float *d_sim, fwi_tape **tape, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !m || !tape || (!d_sim && shot && shot->nrec > 0)) throw Error{FWI_EINVAL, "null argument"};
+        check_cfg(cfg);
+        begin_call(c, st);
+        fwi_tape *t = new fwi_tape();
+        try {
+            t->ctx = c;
+            t->grid = *g;
+            t->shot = *shot;
+            t->m = m;
+            t->cfg = *cfg;
+            Exec ex{c, make_setup(g, shot, true), st, m, shot};
+            t->rec.assign(shot->rec, shot->rec + (size_t)shot->nrec * g->ndim);
+            t->shot.rec = t->rec.data();
+            ensure_fields(c, ex.S);
+            t->acts = plan_for(c, ex.S.nt, cfg->nslots);
+            const int used = max_slot_used(t->acts);
+            FieldView fv = padded_view(ex.S);
+            if (cfg->compress) ensure_codec(c, fv, 1);
+            const size_t cap = cfg->pool_bytes ? cfg->pool_bytes : c->pool_default;
+            t->pool.ensure(cap + 8);
+            t->slots.ensure((size_t)std::max(2 * used, 1));
+            reset_status(c, st);
+            setup_ckpt(ex, cfg, t->pool.p, cap, t->slots.p, used);
+            ex.dsim = d_sim;
+            ex.init_fields();
+            t->next = ex.run(t->acts, 0, true);
+            t->xcur.ensure(c->padded_elems);
+            t->xprev.ensure(c->padded_elems);
+            HIPCHK(hipMemcpyAsync(t->xcur.p, ex.cur - ex.S.pad.origin, c->padded_elems * sizeof(float),
+                                  hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(t->xprev.p, ex.prev - ex.S.pad.origin, c->padded_elems * sizeof(float),
+                                  hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipGetLastError());
+            finish_status(c, st);
+            end_call(c, st);
+        } catch (...) {
+            t->pool.release(); t->slots.release(); t->xcur.release(); t->xprev.release();
+            delete t;
+            throw;
+        }
+        *tape = t;
+    });
+}
+
+int fwi_backward(fwi_ctx *c, fwi_tape *t, const float *dd, float *grad, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !t || !grad || (!dd && t->shot.nrec > 0)) throw Error{FWI_EINVAL, "null argument"};
+        if (t->used) throw Error{FWI_EINVAL, "tape already back-propagated"};
+        begin_call(c, st);
+        Exec ex{c, make_setup(&t->grid, &t->shot, true), st, t->m, &t->shot};
+        ensure_fields(c, ex.S);
+        const int used = max_slot_used(t->acts);
+        FieldView fv = padded_view(ex.S);
+        if (t->cfg.compress) ensure_codec(c, fv, 1);
+        const size_t cap = t->cfg.pool_bytes ? t->cfg.pool_bytes : c->pool_default;
+        reset_status(c, st);
+        setup_ckpt(ex, &t->cfg, t->pool.p, cap, t->slots.p, used);
+        ex.grad = grad;
+        ex.adj_src = dd;
+        ex.init_fields();
+        ex.init_adjoint();
+        ex.cur = t->xcur.p + ex.S.pad.origin;
+        ex.prev = t->xprev.p + ex.S.pad.origin;
+        ex.work = t->grid.nt;
+        ex.reached = t->grid.nt;
+        ex.run(t->acts, t->next, false);
+        HIPCHK(hipGetLastError());
+        finish_status(c, st);
+        t->used = true;
+        end_call(c, st);
+    });
+}
+
+int fwi_tape_free(fwi_tape *t)
+{
+    return guarded([&] {
+        if (!t) return;
+        t->pool.release(); t->slots.release(); t->xcur.release(); t->xprev.release();
+        delete t;
+    });
+}
+
+int ckpt_bound(int ndim, const int n[3], size_t *max_bytes)
+{
+    return guarded([&] {
+        if ((ndim != 2 && ndim != 3) || !n || !max_bytes) throw Error{FWI_EINVAL, "bad arguments"};
+        long dims[3];
+        for (int d = 0; d < ndim; ++d)
+            if (n[d] < 1) throw Error{FWI_EINVAL, "dims must be >= 1"};
+        dims[0] = n[0];
+        dims[1] = ndim == 3 ? n[1] : 1;
+        dims[2] = ndim == 3 ? n[2] : n[1];
+        *max_bytes = (size_t)codec_bound(codec_geom(ndim, dims));
+    });
+}
+
+static FieldView dense_view(int ndim, const int n[3])
+{
+    FieldView f;
+    f.ndim = ndim;
+    f.n[0] = n[0];
+    f.n[1] = ndim == 3 ? n[1] : 1;
+    f.n[2] = ndim == 3 ? n[2] : n[1];
+    f.sx = f.n[1] * f.n[2];
+    f.sy = ndim == 3 ? f.n[2] : 0;
+    return f;
+}
+
+int ckpt_compress(fwi_ctx *c, const float *field, int ndim, const int n[3], double atol, void *out,
+                  size_t cap, size_t *nbytes, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !field || !out || !nbytes || !n) throw Error{FWI_EINVAL, "null argument"};
+        if (ndim != 2 && ndim != 3) throw Error{FWI_EINVAL, "ndim must be 2 or 3"};
+        for (int d = 0; d < ndim; ++d)
+            if (n[d] < 1) throw Error{FWI_EINVAL, "dims must be >= 1"};
+        if (!(atol >= 2.2250738585072014e-308) || !std::isfinite(atol))
+            throw Error{FWI_EINVAL, "atol must be a positive normal number"};
+        begin_call(c, st);
+        FieldView f = dense_view(ndim, n);
+        ensure_codec(c, f, 1);
+        reset_status(c, st);
+        EncodeArgs e{};
+        e.f = f;
+        e.src = field;
+        e.atol = atol;
+        e.scratch = c->scratch.p;
+        e.chunk_bits = c->chunk_bits.p;
+        e.chunk_off = c->chunk_off.p;
+        e.dst = (unsigned char *)out;
+        e.cap = cap;
+        e.out_bytes = c->misc.p + 0;
+        e.pool_high = c->misc.p + 1;
+        e.total_bytes = c->misc.p + 2;
+        e.flags = c->flags.p;
+        {
+            Timer tm(c, st, K_ENC);
+            codec_encode(e, st);
+        }
+        HIPCHK(hipGetLastError());
+        unsigned long long nb = 0;
+        HIPCHK(hipMemcpyAsync(&nb, c->misc.p, sizeof(nb), hipMemcpyDeviceToHost, st));
+        finish_status(c, st);
+        *nbytes = (size_t)nb;
+        c->stats.n_encode = 1;
+        end_call(c, st);
+    });
+}
+
+int ckpt_decompress(fwi_ctx *c, const void *stream, size_t nbytes, float *field, int ndim, const int n[3],
+                    hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !stream || !field || !n) throw Error{FWI_EINVAL, "null argument"};
+        if (ndim != 2 && ndim != 3) throw Error{FWI_EINVAL, "ndim must be 2 or 3"};
+        for (int d = 0; d < ndim; ++d)
+            if (n[d] < 1) throw Error{FWI_EINVAL, "dims must be >= 1"};
+        begin_call(c, st);
+        FieldView f = dense_view(ndim, n);
+        CodecGeom g = codec_geom(ndim, f.n);
+        if (nbytes < 64) throw Error{FWI_ECORRUPT, "stream shorter than its header"};
+        unsigned char h[64];
+        HIPCHK(hipMemcpyAsync(h, stream, 64, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        auto u32 = [&](int o) { unsigned v; memcpy(&v, h + o, 4); return v; };
+        auto u64 = [&](int o) { unsigned long long v; memcpy(&v, h + o, 8); return v; };
+        const unsigned want[3] = {(unsigned)n[0], (unsigned)(ndim == 3 ? n[1] : n[1]),
+                                  (unsigned)(ndim == 3 ? n[2] : 1)};
+        if (memcmp(h, "FWZ1", 4) != 0 || h[4] != 1 || h[5] != 0) throw Error{FWI_ECORRUPT, "bad magic or version"};
+        if (h[6] != ndim || h[7] != 24 || h[20] != g.guard || h[22] != g.tp || h[21] != (ndim == 3 ? 4 : 6))
+            throw Error{FWI_ECORRUPT, "stream parameters do not match"};
+        if (u32(8) != want[0] || u32(12) != want[1] || u32(16) != want[2])
+            throw Error{FWI_ECORRUPT, "stream dims do not match"};
+        if ((long)u32(36) != g.nchunks || (long)u64(40) != g.nblocks) throw Error{FWI_ECORRUPT, "bad tables"};
+        const unsigned long long pbits = u64(48);
+        const unsigned long long total = 64ull + (unsigned long long)g.table_bytes + 8ull * ((pbits + 63) / 64);
+        if (u64(56) != total || nbytes < total) throw Error{FWI_ECORRUPT, "stream length mismatch"};
+        reset_status(c, st);
+        DecodeArgs d{};
+        d.f = f;
+        d.dst = field;
+        d.stream = (const unsigned char *)stream;
+        d.nbytes = nbytes;
+        d.flags = c->flags.p;
+        {
+            Timer tm(c, st, K_DEC);
+            codec_decode(d, st);
+        }
+        HIPCHK(hipGetLastError());
+        finish_status(c, st);
+        c->stats.n_decode = 1;
+        end_call(c, st);
+    });
+}
+
+int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap, int *nactions, long long *nforward)
+{
+    return guarded([&] {
+        if (nsteps < 1 || nslots < 0 || !nactions) throw Error{FWI_EINVAL, "bad arguments"};
+        std::vector<fwi_action> a = revolve_plan(nsteps, nslots);
+        *nactions = (int)a.size();
+        if (nforward) {
+            long long f = 0;
+            for (auto &x : a)
+                if (x.op == FWI_ADVANCE) f += x.b - x.a;
+            *nforward = f;
+        }
+        if ((int)a.size() > cap || !out) throw Error{FWI_ECAPACITY, "action buffer too small"};
+        std::copy(a.begin(), a.end(), out);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+"""ctypes binding of libfwigrad (include/fwigrad.h).
+
+Argument marshalling only: every step of the gradient path runs in the HIP
+kernels of libfwigrad.so; torch supplies device memory and the current
+stream.  Importing works without a GPU; any call needs the built library and
+a HIP device and fails loudly otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfwigrad.so")
+
+FWI_OK, FWI_EINVAL, FWI_ENOMEM, FWI_ECAPACITY = 0, -1, -2, -3
+FWI_ECORRUPT, FWI_ENONFINITE, FWI_EUNSTABLE, FWI_EHIP = -4, -5, -6, -7
+ADVANCE, TAKESHOT, RESTORE, REVERSE, FREE = range(5)
+_OPNAME = {ADVANCE: "advance", TAKESHOT: "takeshot", RESTORE: "restore",
+           REVERSE: "reverse", FREE: "free"}
+
+
+class FwiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libfwigrad error %d: %s" % (code, msg))
+        self.code = code
+
+
+class fwi_grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("h", ctypes.c_double),
+                ("space_order", ctypes.c_int), ("nbl", ctypes.c_int), ("nt", ctypes.c_int),
+                ("dt", ctypes.c_double), ("vmax", ctypes.c_double)]
+
+
+class fwi_shot(ctypes.Structure):
+    _fields_ = [("src", ctypes.c_int * 3), ("wavelet", ctypes.c_void_p),
+                ("nrec", ctypes.c_int), ("rec", ctypes.c_void_p)]
+
+
+class fwi_ckpt_cfg(ctypes.Structure):
+    _fields_ = [("nslots", ctypes.c_int), ("compress", ctypes.c_int),
+                ("atol", ctypes.c_double), ("pool_bytes", ctypes.c_size_t)]
+
+
+class fwi_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("ms_total", "ms_forward", "ms_adjoint", "ms_encode", "ms_decode")] + \
+               [(n, ctypes.c_longlong) for n in
+                ("n_forward", "n_adjoint", "n_encode", "n_decode", "ckpt_bytes",
+                 "ckpt_raw_bytes", "pool_high")]
+
+
+class fwi_action(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int), ("a", ctypes.c_int), ("b", ctypes.c_int)]
+
+
+_lib = None
+
+EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_stats",
+           "fwi_last_error", "fwi_forward", "fwi_gradient", "fwi_forward_ckpt",
+           "fwi_backward", "fwi_tape_free", "ckpt_bound", "ckpt_compress",
+           "ckpt_decompress", "fwi_revolve_plan"]
+
+
+def lib():
+    """Load libfwigrad.so (built by paper_2009_12623_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libfwigrad.so is not built; run __graft_entry__.build() "
+                           "or python -m paper_2009_12623_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    L.fwi_ctx_create.argtypes = [ctypes.POINTER(P), I, ctypes.c_size_t]
+    L.fwi_ctx_destroy.argtypes = [P]
+    L.fwi_ctx_set_timing.argtypes = [P, I]
+    L.fwi_ctx_stats.argtypes = [P, ctypes.POINTER(fwi_stats)]
+    L.fwi_last_error.restype = ctypes.c_char_p
+    L.fwi_forward.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), P, P]
+    L.fwi_gradient.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), P,
+                               ctypes.POINTER(fwi_ckpt_cfg), P, ctypes.POINTER(ctypes.c_double), P]
+    L.fwi_forward_ckpt.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot),
+                                   ctypes.POINTER(fwi_ckpt_cfg), P, ctypes.POINTER(P), P]
+    L.fwi_backward.argtypes = [P, P, P, P, P]
+    L.fwi_tape_free.argtypes = [P]
+    L.ckpt_bound.argtypes = [I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_size_t)]
+    L.ckpt_compress.argtypes = [P, P, I, ctypes.POINTER(ctypes.c_int), ctypes.c_double, P,
+                                ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]
+    L.ckpt_decompress.argtypes = [P, P, ctypes.c_size_t, P, I, ctypes.POINTER(ctypes.c_int), P]
+    L.fwi_revolve_plan.argtypes = [I, I, ctypes.POINTER(fwi_action), I, ctypes.POINTER(I),
+                                   ctypes.POINTER(ctypes.c_longlong)]
+    _lib = L
+    return L
+
+
+def check(rc):
+    if rc != FWI_OK:
+        raise FwiError(rc, lib().fwi_last_error().decode())
+
+
+def _dims3(shape):
+    return (ctypes.c_int * 3)(*(list(shape) + [1] * (3 - len(shape))))
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------- host-only calls
+def ckpt_bound(shape) -> int:
+    out = ctypes.c_size_t()
+    check(lib().ckpt_bound(len(shape), _dims3(shape), ctypes.byref(out)))
+    return out.value
+
+
+def fwi_revolve_plan(nsteps: int, nslots: int):
+    """[(op, a, b), ...] with op names as in the oracle's schedule, and the
+    number of forward steps."""
+    n = ctypes.c_int()
+    nf = ctypes.c_longlong()
+    rc = lib().fwi_revolve_plan(nsteps, nslots, None, 0, ctypes.byref(n), ctypes.byref(nf))
+    if rc not in (FWI_OK, FWI_ECAPACITY):
+        check(rc)
+    buf = (fwi_action * max(n.value, 1))()
+    check(lib().fwi_revolve_plan(nsteps, nslots, buf, n.value, ctypes.byref(n), ctypes.byref(nf)))
+    acts = []
+    for a in buf[:n.value]:
+        name = _OPNAME[a.op]
+        acts.append((name, a.a) if name in ("reverse", "free") else (name, a.a, a.b))
+    return acts, nf.value
+
+
+# ---------------------------------------------------------------- helpers
+def grid_of(shot) -> fwi_grid:
+    """fwi_grid from an object with ndim, shape, h, so, nbl, nt, dt, vmax."""
+    g = fwi_grid()
+    g.ndim = shot.ndim
+    g.n = _dims3(shot.shape)
+    g.h, g.space_order, g.nbl = shot.h, shot.so, shot.nbl
+    g.nt, g.dt, g.vmax = shot.nt, shot.dt, shot.vmax
+    return g
+
+
+class ShotArgs:
+    """Keeps the host receiver array and the device wavelet alive."""
+
+    def __init__(self, shot, wavelet: torch.Tensor):
+        self.rec = np.ascontiguousarray(np.asarray(shot.rec, dtype=np.int32).reshape(-1))
+        self.wavelet = wavelet
+        s = fwi_shot()
+        s.src = _dims3(tuple(shot.src))
+        s.wavelet = ctypes.c_void_p(wavelet.data_ptr())
+        s.nrec = len(self.rec) // shot.ndim if shot.ndim else 0
+        s.rec = self.rec.ctypes.data_as(ctypes.c_void_p) if len(self.rec) else None
+        self.c = s
+        self.nrec = s.nrec
+
+
+class Tape:
+    def __init__(self, ctx, handle, shot_args, m):
+        self.ctx, self.handle, self.shot_args, self.m = ctx, handle, shot_args, m
+
+    def free(self):
+        if self.handle:
+            check(lib().fwi_tape_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """One libfwigrad context on a HIP device."""
+
+    def __init__(self, device: int = 0, pool_bytes: int = 0):
+        self.device = device
+        h = ctypes.c_void_p()
+        check(lib().fwi_ctx_create(ctypes.byref(h), device, int(pool_bytes)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            check(lib().fwi_ctx_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, on: bool):
+        check(lib().fwi_ctx_set_timing(self.h, int(bool(on))))
+
+    def stats(self) -> dict:
+        s = fwi_stats()
+        check(lib().fwi_ctx_stats(self.h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in fwi_stats._fields_}
+
+    # Eq. (2)
+    def forward(self, shot, m: torch.Tensor, wavelet: torch.Tensor) -> torch.Tensor:
+        sa = ShotArgs(shot, wavelet)
+        g = grid_of(shot)
+        d = torch.empty((shot.nt, sa.nrec), dtype=torch.float32, device=m.device)
+        check(lib().fwi_forward(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), _ptr(d),
+                                _stream()))
+        return d
+
+    # Eqs. (3)-(4)
+    def gradient(self, shot, m, wavelet, d_obs, nslots=10, compress=False, atol=1e-4,
+                 grad=None):
+        sa = ShotArgs(shot, wavelet)
+        g = grid_of(shot)
+        cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), float(atol), 0)
+        out = torch.empty_like(m) if grad is None else grad
+        phi = ctypes.c_double()
+        check(lib().fwi_gradient(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), _ptr(d_obs),
+                                 ctypes.byref(cfg), _ptr(out), ctypes.byref(phi), _stream()))
+        return phi.value, out
+
+    def forward_ckpt(self, shot, m, wavelet, nslots=10, compress=False, atol=1e-4, pool_bytes=0):
+        sa = ShotArgs(shot, wavelet)
+        g = grid_of(shot)
+        cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), float(atol), int(pool_bytes))
+        d = torch.empty((shot.nt, sa.nrec), dtype=torch.float32, device=m.device)
+        t = ctypes.c_void_p()
+        check(lib().fwi_forward_ckpt(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c),
+                                     ctypes.byref(cfg), _ptr(d), ctypes.byref(t), _stream()))
+        return d, Tape(self, t, sa, m)
+
+    def backward(self, tape: Tape, dd: torch.Tensor, grad=None) -> torch.Tensor:
+        out = torch.empty_like(tape.m) if grad is None else grad
+        check(lib().fwi_backward(self.h, tape.handle, _ptr(dd.contiguous()), _ptr(out), _stream()))
+        return out
+
+    # codec (Sec. 1.4 / Sec. 3)
+    def compress(self, field: torch.Tensor, atol: float) -> torch.Tensor:
+        cap = ckpt_bound(field.shape)
+        out = torch.empty(cap, dtype=torch.uint8, device=field.device)
+        nb = ctypes.c_size_t()
+        check(lib().ckpt_compress(self.h, _ptr(field), field.dim(), _dims3(field.shape), float(atol),
+                                  _ptr(out), cap, ctypes.byref(nb), _stream()))
+        return out[:nb.value]
+
+    def decompress(self, stream: torch.Tensor, shape) -> torch.Tensor:
+        out = torch.empty(tuple(shape), dtype=torch.float32, device=stream.device)
+        check(lib().ckpt_decompress(self.h, _ptr(stream), stream.numel(), _ptr(out), len(shape),
+                                    _dims3(shape), _stream()))
+        return out

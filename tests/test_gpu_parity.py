@@ -1,0 +1,232 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars: FP32 receiver traces and gradients within relative L2 1e-4 of the FP64
+oracle; compressed streams bit-exact; uncompressed checkpointing bitwise equal
+to store-all (paper Sec. 1.3); compressed-checkpoint gradient within relative
+L2 1e-3 of the uncompressed one.  Sizes span several stencil tiles and codec
+chunks with ragged tails.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import codec as ocodec
+from oracle import metrics, solver
+
+pytestmark = pytest.mark.gpu
+
+F = pytest.importorskip("paper_2009_12623_amd.fwigrad")
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = F.Context(0, pool_bytes=1 << 30)
+    yield c
+    c.close()
+
+
+def inputs(shot, seed=3):
+    v0, vt = synth.tiny_models(shot.shape, seed=seed)
+    m0 = synth.slowness2(synth.extend(v0, shot.nbl)).astype(np.float32)
+    mt = synth.slowness2(synth.extend(vt, shot.nbl)).astype(np.float32)
+    q = shot.wavelet().astype(np.float32)
+    return m0, mt, q
+
+
+def oracle_problem(shot, m32, q32):
+    return solver.Problem(shot, m32.astype(np.float64), wavelet=q32.astype(np.float64))
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+CASES = [
+    # ndim, n, so, nbl, nt
+    (2, 37, 4, 6, 60),
+    (2, 70, 16, 10, 80),
+    (2, 300, 8, 8, 120),     # two 2D z-tiles, ragged
+    (3, 19, 8, 5, 40),
+    (3, 26, 4, 4, 30),       # several y tiles, ragged
+    (3, 14, 16, 4, 30),
+]
+
+
+@pytest.mark.parametrize("ndim,n,so,nbl,nt", CASES)
+def test_forward_traces_match_oracle(ctx, ndim, n, so, nbl, nt):
+    shot = synth.tiny_shot(ndim, n=n, so=so, nbl=nbl, nt=nt)
+    m0, _, q = inputs(shot)
+    d = ctx.forward(shot, dev(m0), dev(q)).cpu().numpy()
+    dref = solver.forward(oracle_problem(shot, m0, q))
+    err = metrics.rel_l2(d, dref)
+    print("forward", ndim, n, so, "rel L2 vs FP64", err)
+    assert err <= 1e-4
+
+
+@pytest.mark.parametrize("ndim,n,so,nbl,nt", CASES)
+def test_gradient_matches_oracle(ctx, ndim, n, so, nbl, nt):
+    shot = synth.tiny_shot(ndim, n=n, so=so, nbl=nbl, nt=nt)
+    m0, mt, q = inputs(shot)
+    p0 = oracle_problem(shot, m0, q)
+    pt = oracle_problem(shot, mt, q)
+    dobs = solver.forward(pt)
+    phi_ref, gref, _ = solver.gradient(p0, dobs)
+    phi, g = ctx.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=nt)
+    g = g.cpu().numpy()
+    err = metrics.rel_l2(g, gref)
+    print("gradient", ndim, n, so, "rel L2 vs FP64", err, "phi", phi, phi_ref)
+    assert err <= 1e-4
+    assert abs(phi - phi_ref) <= 1e-4 * phi_ref
+
+
+@pytest.mark.parametrize("nslots", [0, 1, 3, 7])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_revolve_is_bitwise_store_all(ctx, ndim, nslots):
+    shot = synth.tiny_shot(ndim, n=30 if ndim == 2 else 16, so=8, nbl=5, nt=45)
+    m0, mt, q = inputs(shot)
+    dobs = ctx.forward(shot, dev(mt), dev(q))
+    phi_a, ga = ctx.gradient(shot, dev(m0), dev(q), dobs, nslots=shot.nt)
+    phi_b, gb = ctx.gradient(shot, dev(m0), dev(q), dobs, nslots=nslots)
+    assert phi_a == phi_b
+    assert torch.equal(ga, gb)
+    st = ctx.stats()
+    from oracle import revolve
+    assert st["n_forward"] == revolve.T_closed(shot.nt, min(nslots, shot.nt))
+    assert st["n_adjoint"] == shot.nt
+
+
+@pytest.mark.parametrize("ndim,so", [(2, 4), (3, 8)])
+def test_compressed_gradient_close_to_exact(ctx, ndim, so):
+    shot = synth.tiny_shot(ndim, n=48 if ndim == 2 else 20, so=so, nbl=6, nt=70)
+    m0, mt, q = inputs(shot)
+    dobs = ctx.forward(shot, dev(mt), dev(q))
+    _, gexact = ctx.gradient(shot, dev(m0), dev(q), dobs, nslots=5)
+    errs = []
+    for atol in (1e-2, 1e-4, 1e-6):
+        _, gc = ctx.gradient(shot, dev(m0), dev(q), dobs, nslots=5, compress=True, atol=atol)
+        errs.append(metrics.rel_l2(gc.cpu().numpy(), gexact.cpu().numpy()))
+        st = ctx.stats()
+        assert st["n_encode"] > 0 and st["n_decode"] > 0
+    print("compressed gradient rel errors", errs)
+    assert errs[1] <= 1e-3
+    assert errs[2] <= errs[0]
+
+
+def test_compressed_gradient_matches_oracle_compressed(ctx):
+    shot = synth.tiny_shot(2, n=40, so=4, nbl=6, nt=60)
+    m0, mt, q = inputs(shot)
+    p0 = oracle_problem(shot, m0, q)
+    dobs = solver.forward(oracle_problem(shot, mt, q))
+    _, gref = solver.gradient_checkpointed(p0, dobs, 4, atol=1e-4)
+    _, g = ctx.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=4,
+                        compress=True, atol=1e-4)
+    assert metrics.rel_l2(g.cpu().numpy(), gref) <= 1e-3
+
+
+def test_autograd_split_equals_gradient(ctx):
+    shot = synth.tiny_shot(2, n=33, so=8, nbl=5, nt=50)
+    m0, mt, q = inputs(shot)
+    dobs = ctx.forward(shot, dev(mt), dev(q))
+    for compress in (False, True):
+        phi, g = ctx.gradient(shot, dev(m0), dev(q), dobs, nslots=4, compress=compress, atol=1e-4)
+        d, tape = ctx.forward_ckpt(shot, dev(m0), dev(q), nslots=4, compress=compress, atol=1e-4,
+                                   pool_bytes=1 << 26)
+        g2 = ctx.backward(tape, d - dobs)
+        tape.free()
+        assert torch.equal(g, g2)
+
+
+# ------------------------------------------------------------------ codec
+def codec_fields():
+    rng = np.random.default_rng(21)
+    yield synth.wavefield_like((37, 29, 45), seed=1)
+    yield synth.wavefield_like((130, 97), seed=2)
+    yield synth.wavefield_like((64, 64, 64), seed=3, noise=1e-3)
+    yield (rng.standard_normal((9, 17, 70)) * 3).astype(np.float32)
+    yield np.zeros((5, 6, 7), np.float32)
+    yield np.full((3, 2), 1.5, np.float32)
+    yield (rng.standard_normal((1, 1)) * 1.0).astype(np.float32)
+    x = (rng.standard_normal((33, 65)) * 2.0 ** rng.integers(-20, 6, (33, 65))).astype(np.float32)
+    x[0, :5] = np.float32(1e-42)         # subnormals count as zero
+    yield x
+
+
+@pytest.mark.parametrize("atol", [1e-1, 1e-3, 1e-4, 1e-6, 2.0 ** -70])
+def test_codec_streams_bit_exact(ctx, atol):
+    for x in codec_fields():
+        ref = ocodec.compress(x, atol)
+        s = ctx.compress(dev(x), atol).cpu().numpy().tobytes()
+        assert s == ref, (x.shape, atol, len(s), len(ref))
+        y = ctx.decompress(dev(np.frombuffer(ref, np.uint8).copy()), x.shape).cpu().numpy()
+        yref = ocodec.decompress(ref, x.shape)
+        assert np.array_equal(y.view(np.uint32), yref.view(np.uint32))
+
+
+def test_codec_on_oracle_wavefields(ctx):
+    # float32-rounded states of an oracle FP64 propagation (2D and 3D)
+    for ndim, n in ((2, 90), (3, 30)):
+        shot = synth.tiny_shot(ndim, n=n, so=8, nbl=6, nt=60)
+        m0, _, q = inputs(shot)
+        _, states = solver.forward(oracle_problem(shot, m0, q), keep_states=True)
+        for k in (10, 35, 60):
+            x = states[k].astype(np.float32)
+            for atol in (1e-2, 1e-4):
+                ref = ocodec.compress(x, atol)
+                s = ctx.compress(dev(x), atol).cpu().numpy().tobytes()
+                assert s == ref
+
+
+def test_codec_error_paths(ctx):
+    x = dev(synth.wavefield_like((20, 20, 20), seed=4))
+    s = ctx.compress(x, 1e-4)
+    with pytest.raises(F.FwiError) as e:
+        ctx.decompress(s[:-8], (20, 20, 20))
+    assert e.value.code == F.FWI_ECORRUPT
+    bad = s.clone()
+    bad[0] = 0
+    with pytest.raises(F.FwiError) as e:
+        ctx.decompress(bad, (20, 20, 20))
+    assert e.value.code == F.FWI_ECORRUPT
+    with pytest.raises(F.FwiError) as e:
+        ctx.decompress(s, (20, 20, 21))
+    assert e.value.code == F.FWI_ECORRUPT
+    y = x.clone()
+    y[3, 4, 5] = float("nan")
+    with pytest.raises(F.FwiError) as e:
+        ctx.compress(y, 1e-4)
+    assert e.value.code == F.FWI_ENONFINITE
+    import ctypes
+    out = torch.empty(100, dtype=torch.uint8, device=DEV)
+    nb = ctypes.c_size_t()
+    rc = F.lib().ckpt_compress(ctx.h, ctypes.c_void_p(x.data_ptr()), 3, F._dims3((20, 20, 20)),
+                               1e-4, ctypes.c_void_p(out.data_ptr()), 100, ctypes.byref(nb),
+                               F._stream())
+    assert rc == F.FWI_ECAPACITY
+
+
+def test_gradient_error_paths(ctx):
+    shot = synth.tiny_shot(2, n=20, so=4, nbl=4, nt=20)
+    m0, mt, q = inputs(shot)
+    dobs = ctx.forward(shot, dev(mt), dev(q))
+    import copy
+    bad = copy.copy(shot)
+    bad.dt = shot.dt * 2.0
+    with pytest.raises(F.FwiError) as e:
+        ctx.gradient(bad, dev(m0), dev(q), dobs)
+    assert e.value.code == F.FWI_EUNSTABLE
+    bad = copy.copy(shot)
+    bad.rec = np.array([[0, 2], [20, 2]], np.int32)
+    with pytest.raises(F.FwiError) as e:
+        ctx.forward(bad, dev(m0), dev(q))
+    assert e.value.code == F.FWI_EINVAL
+    small = F.Context(0, pool_bytes=1 << 12)
+    with pytest.raises(F.FwiError) as e:
+        small.gradient(shot, dev(m0), dev(q), dobs, nslots=3)
+    assert e.value.code == F.FWI_ECAPACITY
+    with pytest.raises(F.FwiError) as e:
+        small.gradient(shot, dev(m0), dev(q), dobs, nslots=3, compress=True, atol=1e-9)
+    assert e.value.code == F.FWI_ECAPACITY
+    small.close()

@@ -1,0 +1,74 @@
+"""Host-only checks of libfwigrad: it loads, exports every function the
+header declares, its schedule equals the oracle's, its codec bound equals the
+oracle's, and argument errors come back as status codes (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import codec as ocodec
+from oracle import revolve
+
+F = pytest.importorskip("paper_2009_12623_amd.fwigrad")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fwigrad.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    L = F.lib()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(F.EXPORTS) == names
+
+
+@pytest.mark.parametrize("N,s", [(1, 0), (5, 1), (10, 2), (37, 3), (60, 6), (200, 10),
+                                 (500, 10), (120, 119), (300, 1000)])
+def test_schedule_equals_oracle(N, s):
+    acts, nf = F.fwi_revolve_plan(N, s)
+    ref = revolve.schedule(N, s)
+    assert acts == ref
+    assert nf == revolve.T_closed(N, min(s, N)) == revolve.forward_steps(ref)
+
+
+def test_schedule_large_counts():
+    for N, s in [(2000, 40), (3000, 40), (1500, 40)]:
+        _, nf = F.fwi_revolve_plan(N, s)
+        assert nf == revolve.T_closed(N, s)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (4, 4), (181, 181), (1081, 481), (4, 4, 4),
+                                   (5, 9, 13), (256, 256, 256), (961, 961, 367)])
+def test_codec_bound_equals_oracle(shape):
+    assert F.ckpt_bound(shape) == ocodec.bound(shape)
+
+
+def test_bad_arguments_are_status_codes():
+    L = F.lib()
+    n = ctypes.c_int()
+    assert L.fwi_revolve_plan(0, 3, None, 0, ctypes.byref(n), None) == F.FWI_EINVAL
+    assert L.fwi_revolve_plan(10, -1, None, 0, ctypes.byref(n), None) == F.FWI_EINVAL
+    assert L.fwi_revolve_plan(10, 2, None, 0, ctypes.byref(n), None) == F.FWI_ECAPACITY
+    out = ctypes.c_size_t()
+    dims = (ctypes.c_int * 3)(4, 0, 4)
+    assert L.ckpt_bound(3, dims, ctypes.byref(out)) == F.FWI_EINVAL
+    assert L.ckpt_bound(4, dims, ctypes.byref(out)) == F.FWI_EINVAL
+    assert b"dims" in L.fwi_last_error() or len(L.fwi_last_error()) > 0
+
+
+def test_context_creation_without_device_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    h = ctypes.c_void_p()
+    rc = F.lib().fwi_ctx_create(ctypes.byref(h), 0, 0)
+    assert rc in (F.FWI_EHIP, F.FWI_EINVAL)
