@@ -1,0 +1,331 @@
+#!/usr/bin/env python3
+"""Benchmark: compressed-checkpoint FWI gradient on one MI355X.
+
+One step = one full gradient of one shot (forward sweep with checkpoints,
+reverse sweep with restores/recomputation, adjoint + imaging, residual and
+objective) on the 3D workload: 881x881x287 physical grid at 25 m plus a
+40-point absorbing layer (961x961x367 computational points), space order 8,
+2000 steps, 8 Hz Ricker, 221x221 surface receivers, a synthetic
+thrust-faulted layered model (2.2-6.0 km/s, smoothed for the gradient).
+
+Checkpoint slots for the compressed run are chosen under the HBM budget of
+uncompressed Revolve with 40 slots, by a cost model fed with the kernel
+times of a pilot run.  Prints one JSON line (see README of the metric in
+the design doc).  Inputs are generated on the device before timing starts.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "FWI gradient s/shot & stencil Gpt/s at fixed grad error; codec GB/s"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------- workloads
+def workload_c3(torch, dev, nt):
+    import synth
+    shot = synth.config3_shot(nt=nt)
+    t0 = time.time()
+    vt = synth.thrust_3d_torch(shot.shape, dev)
+    vs = synth.gauss_smooth_torch(vt, 3.0)
+    m0 = (1.0 / synth.extend_torch(vs, shot.nbl) ** 2).float().contiguous()
+    mt = (1.0 / synth.extend_torch(vt, shot.nbl) ** 2).float().contiguous()
+    del vt, vs
+    log("model %s built in %.1f s" % (tuple(m0.shape), time.time() - t0))
+    name = ("3D acoustic FWI gradient, single shot: 881x881x287 physical at 25 m "
+            "(961x961x367 with the 40-point layer), SO8, %d steps, 8 Hz Ricker, "
+            "221x221 surface receivers, synthetic thrust-faulted layers" % nt)
+    return shot, m0, mt, name, 40
+
+
+def workload_c1(torch, dev, nt):
+    import synth
+    shot = synth.config1_shot(nt=nt)
+    v0, vt = synth.layered_2d()
+    m0 = torch.from_numpy(synth.slowness2(synth.extend(v0, shot.nbl)).astype(np.float32)).to(dev)
+    mt = torch.from_numpy(synth.slowness2(synth.extend(vt, shot.nbl)).astype(np.float32)).to(dev)
+    name = ("2D acoustic FWI gradient, single shot: 101x101 at 10 m (181x181 with the "
+            "40-point layer), SO4, %d steps, 10 Hz Ricker, 101 receivers" % nt)
+    return shot, m0, mt, name, 10
+
+
+# ------------------------------------------------------------ cost model
+def schedule_counts(F, nt, s):
+    acts, nf = F.fwi_revolve_plan(nt, s)
+    nts = sum(1 for a in acts if a[0] == "takeshot")
+    rr = ra = 0
+    for i, a in enumerate(acts):
+        if a[0] == "restore" and a[1] >= 0:
+            if i + 1 < len(acts) and acts[i + 1][0] == "reverse":
+                rr += 1
+            else:
+                ra += 1
+    return nf, nts, rr, ra
+
+
+def choose_slots(F, nt, st, budget, margin=1.3):
+    """Least predicted time over slot counts whose compressed checkpoints fit
+    the budget.  Costs per unit from the pilot run's HIP-event timings."""
+    tf = st["ms_forward"] / max(st["n_forward"], 1)
+    ta = st["ms_adjoint"] / max(st["n_adjoint"], 1)
+    te = st["ms_encode"] / max(st["n_encode"], 1)
+    td = st["ms_decode"] / max(st["n_decode"], 1)
+    per_field = st["ckpt_bytes"] / max(st["n_encode"], 1)
+    best = None
+    cands = sorted({40, 50, 64, 80, 100, 128, 160, 200, 256, 320, 400, 512, 640, 800,
+                    1000, 1280, 1600, 2000, 2500, 3000, nt})
+    table = []
+    for s in cands:
+        if s > nt or 2 * s * per_field * margin > budget:
+            continue
+        nf, nts, rr, ra = schedule_counts(F, nt, s)
+        t = nf * tf + nt * ta + 2 * nts * te + (rr + 2 * ra) * td
+        table.append((s, round(t / 1e3, 3)))
+        if best is None or t < best[1]:
+            best = (s, t)
+    return best, table, dict(tf=tf, ta=ta, te=te, td=td, per_field=per_field)
+
+
+# ----------------------------------------------------------- CPU oracle
+def cpu_baseline(shot, m0_host, counts, seconds=8.0):
+    """Time the FP64 oracle on a bounded sample of the same workload and
+    extrapolate to one gradient with the same schedule counts."""
+    import synth
+    from oracle import codec as ocodec
+    from oracle import solver
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.time()
+    p = solver.Problem(shot, m0_host)
+    setup = time.time() - t0
+    u2, u1 = p.zeros(), p.zeros()
+    nf = 0
+    t0 = time.time()
+    while True:
+        u = p.step(u1, u2, [p.src], [p.q[nf]])
+        u2, u1 = u1, u
+        nf += 1
+        if time.time() - t0 > seconds:
+            break
+    tf = (time.time() - t0) / nf
+    l1, l2 = p.zeros(), p.zeros()
+    g = p.zeros()
+    res = np.random.default_rng(0).standard_normal((1, len(p.rec)))
+    na = 0
+    t0 = time.time()
+    while True:
+        l0 = p.step(l1, l2, p.rec, res[0])
+        p.image(g, u1, l0, l1, l2)
+        l2, l1 = l1, l0
+        na += 1
+        if time.time() - t0 > seconds:
+            break
+    ta = (time.time() - t0) / na
+    del u, u1, u2, l0, l1, l2, g, p
+    slab = synth.wavefield_like((256, 64, shot.comp_shape[2]), seed=5)
+    t0 = time.time()
+    s = ocodec.compress(slab, counts["atol"])
+    te = time.time() - t0
+    t0 = time.time()
+    ocodec.decompress(s, slab.shape)
+    td = time.time() - t0
+    scale = float(np.prod(shot.comp_shape)) / slab.size
+    total = (counts["n_forward"] * tf + counts["n_adjoint"] * ta +
+             counts["n_encode"] * te * scale + counts["n_decode"] * td * scale)
+    sample = ("FP64 oracle on the full grid: %d forward steps (%.2f s each) and %d adjoint+imaging "
+              "steps (%.2f s each); codec on a 256x64x%d slab of a synthetic wavefield scaled to the "
+              "field; extrapolated with this run's counts (%d forward, %d adjoint, %d encodes, "
+              "%d decodes); set-up %.1f s excluded" % (nf, tf, na, ta, shot.comp_shape[2],
+                                                       counts["n_forward"], counts["n_adjoint"],
+                                                       counts["n_encode"], counts["n_decode"], setup))
+    return {"value": round(total, 1), "unit": "s/shot", "cores": threads, "kind": "oracle",
+            "sample": sample}
+
+
+# ------------------------------------------------------------------ main
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1"])
+    ap.add_argument("--nt", type=int, default=None)
+    ap.add_argument("--atol", type=float, default=1e-4)
+    ap.add_argument("--slots", type=int, default=0, help="compressed slots (0: cost model)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 1 GiB device copies (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the path shards by shot with one gradient "
+              "all-reduce, which this build does not run (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2009_12623_amd.fwigrad as F
+    from oracle import metrics
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
+                          "launches": 5}))
+        return
+    wl = workload_c3 if args.workload == "c3" else workload_c1
+    nt = args.nt or (2000 if args.workload == "c3" else 500)
+    shot, m0, mt, name, s_unc = wl(torch, dev, nt)
+    q = torch.from_numpy(shot.wavelet().astype(np.float32)).to(dev)
+    npts = int(np.prod(shot.comp_shape))
+    nphys = int(np.prod(shot.shape))
+
+    ctx = F.Context(0, pool_bytes=int(os.environ.get("FWI_POOL_BYTES", 140 << 30)))
+    ctx.set_timing(True)
+    t0 = time.time()
+    d_obs = ctx.forward(shot, mt, q)
+    torch.cuda.synchronize()
+    log("observed data %s in %.2f s" % (tuple(d_obs.shape), time.time() - t0))
+
+    # uncompressed Revolve reference (the comparison and the HBM budget)
+    t0 = time.time()
+    phi_u, g_u = ctx.gradient(shot, m0, q, d_obs, nslots=s_unc)
+    torch.cuda.synchronize()
+    t_unc = time.time() - t0
+    st_u = ctx.stats()
+    budget = st_u["pool_high"] if st_u["pool_high"] else st_u["ckpt_bytes"]
+    budget = max(budget, 2 * s_unc * 4 * npts)
+    log("uncompressed s=%d: %.2f s, phi %.6e, budget %.1f GB" % (s_unc, t_unc, phi_u, budget / 1e9))
+
+    # pilot compressed run at equal slots: sizes and unit costs
+    t0 = time.time()
+    phi_p, g_p = ctx.gradient(shot, m0, q, d_obs, nslots=s_unc, compress=True, atol=args.atol)
+    torch.cuda.synchronize()
+    t_pilot = time.time() - t0
+    st_p = ctx.stats()
+    err_p = metrics.rel_l2(g_p.cpu().numpy(), g_u.cpu().numpy())
+    log("pilot compressed s=%d: %.2f s, rel err %.2e, %d B/field" %
+        (s_unc, t_pilot, err_p, st_p["ckpt_bytes"] // max(st_p["n_encode"], 1)))
+    if args.slots:
+        s_c, table, unit = args.slots, [], {}
+    else:
+        best, table, unit = choose_slots(F, nt, st_p, budget)
+        s_c = best[0] if best else s_unc
+        log("cost model (slots, predicted s):", table, "->", s_c)
+    del g_p
+
+    def run():
+        return ctx.gradient(shot, m0, q, d_obs, nslots=s_c, compress=True, atol=args.atol,
+                            pool_bytes=int(budget))
+
+    while True:
+        try:
+            for i in range(args.warmup):
+                run()
+            break
+        except F.FwiError as e:
+            if e.code != F.FWI_ECAPACITY or s_c <= s_unc:
+                raise
+            s_c = max(s_unc, int(s_c * 0.8))
+            log("pool overflow, retrying with %d slots" % s_c)
+    torch.cuda.synchronize()
+    log("warmup done")
+    t0 = time.time()
+    for i in range(args.steps):
+        phi_c, g_c = run()
+        log("step %d/%d done" % (i + 1, args.steps))
+    torch.cuda.synchronize()
+    t1 = time.time()
+    st = ctx.stats()
+    s_per_shot = (t1 - t0) / args.steps
+    err = metrics.rel_l2(g_c.cpu().numpy(), g_u.cpu().numpy())
+
+    # roofline of the dominant kernel (time-weighted), from HIP events on the
+    # stream the kernels run on
+    kinds = {
+        "forward_step": (st["ms_forward"], st["n_forward"], 16.0 * npts),
+        "adjoint_imaging_step": (st["ms_adjoint"], st["n_adjoint"], 28.0 * npts),
+    }
+    cf = st["ckpt_raw_bytes"] / max(st["ckpt_bytes"], 1)
+    if st["n_encode"]:
+        kinds["codec_encode"] = (st["ms_encode"], st["n_encode"], 4.0 * npts * (1 + 1 / cf))
+    if st["n_decode"]:
+        kinds["codec_decode"] = (st["ms_decode"], st["n_decode"], 4.0 * npts * (1 + 1 / cf))
+    dom = max(kinds, key=lambda k: kinds[k][0])
+    ms, n, bytes_per = kinds[dom]
+    avg_ms = ms / max(n, 1)
+    achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": bytes_per}
+    fwd_avg = st["ms_forward"] / max(st["n_forward"], 1)
+    out = {
+        "metric": METRIC,
+        "value": round(s_per_shot, 3),
+        "unit": "s/shot",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * s_per_shot, 1),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": name,
+            "computational_grid": list(shot.comp_shape),
+            "nt": nt,
+            "space_order": shot.so,
+            "atol": args.atol,
+            "nslots_compressed": s_c,
+            "nslots_uncompressed": s_unc,
+            "hbm_budget_gb": round(budget / 1e9, 2),
+        },
+        "roofline": roof,
+        "stencil_gpts": {"forward": round(npts / (fwd_avg * 1e-3) / 1e9, 2),
+                         "forward_physical": round(nphys / (fwd_avg * 1e-3) / 1e9, 2),
+                         "adjoint": round(npts / (st["ms_adjoint"] / max(st["n_adjoint"], 1) * 1e-3) / 1e9, 2)},
+        "codec_gbs": {
+            "encode": round(st["n_encode"] * 4.0 * npts / (st["ms_encode"] * 1e-3) / 1e9, 1) if st["n_encode"] else None,
+            "decode": round(st["n_decode"] * 4.0 * npts / (st["ms_decode"] * 1e-3) / 1e9, 1) if st["n_decode"] else None,
+            "compression_factor": round(cf, 2),
+        },
+        "uncompressed_revolve": {"s_per_shot": round(t_unc, 3), "nslots": s_unc},
+        "speedup_vs_uncompressed": round(t_unc / s_per_shot, 3),
+        "grad_rel_l2_vs_uncompressed": float("%.3e" % err),
+        "phi": phi_c,
+        "counts": {k: st[k] for k in ("n_forward", "n_adjoint", "n_encode", "n_decode")},
+        "kernel_ms": {k: round(st[k], 1) for k in ("ms_forward", "ms_adjoint", "ms_encode", "ms_decode", "ms_total")},
+        "cost_model": {"table": table, "unit_ms": {k: round(v, 4) for k, v in unit.items()}},
+    }
+    if not args.no_cpu_baseline:
+        m_host = m0.double().cpu().numpy()
+        del g_u, g_c
+        counts = dict(n_forward=st["n_forward"], n_adjoint=st["n_adjoint"],
+                      n_encode=st["n_encode"], n_decode=st["n_decode"], atol=args.atol)
+        ctx.close()
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(shot, m_host, counts)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -90,7 +90,8 @@ typedef struct {
  * compress = 0 stores exact copies (the gradient then equals the store-all
  * gradient bit for bit), 1 stores each level compressed with absolute
  * tolerance atol; pool_bytes sizes the checkpoint pool of a tape
- * (fwi_forward_ckpt), 0 = the context's default. */
+ * (fwi_forward_ckpt) or caps the part of the context's pool that
+ * fwi_gradient may use; 0 = the context's pool size. */
 typedef struct {
     int nslots;
     int compress;

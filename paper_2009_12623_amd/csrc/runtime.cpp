@@ -480,6 +480,7 @@ struct Exec {
             HIPCHK(hipMemcpyAsync(pool + off + raw_bytes, prev - S.pad.origin, raw_bytes,
                                   hipMemcpyDeviceToDevice, st));
             c->stats.ckpt_bytes += 2LL * (long long)raw_bytes;
+            c->stats.pool_high = std::max<long long>(c->stats.pool_high, (long long)(off + 2 * raw_bytes));
             return;
         }
         for (int lev = 0; lev < 2; ++lev) {
@@ -654,7 +655,7 @@ void finish_status(fwi_ctx *c, hipStream_t st)
     HIPCHK(hipMemcpyAsync(&fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(misc, c->misc.p, sizeof(misc), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    c->stats.pool_high = (long long)misc[1];
+    if (misc[1]) c->stats.pool_high = (long long)misc[1];
     if (misc[2]) c->stats.ckpt_bytes = (long long)misc[2];
     if (fl & 1u) throw Error{FWI_ENONFINITE, "non-finite wavefield reached the codec"};
     if (fl & 2u) throw Error{FWI_ECAPACITY, "checkpoint pool overflow (use fewer slots or a larger pool)"};
@@ -775,8 +776,9 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         FieldView fv = padded_view(ex.S);
         if (cfg->compress) ensure_codec(c, fv, 2 * used);
         if (c->pool.n < c->pool_default) c->pool.ensure(c->pool_default);
+        const size_t cap = cfg->pool_bytes ? std::min(cfg->pool_bytes, c->pool_default) : c->pool_default;
         reset_status(c, st);
-        setup_ckpt(ex, cfg, c->pool.p, c->pool_default, c->slots.p, used);
+        setup_ckpt(ex, cfg, c->pool.p, cap, c->slots.p, used);
         const size_t nd = (size_t)ex.S.nt * ex.S.nrec;
         c->dsim.ensure(std::max<size_t>(nd, 1));
         c->res.ensure(std::max<size_t>(nd, 1));

@@ -224,10 +224,10 @@ class Context:
 
     # Eqs. (3)-(4)
     def gradient(self, shot, m, wavelet, d_obs, nslots=10, compress=False, atol=1e-4,
-                 grad=None):
+                 grad=None, pool_bytes=0):
         sa = ShotArgs(shot, wavelet)
         g = grid_of(shot)
-        cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), float(atol), 0)
+        cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), float(atol), int(pool_bytes))
         out = torch.empty_like(m) if grad is None else grad
         phi = ctypes.c_double()
         check(lib().fwi_gradient(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), _ptr(d_obs),

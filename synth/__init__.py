@@ -159,14 +159,10 @@ def wavefield_like(shape, seed=12624, nshell=6, f_pts=8.0, noise=0.0):
 
 
 # ------------------------------------------------- 3D thrust-faulted layers
-def thrust_3d(shape, nlayer=10, vmin=2200.0, vmax=6000.0, seed=12625,
-              fold_pts=15.0, fault_pts=20.0):
-    """Layered 3D model with folded interfaces and two dipping thrust faults
-    (a synthetic stand-in for the SEG/EAGE Overthrust model, whose values are
-    not used).  Velocity increases with layer index from vmin to vmax."""
+def _thrust_params(shape, nlayer, seed, fold_pts, fault_pts):
+    """Seeded fault planes and folded interface surfaces (2D arrays)."""
     nx, ny, nz = shape
     rng = np.random.default_rng(seed)
-    speeds = np.linspace(vmin, vmax, nlayer)
     x = np.arange(nx, dtype=np.float64)[:, None]
     y = np.arange(ny, dtype=np.float64)[None, :]
     # two thrust faults: planes x cos(a) + y sin(a) = d0 + z tan(dip); the
@@ -178,21 +174,83 @@ def thrust_3d(shape, nlayer=10, vmin=2200.0, vmax=6000.0, seed=12625,
         dip = math.tan(rng.uniform(math.radians(25), math.radians(45)))
         off = rng.uniform(0.5, 1.0) * fault_pts
         faults.append((math.cos(a), math.sin(a), d0, dip, off))
-    idx = np.zeros(shape, dtype=np.int16)
-    zz = np.arange(nz, dtype=np.float64)[None, None, :]
+    surfs = []
     for i in range(1, nlayer):
-        base = nz * i / nlayer
-        surf = np.full((nx, ny), base)
+        surf = np.full((nx, ny), nz * i / nlayer)
         for _ in range(2):
             k = rng.uniform(0.5, 2.5, 2) * 2 * math.pi / np.array([nx, ny])
             ph = rng.uniform(0, 2 * math.pi, 2)
             surf += 0.5 * fold_pts * np.sin(k[0] * x + ph[0]) * np.sin(k[1] * y + ph[1])
+        surfs.append(surf)
+    return faults, surfs
+
+
+def thrust_3d(shape, nlayer=10, vmin=2200.0, vmax=6000.0, seed=12625,
+              fold_pts=15.0, fault_pts=20.0):
+    """Layered 3D model with folded interfaces and two dipping thrust faults
+    (a synthetic stand-in for the SEG/EAGE Overthrust model, whose values are
+    not used).  Velocity increases with layer index from vmin to vmax."""
+    nx, ny, nz = shape
+    faults, surfs = _thrust_params(shape, nlayer, seed, fold_pts, fault_pts)
+    speeds = np.linspace(vmin, vmax, nlayer)
+    x = np.arange(nx, dtype=np.float64)[:, None]
+    y = np.arange(ny, dtype=np.float64)[None, :]
+    zz = np.arange(nz, dtype=np.float64)[None, None, :]
+    idx = np.zeros(shape, dtype=np.int16)
+    for surf in surfs:
         zsurf = surf[:, :, None] + np.zeros_like(zz)
         for cx, sy, d0, dip, off in faults:
             hang = (cx * x + sy * y)[:, :, None] - dip * zz > d0
             zsurf = np.where(hang, zsurf - off, zsurf)
         idx += (zz >= zsurf).astype(np.int16)
     return speeds[idx]
+
+
+def thrust_3d_torch(shape, device, nlayer=10, vmin=2200.0, vmax=6000.0, seed=12625,
+                    fold_pts=15.0, fault_pts=20.0):
+    """``thrust_3d`` assembled with torch on ``device`` (same draws)."""
+    import torch
+    nx, ny, nz = shape
+    faults, surfs = _thrust_params(shape, nlayer, seed, fold_pts, fault_pts)
+    f64 = dict(dtype=torch.float64, device=device)
+    x = torch.arange(nx, **f64)[:, None, None]
+    y = torch.arange(ny, **f64)[None, :, None]
+    zz = torch.arange(nz, **f64)[None, None, :]
+    idx = torch.zeros(shape, dtype=torch.int16, device=device)
+    hangs = [((cx * x + sy * y) - dip * zz > d0, off) for cx, sy, d0, dip, off in faults]
+    for surf in surfs:
+        zsurf = torch.as_tensor(surf, **f64)[:, :, None].expand(nx, ny, nz)
+        for hang, off in hangs:
+            zsurf = torch.where(hang, zsurf - off, zsurf)
+        idx += (zz >= zsurf).to(torch.int16)
+    speeds = torch.as_tensor(np.linspace(vmin, vmax, nlayer), **f64)
+    return speeds[idx.long()]
+
+
+def gauss_smooth_torch(v, sigma, truncate=4.0):
+    """Separable Gaussian smoothing with edge replication (torch)."""
+    import torch
+    import torch.nn.functional as Fn
+    r = int(truncate * sigma + 0.5)
+    t = torch.arange(-r, r + 1, dtype=v.dtype, device=v.device)
+    w = torch.exp(-0.5 * (t / sigma) ** 2)
+    w = (w / w.sum()).view(1, 1, -1)
+    out = v
+    for ax in range(v.dim()):
+        moved = out.movedim(ax, -1)
+        shp = moved.shape
+        flat = moved.reshape(-1, 1, shp[-1])
+        flat = Fn.conv1d(Fn.pad(flat, (r, r), mode="replicate"), w)
+        out = flat.reshape(shp).movedim(-1, ax)
+    return out.contiguous()
+
+
+def extend_torch(v, nbl):
+    import torch.nn.functional as Fn
+    if nbl <= 0:
+        return v.clone()
+    pad = (nbl,) * (2 * v.dim())
+    return Fn.pad(v[None, None], pad, mode="replicate")[0, 0].contiguous()
 
 
 def config3_shot(shape=(881, 881, 287), nt=2000, rec_step=4):
