@@ -66,16 +66,24 @@ def workload_c1(torch, dev, nt):
 
 # ------------------------------------------------------------ cost model
 def schedule_counts(F, nt, s):
+    """forward steps, fields encoded, restores decoding u^k only, restores
+    decoding both levels (a checkpoint keeps u^{k-1} only when the schedule
+    restarts from it)."""
     acts, nf = F.fwi_revolve_plan(nt, s)
-    nts = sum(1 for a in acts if a[0] == "takeshot")
-    rr = ra = 0
+    nenc = rr = ra = 0
+    open_ = {}
     for i, a in enumerate(acts):
-        if a[0] == "restore" and a[1] >= 0:
+        if a[0] == "takeshot":
+            open_[a[1]] = False
+        elif a[0] == "restore" and a[1] >= 0:
             if i + 1 < len(acts) and acts[i + 1][0] == "reverse":
                 rr += 1
             else:
                 ra += 1
-    return nf, nts, rr, ra
+                open_[a[1]] = True
+        elif a[0] == "free":
+            nenc += 2 if open_.pop(a[1]) else 1
+    return nf, nenc, rr, ra
 
 
 def choose_slots(F, nt, st, budget, margin=1.3):
@@ -93,8 +101,8 @@ def choose_slots(F, nt, st, budget, margin=1.3):
     for s in cands:
         if s > nt or 2 * s * per_field * margin > budget:
             continue
-        nf, nts, rr, ra = schedule_counts(F, nt, s)
-        t = nf * tf + nt * ta + 2 * nts * te + (rr + 2 * ra) * td
+        nf, nenc, rr, ra = schedule_counts(F, nt, s)
+        t = nf * tf + nt * ta + nenc * te + (rr + 2 * ra) * td
         table.append((s, round(t / 1e3, 3)))
         if best is None or t < best[1]:
             best = (s, t)
@@ -169,6 +177,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (HBM counter calibration)")
+    ap.add_argument("--sweep", default="",
+                    help="comma list of variant:xchunk pairs for the 3D stencil; times forward "
+                         "and adjoint steps per pair")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path shards by shot with one gradient "
@@ -182,18 +193,50 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     if args.copy_calibration:
-        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
-                          "launches": 5}))
+        # 1 GiB streams through the library's probe kernel (one float per lane)
+        n = 1 << 28
+        a = torch.ones(n, dtype=torch.float32, device=dev)
+        b, c, d = torch.ones_like(a), torch.ones_like(a), torch.empty_like(a)
+        res = {}
+        for nsrc in (1, 3):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            for it in range(6):
+                if it == 1:
+                    ev0.record()
+                F.fwi_bandwidth_probe(a, d) if nsrc == 1 else F.fwi_bandwidth_probe(a, d, b, c)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / 5
+            res["probe_%d_reads" % nsrc] = {"bytes_read": 4 * n * nsrc, "bytes_written": 4 * n,
+                                            "ms": round(ms, 4),
+                                            "GBs": round(4 * n * (nsrc + 1) / ms / 1e6, 1)}
+        print(json.dumps(res))
         return
     wl = workload_c3 if args.workload == "c3" else workload_c1
     nt = args.nt or (2000 if args.workload == "c3" else 500)
     shot, m0, mt, name, s_unc = wl(torch, dev, nt)
     q = torch.from_numpy(shot.wavelet().astype(np.float32)).to(dev)
+    if args.sweep:
+        npts = int(np.prod(shot.comp_shape))
+        rows = []
+        for item in args.sweep.split(","):
+            var, xc = item.split(":")
+            os.environ["FWI_XCHUNK"] = xc
+            c = F.Context(0, pool_bytes=40 << 30)
+            c.set_timing(True)
+            d = c.forward(shot, mt, q)
+            c.gradient(shot, m0, q, d, nslots=8)
+            st = c.stats()
+            tf = st["ms_forward"] / st["n_forward"]
+            ta = st["ms_adjoint"] / st["n_adjoint"]
+            rows.append({"variant": int(var), "xchunk": int(xc), "fwd_ms": round(tf, 4),
+                         "adj_ms": round(ta, 4),
+                         "fwd_GBs": round(16 * npts / tf / 1e6, 1),
+                         "adj_GBs": round(28 * npts / ta / 1e6, 1)})
+            log(rows[-1])
+            c.close()
+        print(json.dumps({"sweep": rows, "nt": nt}))
+        return
     npts = int(np.prod(shot.comp_shape))
     nphys = int(np.prod(shot.shape))
 

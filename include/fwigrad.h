@@ -180,6 +180,13 @@ int ckpt_decompress(fwi_ctx *ctx, const void *stream_bytes, size_t nbytes,
 int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
                      int *nactions, long long *nforward);
 
+/* Bandwidth probe with the stencils' access width (one float per lane):
+ * d = a (nsrc = 1) or d = a + b + c (nsrc = 3), n floats, all [device].
+ * Measures the practical streaming ceiling and calibrates HBM counters
+ * against a kernel of known traffic; not part of the gradient path. */
+int fwi_bandwidth_probe(const float *a, const float *b, const float *c, float *d,
+                        size_t n, int nsrc, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -38,6 +38,9 @@ def linf(F, G) -> float:
 
 
 def rel_l2(F, G) -> float:
-    """||F - G|| / ||G||"""
+    """||F - G|| / ||G|| (0 when both vanish, inf when only G does)"""
     G = np.asarray(G, np.float64)
-    return l2(F, G) / float(np.linalg.norm(G))
+    num, den = l2(F, G), float(np.linalg.norm(G))
+    if den == 0.0:
+        return 0.0 if num == 0.0 else math.inf
+    return num / den

@@ -7,15 +7,17 @@
 
 namespace fwi {
 
-// Working wavefields live in padded buffers so the stencil needs no bounds
-// checks: PAD_X/PAD_Y points before and after x/y, PAD_Z0 before z (keeps
-// interior rows 64-byte aligned) and tile slack after z.  The pads are
-// zero and never written.
+// Every array a time step touches lives in one padded layout so the stencil
+// needs no bounds checks: PAD_X/PAD_Y points before and after x/y, PAD_Z0
+// before z (interior rows start on a 128-byte line) and tile slack plus
+// PAD_Z0 after z.  The pads are zero and never written.  Kernels address a
+// padded array with 32-bit byte offsets from its allocation base, so one
+// padded array holds fewer than 2^30 floats (checked on the host).
 constexpr int PAD_X = 8;
 constexpr int PAD_Y = 8;
-constexpr int PAD_Z0 = 16;
+constexpr int PAD_Z0 = 32;
 constexpr int TILE_Z = 64;     // one wave64 along z
-constexpr int TILE_Y = 8;      // waves along y in the 3D stencil
+constexpr int TILE_Y = 16;     // y rows of a 3D stencil tile (8 waves, 2 rows each)
 constexpr int TILE_Z2 = 256;   // z extent of a 2D stencil workgroup
 
 struct Padded {
@@ -30,44 +32,58 @@ struct Padded {
 Padded make_padded(int ndim, const int *comp);
 
 // ------------------------------------------------------------------ stencil
+// All field pointers are allocation bases of padded arrays.
 struct StepParams {
-    const float *u1;        // level k-1 (forward) or k+1 (adjoint); padded, at origin
-    const float *u2;        // level k-2 / k+2; padded, at origin
-    float *out;             // new level; padded, at origin; may equal u2
-    const float *b;         // dt^2/m, computational grid (unpadded)
-    const float *uk;        // adjoint only: forward state u^k, padded, at origin
-    float *g;               // adjoint only: gradient, unpadded
+    const float *u1;        // level k-1 (forward) or k+1 (adjoint)
+    const float *u2;        // level k-2 / k+2
+    float *out;             // new level; may equal u2
+    const float *b;         // dt^2/m
+    const float *uk;        // adjoint only: forward state u^k
+    float *g;               // adjoint only: gradient accumulator
     long psx, psy;          // padded strides
-    long sx, sy;            // unpadded strides
+    long origin;            // element offset of the interior point (0,0,0)
     int nx, ny, nz, nbl;
     float kappa;            // e = kappa * b * sum(d_axis^2)
     float inv_dt2;
     float w[9];             // a_k / h^2, k = 0..R
-    long src;               // unpadded index of the source node, -1 if none
+    long src;               // origin-relative padded offset of the source node, -1 if none
     const float *wav;       // wavelet (device)
     int step;               // wavelet sample injected by this step
     int xchunk;             // x planes per workgroup
+    // forward only: sample u1 at the receivers into grow (nullptr: skip)
+    const int *rec_off;     // padded offsets from the allocation base
+    int nrec;
+    float *grow;
 };
 
 void launch_step(const StepParams &p, int ndim, int radius, bool adjoint,
                  hipStream_t st);
 
-void launch_coef(const float *m, float *b, size_t n, double dt, hipStream_t st);
-void launch_gather(const float *field_origin, const long *rec_off, int nrec,
+// unpadded computational grid <-> padded layout
+struct PadMap {
+    long nx, ny, nz;        // computational dims (ny = 1 in 2D)
+    long sx, sy;            // padded strides
+    long origin;
+};
+void launch_coef(const float *m, float *b_padded, const PadMap &pm, double dt, hipStream_t st);
+void launch_unpad(const float *acc_padded, float *g, const PadMap &pm, hipStream_t st);
+void launch_probe(const float *a, const float *b, const float *c, float *d, size_t n, int nsrc,
+                  hipStream_t st);
+void launch_gather(const float *field_origin, const int *rec_off, int nrec,
                    float *out_row, hipStream_t st);
 void launch_residual(const float *d_sim, const float *d_obs, float *res,
                      size_t n, double *partials, int nparts, double *phi,
                      hipStream_t st);
 
-// adjoint receiver injection at unique nodes (CSR over receivers)
+// adjoint receiver injection at unique nodes (CSR over receivers); field
+// pointers are allocation bases of padded arrays
 struct InjectParams {
-    float *lam;             // new adjoint level, padded, at origin
-    float *g;               // unpadded gradient
-    const float *uk;        // forward state, padded, at origin
-    const float *b;         // unpadded
+    float *lam;             // new adjoint level
+    float *g;               // gradient accumulator
+    const float *uk;        // forward state
+    const float *b;
     const float *res_row;   // residual row of this step (nrec)
-    const long *node_pad;   // padded offset of unique node j
-    const long *node_unp;   // unpadded offset
+    const int *node_pad;    // padded offset (from the base) of unique node j
     const int *node_xyz;    // 3 ints per node (computational coords)
     const int *rec_ptr;     // CSR: receivers of node j = rec_idx[rec_ptr[j]..rec_ptr[j+1])
     const int *rec_idx;

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -83,8 +84,9 @@ struct fwi_ctx {
     int device = 0;
     size_t pool_default = 0;
     DevBuf<unsigned char> pool;
-    // working fields (padded) and coefficient b = dt^2/m (unpadded)
-    DevBuf<float> fa, fb, la, lb, coef;
+    // working fields, coefficient b = dt^2/m and gradient accumulator, all
+    // in the padded layout
+    DevBuf<float> fa, fb, la, lb, coef, gacc;
     size_t padded_elems = 0;
     // codec scratch
     DevBuf<unsigned long long> scratch, chunk_bits, chunk_off, misc;
@@ -92,11 +94,12 @@ struct fwi_ctx {
     DevBuf<unsigned int> flags;
     DevBuf<double> partials, phi;
     // receivers
-    DevBuf<long> rec_off, node_pad, node_unp;
+    DevBuf<int> rec_off, node_pad;
     DevBuf<int> node_xyz, rec_ptr, rec_idx;
     DevBuf<float> dsim, res;
     // timing
     bool timing = false;
+    int xchunk3 = 0;           // 3D stencil x planes per workgroup (0: automatic)
     fwi_stats stats{};
     std::vector<hipEvent_t> evpool;
     size_t evused = 0;
@@ -127,6 +130,7 @@ struct fwi_tape {
     const float *m = nullptr;
     fwi_ckpt_cfg cfg{};
     std::vector<fwi_action> acts;
+    std::vector<char> both, slot_both;
     size_t next = 0;
     DevBuf<unsigned char> pool;
     DevBuf<StreamSlot> slots;
@@ -141,15 +145,15 @@ struct Setup {
     int ndim = 0, R = 0, nt = 0, nbl = 0;
     int comp[3] = {1, 1, 1};
     Padded pad;
-    long usx = 0, usy = 0;
+    long usx = 0, usy = 0;          // strides of the unpadded computational grid
     size_t ncomp = 0;
     double dt = 0, h = 0;
     float w[9] = {0};
     float kappa = 0, inv_dt2 = 0;
-    long src_unp = -1;
+    long src_pad = -1;              // origin-relative padded offset of the source
     int nrec = 0;
-    std::vector<long> rec_pad;
-    std::vector<long> node_pad, node_unp;
+    std::vector<int> rec_pad;       // base-relative padded offsets of the receivers
+    std::vector<int> node_pad;
     std::vector<int> node_xyz, rec_ptr, rec_idx;
 };
 
@@ -210,6 +214,8 @@ Setup make_setup(const fwi_grid *g, const fwi_shot *shot, bool need_src)
     s.h = g->h;
     for (int d = 0; d < g->ndim; ++d) s.comp[d] = g->n[d] + 2 * g->nbl;
     s.pad = make_padded(g->ndim, s.comp);
+    if (s.pad.elems() >= ((size_t)1 << 30))
+        throw Error{FWI_EINVAL, "grid too large: a padded field must hold fewer than 2^30 points"};
     const int nx = s.pad.nx, ny = s.pad.ny, nz = s.pad.nz;
     s.ncomp = (size_t)nx * ny * nz;
     s.usx = (long)ny * nz;
@@ -237,7 +243,7 @@ Setup make_setup(const fwi_grid *g, const fwi_shot *shot, bool need_src)
         if (!inside(shot->src)) throw Error{FWI_EINVAL, "source outside the physical grid"};
         int c[3];
         coords(shot->src, c);
-        s.src_unp = (long)c[0] * s.usx + (long)c[1] * s.usy + c[2];
+        s.src_pad = (long)c[0] * s.pad.sx + (long)c[1] * s.pad.sy + c[2];
     }
     if (shot->nrec < 0) throw Error{FWI_EINVAL, "nrec must be >= 0"};
     if (shot->nrec > 0 && !shot->rec) throw Error{FWI_EINVAL, "receiver list is null"};
@@ -249,15 +255,14 @@ Setup make_setup(const fwi_grid *g, const fwi_shot *shot, bool need_src)
         if (!inside(p)) throw Error{FWI_EINVAL, "receiver " + std::to_string(r) + " outside the physical grid"};
         int c[3];
         coords(p, c);
-        s.rec_pad[r] = (long)c[0] * s.pad.sx + (long)c[1] * s.pad.sy + c[2];
+        s.rec_pad[r] = (int)(s.pad.origin + (long)c[0] * s.pad.sx + (long)c[1] * s.pad.sy + c[2]);
         nodes[(long)c[0] * s.usx + (long)c[1] * s.usy + c[2]].push_back(r);
     }
     s.rec_ptr.push_back(0);
     for (auto &kv : nodes) {
         const long u = kv.first;
         const int cx = (int)(u / s.usx), cy = (int)((u / s.usy) % ny), cz = (int)(u % nz);
-        s.node_unp.push_back(u);
-        s.node_pad.push_back((long)cx * s.pad.sx + (long)cy * s.pad.sy + cz);
+        s.node_pad.push_back((int)(s.pad.origin + (long)cx * s.pad.sx + (long)cy * s.pad.sy + cz));
         s.node_xyz.push_back(cx);
         s.node_xyz.push_back(cy);
         s.node_xyz.push_back(cz);
@@ -279,13 +284,15 @@ void ensure_fields(fwi_ctx *c, const Setup &s)
     const size_t pe = s.pad.elems();
     if (pe != c->padded_elems) {
         c->fa.release(); c->fb.release(); c->la.release(); c->lb.release();
+        c->coef.release(); c->gacc.release();
         c->fa.ensure(pe, true);
         c->fb.ensure(pe, true);
         c->la.ensure(pe, true);
         c->lb.ensure(pe, true);
+        c->coef.ensure(pe, true);
+        c->gacc.ensure(pe, true);
         c->padded_elems = pe;
     }
-    c->coef.ensure(s.ncomp);
 }
 
 FieldView padded_view(const Setup &s)
@@ -393,15 +400,29 @@ struct Exec {
     size_t pool_cap = 0;
     StreamSlot *slots = nullptr;
     size_t raw_bytes = 0;            // uncompressed: bytes of one padded level
+    std::vector<char> slot_both;     // slot holds both levels
 
-    float *origin(float *base) const { return base + S.pad.origin; }
-    float *W0() const { return origin(c->fa.p); }
-    float *W1() const { return origin(c->fb.p); }
+    // cur/prev/l1/l2 are allocation bases of padded arrays
+    float *at_origin(float *base) const { return base + S.pad.origin; }
+    float *W0() const { return c->fa.p; }
+    float *W1() const { return c->fb.p; }
     bool in_w(const float *p) const { return p == W0() || p == W1(); }
+
+    PadMap padmap() const
+    {
+        PadMap pm;
+        pm.nx = S.pad.nx;
+        pm.ny = S.pad.ny;
+        pm.nz = S.pad.nz;
+        pm.sx = S.pad.sx;
+        pm.sy = S.ndim == 3 ? S.pad.sy : 0;
+        pm.origin = S.pad.origin;
+        return pm;
+    }
 
     void init_fields()
     {
-        launch_coef(m, c->coef.p, S.ncomp, S.dt, st);
+        launch_coef(m, c->coef.p, padmap(), S.dt, st);
         HIPCHK(hipMemsetAsync(c->fa.p, 0, c->padded_elems * sizeof(float), st));
         HIPCHK(hipMemsetAsync(c->fb.p, 0, c->padded_elems * sizeof(float), st));
         cur = W0();
@@ -414,11 +435,10 @@ struct Exec {
     {
         HIPCHK(hipMemsetAsync(c->la.p, 0, c->padded_elems * sizeof(float), st));
         HIPCHK(hipMemsetAsync(c->lb.p, 0, c->padded_elems * sizeof(float), st));
-        l1 = origin(c->la.p);
-        l2 = origin(c->lb.p);
-        HIPCHK(hipMemsetAsync(grad, 0, S.ncomp * sizeof(float), st));
+        l1 = c->la.p;
+        l2 = c->lb.p;
+        HIPCHK(hipMemsetAsync(c->gacc.p, 0, c->padded_elems * sizeof(float), st));
         upload(c->node_pad, S.node_pad, st);
-        upload(c->node_unp, S.node_unp, st);
         upload(c->node_xyz, S.node_xyz, st);
         upload(c->rec_ptr, S.rec_ptr, st);
         upload(c->rec_idx, S.rec_idx, st);
@@ -430,8 +450,7 @@ struct Exec {
         p.b = c->coef.p;
         p.psx = S.pad.sx;
         p.psy = S.ndim == 3 ? S.pad.sy : 0;
-        p.sx = S.usx;
-        p.sy = S.ndim == 3 ? S.usy : 0;
+        p.origin = S.pad.origin;
         p.nx = S.pad.nx;
         p.ny = S.pad.ny;
         p.nz = S.pad.nz;
@@ -440,7 +459,15 @@ struct Exec {
         p.inv_dt2 = S.inv_dt2;
         for (int k = 0; k < 9; ++k) p.w[k] = S.w[k];
         p.src = -1;
-        p.xchunk = S.ndim == 3 ? 32 : 16;
+        if (S.ndim == 3) {
+            // short x chunks: many workgroups in flight; the 2R halo planes
+            // re-read per chunk come from L2
+            int xc = 32;
+            if (c->xchunk3 > 0) xc = c->xchunk3;
+            p.xchunk = std::max(xc, std::min(16, S.pad.nx));
+        } else {
+            p.xchunk = 16;
+        }
         return p;
     }
 
@@ -450,44 +477,62 @@ struct Exec {
         if (!prev_valid) throw Error{FWI_EINVAL, "internal: advance without the older level"};
         Timer tm(c, st, K_FWD);
         StepParams p = params();
-        p.src = S.src_unp;
+        p.src = S.src_pad;
         p.wav = shot->wavelet;
+        p.rec_off = c->rec_off.p;
+        p.nrec = S.nrec;
         for (int k = a + 1; k <= b; ++k) {
             float *out = in_w(prev) ? prev : (cur == W0() ? W1() : W0());
             p.u1 = cur;
             p.u2 = prev;
             p.out = out;
             p.step = k - 1;
+            // the launch samples the level it reads, u^{k-1}, on first visit
+            p.grow = nullptr;
+            if (record && k - 1 >= 1 && k - 1 > reached) {
+                p.grow = dsim + (size_t)(k - 2) * S.nrec;
+                reached = k - 1;
+            }
             launch_step(p, S.ndim, S.R, false, st);
             prev = cur;
             cur = out;
-            if (record && k > reached) {
-                launch_gather(cur, c->rec_off.p, S.nrec, dsim + (size_t)(k - 1) * S.nrec, st);
-                reached = k;
-            }
         }
         c->stats.n_forward += b - a;
         work = b;
     }
 
-    void takeshot(int slot, int k)
+    // sample the working level if the first sweep has not recorded it yet
+    void flush_record()
+    {
+        if (dsim && work >= 1 && work > reached) {
+            launch_gather(cur, c->rec_off.p, S.nrec, dsim + (size_t)(work - 1) * S.nrec, st);
+            reached = work;
+        }
+    }
+
+    // store x_k; the older level only when the schedule will advance from it
+    void takeshot(int slot, int k, bool both)
     {
         if (work != k) throw Error{FWI_EINVAL, "internal: takeshot of a state not held"};
-        c->stats.ckpt_raw_bytes += 2LL * (long long)S.ncomp * 4;
+        if ((int)slot_both.size() <= slot) slot_both.resize(slot + 1, 0);
+        slot_both[slot] = both;
+        const int levels = both ? 2 : 1;
+        c->stats.ckpt_raw_bytes += (long long)levels * (long long)S.ncomp * 4;
         if (!compress) {
             const size_t off = (size_t)(2 * slot) * raw_bytes;
-            HIPCHK(hipMemcpyAsync(pool + off, cur - S.pad.origin, raw_bytes, hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(pool + off + raw_bytes, prev - S.pad.origin, raw_bytes,
-                                  hipMemcpyDeviceToDevice, st));
-            c->stats.ckpt_bytes += 2LL * (long long)raw_bytes;
-            c->stats.pool_high = std::max<long long>(c->stats.pool_high, (long long)(off + 2 * raw_bytes));
+            HIPCHK(hipMemcpyAsync(pool + off, cur, raw_bytes, hipMemcpyDeviceToDevice, st));
+            if (both)
+                HIPCHK(hipMemcpyAsync(pool + off + raw_bytes, prev, raw_bytes, hipMemcpyDeviceToDevice, st));
+            c->stats.ckpt_bytes += (long long)levels * (long long)raw_bytes;
+            c->stats.pool_high = std::max<long long>(c->stats.pool_high,
+                                                     (long long)(off + (size_t)levels * raw_bytes));
             return;
         }
-        for (int lev = 0; lev < 2; ++lev) {
+        for (int lev = 0; lev < levels; ++lev) {
             Timer tm(c, st, K_ENC);
             EncodeArgs e{};
             e.f = padded_view(S);
-            e.src = lev == 0 ? cur : prev;
+            e.src = at_origin(lev == 0 ? cur : prev);
             e.atol = atol;
             e.scratch = c->scratch.p;
             e.chunk_bits = c->chunk_bits.p;
@@ -497,7 +542,9 @@ struct Exec {
             e.pool_cap = pool_cap;
             e.slots = slots;
             e.slot_index = 2 * slot + lev;
-            e.prev_index = lev == 1 ? 2 * slot : (slot == 0 ? -1 : 2 * slot - 1);
+            // streams are stacked: this one starts after the last stream of
+            // the slot below (or after level 0 of this slot)
+            e.prev_index = lev == 1 ? 2 * slot : (slot == 0 ? -1 : 2 * (slot - 1) + (slot_both[slot - 1] ? 1 : 0));
             e.out_bytes = c->misc.p + 0;
             e.pool_high = c->misc.p + 1;
             e.total_bytes = c->misc.p + 2;
@@ -517,15 +564,15 @@ struct Exec {
             prev_valid = true;
         } else if (!compress) {
             const size_t off = (size_t)(2 * slot) * raw_bytes;
-            cur = origin((float *)(pool + off));
-            prev = origin((float *)(pool + off + raw_bytes));
-            prev_valid = true;
+            cur = (float *)(pool + off);
+            prev = (float *)(pool + off + raw_bytes);
+            prev_valid = slot < (int)slot_both.size() && slot_both[slot];
         } else {
             for (int lev = 0; lev < (only_cur ? 1 : 2); ++lev) {
                 Timer tm(c, st, K_DEC);
                 DecodeArgs d{};
                 d.f = padded_view(S);
-                d.dst = lev == 0 ? W0() : W1();
+                d.dst = at_origin(lev == 0 ? W0() : W1());
                 d.stream = nullptr;
                 d.pool = pool;
                 d.slots = slots;
@@ -545,6 +592,7 @@ struct Exec {
     {
         if (work != k) throw Error{FWI_EINVAL, "internal: reverse without its state"};
         if (!adj_src) {
+            flush_record();
             const size_t n = (size_t)S.nt * S.nrec;
             launch_residual(dsim, d_obs, c->res.p, n, c->partials.p, (int)c->partials.n, c->phi.p, st);
             adj_src = c->res.p;
@@ -555,20 +603,19 @@ struct Exec {
         p.u2 = l2;
         p.out = l2;
         p.uk = cur;
-        p.g = grad;
+        p.g = c->gacc.p;
         launch_step(p, S.ndim, S.R, true, st);
         InjectParams ip{};
         ip.lam = l2;
-        ip.g = grad;
+        ip.g = c->gacc.p;
         ip.uk = cur;
         ip.b = c->coef.p;
         ip.res_row = adj_src + (size_t)(k - 1) * S.nrec;
         ip.node_pad = c->node_pad.p;
-        ip.node_unp = c->node_unp.p;
         ip.node_xyz = c->node_xyz.p;
         ip.rec_ptr = c->rec_ptr.p;
         ip.rec_idx = c->rec_idx.p;
-        ip.nnode = (int)S.node_unp.size();
+        ip.nnode = (int)S.node_pad.size();
         ip.nx = S.pad.nx;
         ip.ny = S.pad.ny;
         ip.nz = S.pad.nz;
@@ -582,21 +629,25 @@ struct Exec {
     }
 
     // run acts[from, to); stops before the first REVERSE if stop_at_reverse
-    size_t run(const std::vector<fwi_action> &acts, size_t from, bool stop_at_reverse)
+    size_t run(const std::vector<fwi_action> &acts, const std::vector<char> &both, size_t from,
+               bool stop_at_reverse)
     {
         size_t i = from;
         for (; i < acts.size(); ++i) {
             const fwi_action &a = acts[i];
             switch (a.op) {
             case FWI_ADVANCE: advance(a.a, a.b, true); break;
-            case FWI_TAKESHOT: takeshot(a.a, a.b); break;
+            case FWI_TAKESHOT: takeshot(a.a, a.b, both[i] != 0); break;
             case FWI_RESTORE: {
                 const bool only = compress && i + 1 < acts.size() && acts[i + 1].op == FWI_REVERSE;
                 restore(a.a, a.b, only);
                 break;
             }
             case FWI_REVERSE:
-                if (stop_at_reverse) return i;
+                if (stop_at_reverse) {
+                    flush_record();
+                    return i;
+                }
                 reverse(a.a);
                 break;
             case FWI_FREE: break;
@@ -613,6 +664,25 @@ const std::vector<fwi_action> &plan_for(fwi_ctx *c, int nt, int nslots)
     auto it = c->plans.find(key);
     if (it == c->plans.end()) it = c->plans.emplace(key, revolve_plan(nt, nslots)).first;
     return it->second;
+}
+
+// flag each TAKESHOT whose state is later restored and advanced from (only
+// those need the older leapfrog level; the others serve one reverse step)
+std::vector<char> restart_flags(const std::vector<fwi_action> &acts)
+{
+    std::vector<char> both(acts.size(), 0);
+    std::vector<size_t> open;   // action index of the takeshot in each slot
+    for (size_t i = 0; i < acts.size(); ++i) {
+        const fwi_action &a = acts[i];
+        if (a.op == FWI_TAKESHOT) {
+            if ((int)open.size() <= a.a) open.resize(a.a + 1);
+            open[a.a] = i;
+        } else if (a.op == FWI_RESTORE && a.a >= 0 && i + 1 < acts.size() &&
+                   acts[i + 1].op == FWI_ADVANCE) {
+            both[open[a.a]] = 1;
+        }
+    }
+    return both;
 }
 
 void check_cfg(const fwi_ckpt_cfg *cfg)
@@ -705,6 +775,7 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         fwi_ctx *c = new fwi_ctx();
         c->device = device;
         c->pool_default = pool_bytes;
+        if (const char *e = std::getenv("FWI_XCHUNK")) c->xchunk3 = std::atoi(e);
         *ctx = c;
     });
 }
@@ -721,7 +792,7 @@ int fwi_ctx_destroy(fwi_ctx *c)
         c->pool.release(); c->fa.release(); c->fb.release(); c->la.release(); c->lb.release();
         c->coef.release(); c->scratch.release(); c->chunk_bits.release(); c->chunk_off.release();
         c->misc.release(); c->slots.release(); c->flags.release(); c->partials.release();
-        c->phi.release(); c->rec_off.release(); c->node_pad.release(); c->node_unp.release();
+        c->phi.release(); c->rec_off.release(); c->node_pad.release(); c->gacc.release();
         c->node_xyz.release(); c->rec_ptr.release(); c->rec_idx.release(); c->dsim.release();
         c->res.release();
         delete c;
@@ -755,6 +826,7 @@ int fwi_forward(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *s
         ex.dsim = d_sim;
         ex.init_fields();
         ex.advance(0, ex.S.nt, true);
+        ex.flush_record();
         HIPCHK(hipGetLastError());
         end_call(c, st);
     });
@@ -790,7 +862,8 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         ex.grad = grad;
         ex.init_fields();
         ex.init_adjoint();
-        ex.run(acts, 0, false);
+        ex.run(acts, restart_flags(acts), 0, false);
+        launch_unpad(c->gacc.p, grad, ex.padmap(), st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(phi, c->phi.p, sizeof(double), hipMemcpyDeviceToHost, st));
         finish_status(c, st);
@@ -827,12 +900,14 @@ int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_sh
             setup_ckpt(ex, cfg, t->pool.p, cap, t->slots.p, used);
             ex.dsim = d_sim;
             ex.init_fields();
-            t->next = ex.run(t->acts, 0, true);
+            t->both = restart_flags(t->acts);
+            t->next = ex.run(t->acts, t->both, 0, true);
+            t->slot_both = ex.slot_both;
             t->xcur.ensure(c->padded_elems);
             t->xprev.ensure(c->padded_elems);
-            HIPCHK(hipMemcpyAsync(t->xcur.p, ex.cur - ex.S.pad.origin, c->padded_elems * sizeof(float),
+            HIPCHK(hipMemcpyAsync(t->xcur.p, ex.cur, c->padded_elems * sizeof(float),
                                   hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(t->xprev.p, ex.prev - ex.S.pad.origin, c->padded_elems * sizeof(float),
+            HIPCHK(hipMemcpyAsync(t->xprev.p, ex.prev, c->padded_elems * sizeof(float),
                                   hipMemcpyDeviceToDevice, st));
             HIPCHK(hipGetLastError());
             finish_status(c, st);
@@ -864,11 +939,13 @@ int fwi_backward(fwi_ctx *c, fwi_tape *t, const float *dd, float *grad, hipStrea
         ex.adj_src = dd;
         ex.init_fields();
         ex.init_adjoint();
-        ex.cur = t->xcur.p + ex.S.pad.origin;
-        ex.prev = t->xprev.p + ex.S.pad.origin;
+        ex.cur = t->xcur.p;
+        ex.prev = t->xprev.p;
         ex.work = t->grid.nt;
         ex.reached = t->grid.nt;
-        ex.run(t->acts, t->next, false);
+        ex.slot_both = t->slot_both;
+        ex.run(t->acts, t->both, t->next, false);
+        launch_unpad(c->gacc.p, grad, ex.padmap(), st);
         HIPCHK(hipGetLastError());
         finish_status(c, st);
         t->used = true;
@@ -995,6 +1072,17 @@ int ckpt_decompress(fwi_ctx *c, const void *stream, size_t nbytes, float *field,
         finish_status(c, st);
         c->stats.n_decode = 1;
         end_call(c, st);
+    });
+}
+
+int fwi_bandwidth_probe(const float *a, const float *b, const float *c, float *d, size_t n, int nsrc,
+                        hipStream_t st)
+{
+    return guarded([&] {
+        if (!a || !d || (nsrc == 3 && (!b || !c)) || (nsrc != 1 && nsrc != 3))
+            throw Error{FWI_EINVAL, "bad arguments"};
+        launch_probe(a, b, c, d, n, nsrc, st);
+        HIPCHK(hipGetLastError());
     });
 }
 

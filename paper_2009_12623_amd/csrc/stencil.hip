@@ -8,13 +8,20 @@
 // lam^{k+1}, lam^{k+2} adjoint).  The adjoint variant also accumulates
 //   g -= u^k (out - 2 c + u2) / dt^2.
 //
-// Work split: a workgroup owns a (y, z) tile (64 z = one wave, TILE_Y waves
-// along y; 256 z in 2D) and streams a chunk of x planes.  Each lane keeps the
-// 2R+1 x-neighbours of its column in registers; the y and z neighbours of
-// the current plane come from an LDS tile whose centre is written from the
-// register queue, so global loads per point and step are one new x plane
-// value plus the halo ring.  Fields are padded (see internal.hpp), so no
-// load needs a bounds check; lanes outside the grid compute nothing.
+// Layout: every array a step touches (the levels, b, u^k, the gradient
+// accumulator) shares one padded layout whose interior rows start on
+// 128-byte L2 lines, and is addressed by 32-bit byte offsets from the
+// allocation base (one scalar base + one vector offset per load).
+//
+// Work split: a workgroup owns a (y, z) tile and streams a chunk of x planes.
+// Each lane keeps the 2R+1 x-neighbours of its column(s) in registers; the
+// y and z neighbours of the current plane come from a double-buffered LDS
+// tile whose centre is written from the register queue.  The loads of plane
+// x+1 (queue value, halo ring, u2, b, and for the adjoint u^k and g) are
+// issued before plane x is computed, and one barrier closes each plane.
+// Lanes outside the grid compute nothing.  Extra workgroups at the end of a
+// forward launch sample the receivers from the level the launch reads
+// (u^{k-1}), so the first sweep needs no separate gather launch.
 #include "internal.hpp"
 
 namespace fwi {
@@ -29,120 +36,303 @@ __device__ __forceinline__ int layer_depth(int i, int n, int nbl)
     return d > 0 ? d : 0;
 }
 
-template <int R, bool ADJ>
-__device__ __forceinline__ void finish_point(const StepParams &p, int x, int y, int z,
-                                             long pi, float c, float lap)
+// load/store through a base pointer and an unsigned byte offset
+__device__ __forceinline__ float ld(const float *base, unsigned off)
 {
-    const long ui = (long)x * p.sx + (long)y * p.sy + z;
-    const float bb = p.b[ui];
-    const float u2v = p.u2[pi];
-    const int dx = layer_depth(x, p.nx, p.nbl);
-    const int dy = p.ny > 1 ? layer_depth(y, p.ny, p.nbl) : 0;
-    const int dz = layer_depth(z, p.nz, p.nbl);
-    const int dsum = dx * dx + dy * dy + dz * dz;
-    float num;
+    return *(const float *)((const char *)base + off);
+}
+
+__device__ __forceinline__ float ldnt(const float *base, unsigned off)
+{
+    return __builtin_nontemporal_load((const float *)((const char *)base + off));
+}
+
+__device__ __forceinline__ void st(float *base, unsigned off, float v)
+{
+    *(float *)((char *)base + off) = v;
+}
+
+// new level from the Laplacian and the point values
+template <bool ADJ>
+__device__ __forceinline__ float update(const StepParams &p, int dsum, bool is_src, float c,
+                                        float lap, float u2v, float bb)
+{
     float outv;
     if (dsum == 0) {
-        num = 2.0f * c + bb * lap - u2v;
-        if (!ADJ && ui == p.src) num += bb * p.wav[p.step];
+        float num = 2.0f * c + bb * lap - u2v;
+        if (!ADJ && is_src) num += bb * p.wav[p.step];
         outv = num;
     } else {
         const float e = p.kappa * bb * (float)dsum;
-        num = 2.0f * c + bb * lap - (1.0f - e) * u2v;
-        if (!ADJ && ui == p.src) num += bb * p.wav[p.step];
+        float num = 2.0f * c + bb * lap - (1.0f - e) * u2v;
+        if (!ADJ && is_src) num += bb * p.wav[p.step];
         outv = num / (1.0f + e);
     }
-    p.out[pi] = outv;
-    if (ADJ) {
-        const float ukv = p.uk[pi];
-        p.g[ui] -= ukv * (outv - 2.0f * c + u2v) * p.inv_dt2;
-    }
+    return outv;
+}
+
+__device__ __forceinline__ void gather_block(const StepParams &p, int blk)
+{
+    const int j = blk * (int)(blockDim.x * blockDim.y) + (int)(threadIdx.y * blockDim.x + threadIdx.x);
+    if (j < p.nrec) p.grow[j] = ld(p.u1, 4u * (unsigned)p.rec_off[j]);
+}
+
+// ------------------------------------------------------------------- 3D
+// Workgroup = 64 (z) x 8 (y) lanes; each lane owns two rows of a 64 x 16
+// (z, y) tile.  Tiles are numbered z fastest, then y, then x chunk, and
+// handed out so that each XCD (workgroups are dealt to the 8 XCDs round
+// robin) works on one contiguous range, keeping halo reuse inside its L2.
+// Read-once streams (u2, b, u^k, g) use non-temporal loads.
+constexpr int T3_ROWS = 16;
+
+__device__ __forceinline__ void tile_coords(int hw, int nwg, int ntz, int nty, int &tzi, int &tyi,
+                                            int &txi, bool &valid)
+{
+    const int per = (nwg + 7) >> 3;
+    const int logical = (hw & 7) * per + (hw >> 3);
+    valid = logical < nwg;
+    tzi = logical % ntz;
+    const int rest = logical / ntz;
+    tyi = rest % nty;
+    txi = rest / nty;
 }
 
 template <int R, bool ADJ>
-__global__ __launch_bounds__(TILE_Z *TILE_Y)
-void step3d_kernel(StepParams p)
+__global__ __launch_bounds__(TILE_Z * 8)
+void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
 {
-    __shared__ float tile[TILE_Y + 2 * R][TILE_Z + 2 * R];
+    __shared__ float tile[2][T3_ROWS + 2 * R][TILE_Z + 2 * R];
+    const int hw = blockIdx.x;
+    if (hw >= launched) {                          // receiver sampling blocks
+        gather_block(p, hw - launched);
+        return;
+    }
+    int tzi, tyi, txi;
+    bool valid;
+    tile_coords(hw, nwg, ntz, nty, tzi, tyi, txi, valid);
+    if (!valid) return;                            // whole workgroup, before any barrier
+
     const int tz = threadIdx.x;
     const int ty = threadIdx.y;
-    const int z0 = blockIdx.x * TILE_Z;
-    const int y0 = blockIdx.y * TILE_Y;
+    const int z0 = tzi * TILE_Z;
+    const int y0 = tyi * T3_ROWS;
     const int z = z0 + tz;
-    const int y = y0 + ty;
-    const int xb = blockIdx.z * p.xchunk;
-    int xe = xb + p.xchunk;
-    if (xe > p.nx) xe = p.nx;
-    const bool active = z < p.nz && y < p.ny;
-    const float *col = p.u1 + (long)y * p.psy + z;
+    const int ya = y0 + ty;
+    const int yb = ya + 8;
+    const int xb = txi * p.xchunk;
+    const int xe = min(xb + p.xchunk, p.nx);
+    const bool zin = z < p.nz;
+    const bool act_a = zin && ya < p.ny;
+    const bool act_b = zin && yb < p.ny;
+    // byte strides and offsets (unsigned arithmetic; every result is in range)
+    const unsigned bsx = 4u * (unsigned)p.psx, bsy = 4u * (unsigned)p.psy;
+    const unsigned org = 4u * (unsigned)p.origin;
+    const unsigned srcb = p.src >= 0 ? org + 4u * (unsigned)p.src : 0xFFFFFFFFu;
+    const float *__restrict__ u1 = p.u1;
+    const float *__restrict__ u2 = p.u2;
+    const float *__restrict__ bq = p.b;
+    const bool hy = ty < R;
+    const unsigned hy_top = org + (unsigned)(y0 - R + ty) * bsy + 4u * z;
+    const unsigned hy_bot = org + (unsigned)(y0 + T3_ROWS + ty) * bsy + 4u * z;
+    const bool hzl = tz < R, hzr = tz >= TILE_Z - R;
+    const bool hz = hzl || hzr;
+    const unsigned hz_off = 4u * (unsigned)(hzl ? (z0 - R + tz) : (z + R));
+    const unsigned hza = org + (unsigned)ya * bsy + hz_off;
+    const unsigned hzb = org + (unsigned)yb * bsy + hz_off;
+    const int hcol = hzl ? tz : tz + 2 * R;
+    const unsigned cola = org + (unsigned)ya * bsy + 4u * z;
+    const unsigned colb = cola + 8u * bsy;
+    const int dy_a = layer_depth(ya, p.ny, p.nbl), dy_b = layer_depth(yb, p.ny, p.nbl);
+    const int dz = layer_depth(z, p.nz, p.nbl);
+    const int dyz_a = dy_a * dy_a + dz * dz, dyz_b = dy_b * dy_b + dz * dz;
 
-    float q[2 * R + 1];
+    float qa[2 * R + 1], qb[2 * R + 1];
 #pragma unroll
-    for (int i = 0; i < 2 * R; ++i) q[i + 1] = col[(long)(xb - R + i) * p.psx];
+    for (int i = 0; i <= 2 * R; ++i) {
+        qa[i] = ld(u1, cola + (unsigned)(xb - R + i) * bsx);
+        qb[i] = ld(u1, colb + (unsigned)(xb - R + i) * bsx);
+    }
+    {
+        const unsigned pl = (unsigned)xb * bsx;
+        tile[0][ty + R][tz + R] = qa[R];
+        tile[0][ty + 8 + R][tz + R] = qb[R];
+        if (hy) {
+            tile[0][ty][tz + R] = ld(u1, pl + hy_top);
+            tile[0][ty + T3_ROWS + R][tz + R] = ld(u1, pl + hy_bot);
+        }
+        if (hz) {
+            tile[0][ty + R][hcol] = ld(u1, pl + hza);
+            tile[0][ty + 8 + R][hcol] = ld(u1, pl + hzb);
+        }
+    }
+    unsigned pa = cola + (unsigned)xb * bsx;           // row a; row b at + 8 rows
+    const unsigned boff = 8u * bsy;
+    float u2a = act_a ? ldnt(u2, pa) : 0.f, u2b = act_b ? ldnt(u2, pa + boff) : 0.f;
+    float ba = act_a ? ldnt(bq, pa) : 0.f, bbv = act_b ? ldnt(bq, pa + boff) : 0.f;
+    float uka = 0.f, ukb = 0.f, ga = 0.f, gb = 0.f;
+    if (ADJ) {
+        uka = act_a ? ldnt(p.uk, pa) : 0.f;
+        ukb = act_b ? ldnt(p.uk, pa + boff) : 0.f;
+        ga = act_a ? ldnt(p.g, pa) : 0.f;
+        gb = act_b ? ldnt(p.g, pa + boff) : 0.f;
+    }
+    __syncthreads();
 
     for (int x = xb; x < xe; ++x) {
-#pragma unroll
-        for (int i = 0; i < 2 * R; ++i) q[i] = q[i + 1];
-        q[2 * R] = col[(long)(x + R) * p.psx];
-        const float *plane = p.u1 + (long)x * p.psx;
-        __syncthreads();
-        tile[ty + R][tz + R] = q[R];
-        for (int r = ty; r < R; r += TILE_Y) {
-            tile[r][tz + R] = plane[(long)(y0 - R + r) * p.psy + z];
-            tile[r + TILE_Y + R][tz + R] = plane[(long)(y0 + TILE_Y + r) * p.psy + z];
+        const int cur = (x - xb) & 1;
+        const bool nxt = x + 1 < xe;
+        // ---- issue the loads of plane x+1 (halo first: needed soonest)
+        float nqa = 0.f, nqb = 0.f, nht = 0.f, nhb = 0.f, nza = 0.f, nzb = 0.f;
+        float nu2a = 0.f, nu2b = 0.f, nba = 0.f, nbb = 0.f, nuka = 0.f, nukb = 0.f, nga = 0.f, ngb = 0.f;
+        if (nxt) {
+            const unsigned pl = (unsigned)(x + 1) * bsx;
+            if (hy) {
+                nht = ld(u1, pl + hy_top);
+                nhb = ld(u1, pl + hy_bot);
+            }
+            if (hz) {
+                nza = ld(u1, pl + hza);
+                nzb = ld(u1, pl + hzb);
+            }
+            nqa = ld(u1, cola + pl + (unsigned)R * bsx);
+            nqb = ld(u1, colb + pl + (unsigned)R * bsx);
+            const unsigned na = pa + bsx;
+            if (act_a) {
+                nu2a = ldnt(u2, na);
+                nba = ldnt(bq, na);
+                if (ADJ) { nuka = ldnt(p.uk, na); nga = ldnt(p.g, na); }
+            }
+            if (act_b) {
+                nu2b = ldnt(u2, na + boff);
+                nbb = ldnt(bq, na + boff);
+                if (ADJ) { nukb = ldnt(p.uk, na + boff); ngb = ldnt(p.g, na + boff); }
+            }
         }
-        if (tz < R) tile[ty + R][tz] = plane[(long)y * p.psy + z0 - R + tz];
-        if (tz >= TILE_Z - R) tile[ty + R][tz + 2 * R] = plane[(long)y * p.psy + z + R];
-        __syncthreads();
-        if (active) {
-            const float c = q[R];
+        // ---- plane x
+        const int dx = layer_depth(x, p.nx, p.nbl);
+        if (act_a) {
+            const float c = qa[R];
             float lap = 3.0f * p.w[0] * c;
 #pragma unroll
             for (int k = 1; k <= R; ++k)
-                lap += p.w[k] * ((q[R - k] + q[R + k]) +
-                                 (tile[ty + R - k][tz + R] + tile[ty + R + k][tz + R]) +
-                                 (tile[ty + R][tz + R - k] + tile[ty + R][tz + R + k]));
-            finish_point<R, ADJ>(p, x, y, z, (long)x * p.psx + (long)y * p.psy + z, c, lap);
+                lap += p.w[k] * ((qa[R - k] + qa[R + k]) +
+                                 (tile[cur][ty + R - k][tz + R] + tile[cur][ty + R + k][tz + R]) +
+                                 (tile[cur][ty + R][tz + R - k] + tile[cur][ty + R][tz + R + k]));
+            const float o = update<ADJ>(p, dx * dx + dyz_a, pa == srcb, c, lap, u2a, ba);
+            st(p.out, pa, o);
+            if (ADJ) st(p.g, pa, ga - uka * (o - 2.0f * c + u2a) * p.inv_dt2);
         }
+        if (act_b) {
+            const float c = qb[R];
+            float lap = 3.0f * p.w[0] * c;
+#pragma unroll
+            for (int k = 1; k <= R; ++k)
+                lap += p.w[k] * ((qb[R - k] + qb[R + k]) +
+                                 (tile[cur][ty + 8 + R - k][tz + R] + tile[cur][ty + 8 + R + k][tz + R]) +
+                                 (tile[cur][ty + 8 + R][tz + R - k] + tile[cur][ty + 8 + R][tz + R + k]));
+            const float o = update<ADJ>(p, dx * dx + dyz_b, pa + boff == srcb, c, lap, u2b, bbv);
+            st(p.out, pa + boff, o);
+            if (ADJ) st(p.g, pa + boff, gb - ukb * (o - 2.0f * c + u2b) * p.inv_dt2);
+        }
+        if (!nxt) break;
+        // ---- advance the queues and stage plane x+1 in the other buffer
+#pragma unroll
+        for (int i = 0; i < 2 * R; ++i) {
+            qa[i] = qa[i + 1];
+            qb[i] = qb[i + 1];
+        }
+        qa[2 * R] = nqa;
+        qb[2 * R] = nqb;
+        const int nb = cur ^ 1;
+        tile[nb][ty + R][tz + R] = qa[R];
+        tile[nb][ty + 8 + R][tz + R] = qb[R];
+        if (hy) {
+            tile[nb][ty][tz + R] = nht;
+            tile[nb][ty + T3_ROWS + R][tz + R] = nhb;
+        }
+        if (hz) {
+            tile[nb][ty + R][hcol] = nza;
+            tile[nb][ty + 8 + R][hcol] = nzb;
+        }
+        u2a = nu2a; u2b = nu2b; ba = nba; bbv = nbb;
+        if (ADJ) { uka = nuka; ukb = nukb; ga = nga; gb = ngb; }
+        pa += bsx;
+        __syncthreads();
     }
 }
 
+// ------------------------------------------------------------------- 2D
+// Workgroup = 256 lanes along z, one row each, streaming x with the same
+// pipelining; the z neighbours come from a double-buffered LDS row.
 template <int R, bool ADJ>
 __global__ __launch_bounds__(TILE_Z2)
-void step2d_kernel(StepParams p)
+void step2d_kernel(StepParams p, int ntz, int nwg)
 {
-    __shared__ float row[TILE_Z2 + 2 * R];
+    __shared__ float row[2][TILE_Z2 + 2 * R];
+    const int hw = blockIdx.x;
+    if (hw >= nwg) {
+        gather_block(p, hw - nwg);
+        return;
+    }
+    const int tzi = hw % ntz;
+    const int txi = hw / ntz;
     const int tz = threadIdx.x;
-    const int z0 = blockIdx.x * TILE_Z2;
+    const int z0 = tzi * TILE_Z2;
     const int z = z0 + tz;
-    const int xb = blockIdx.z * p.xchunk;
-    int xe = xb + p.xchunk;
-    if (xe > p.nx) xe = p.nx;
-    const bool active = z < p.nz;
-    const float *col = p.u1 + z;
+    const int xb = txi * p.xchunk;
+    const int xe = min(xb + p.xchunk, p.nx);
+    const bool act = z < p.nz;
+    const unsigned bsx = 4u * (unsigned)p.psx, org = 4u * (unsigned)p.origin;
+    const unsigned srcb = p.src >= 0 ? org + 4u * (unsigned)p.src : 0xFFFFFFFFu;
+    const float *__restrict__ u1 = p.u1;
+    const bool hzl = tz < R, hzr = tz >= TILE_Z2 - R;
+    const unsigned hz_off = org + 4u * (unsigned)(hzl ? (z0 - R + tz) : (z + R));
+    const unsigned col = org + 4u * z;
+    const int dz = layer_depth(z, p.nz, p.nbl);
 
     float q[2 * R + 1];
 #pragma unroll
-    for (int i = 0; i < 2 * R; ++i) q[i + 1] = col[(long)(xb - R + i) * p.psx];
-
+    for (int i = 0; i <= 2 * R; ++i) q[i] = ld(u1, col + (unsigned)(xb - R + i) * bsx);
+    row[0][tz + R] = q[R];
+    if (hzl || hzr) row[0][hzl ? tz : tz + 2 * R] = ld(u1, (unsigned)xb * bsx + hz_off);
+    unsigned pa = col + (unsigned)xb * bsx;
+    float u2v = act ? ldnt(p.u2, pa) : 0.f, bb = act ? ldnt(p.b, pa) : 0.f, ukv = 0.f, gv = 0.f;
+    if (ADJ && act) { ukv = ldnt(p.uk, pa); gv = ldnt(p.g, pa); }
+    __syncthreads();
     for (int x = xb; x < xe; ++x) {
-#pragma unroll
-        for (int i = 0; i < 2 * R; ++i) q[i] = q[i + 1];
-        q[2 * R] = col[(long)(x + R) * p.psx];
-        const float *line = p.u1 + (long)x * p.psx;
-        __syncthreads();
-        row[tz + R] = q[R];
-        if (tz < R) row[tz] = line[z0 - R + tz];
-        if (tz >= TILE_Z2 - R) row[tz + 2 * R] = line[z + R];
-        __syncthreads();
-        if (active) {
+        const int cur = (x - xb) & 1;
+        const bool nxt = x + 1 < xe;
+        float nq = 0.f, nh = 0.f, nu2 = 0.f, nbv = 0.f, nuk = 0.f, ng = 0.f;
+        if (nxt) {
+            if (hzl || hzr) nh = ld(u1, (unsigned)(x + 1) * bsx + hz_off);
+            nq = ld(u1, col + (unsigned)(x + 1 + R) * bsx);
+            if (act) {
+                nu2 = ldnt(p.u2, pa + bsx);
+                nbv = ldnt(p.b, pa + bsx);
+                if (ADJ) { nuk = ldnt(p.uk, pa + bsx); ng = ldnt(p.g, pa + bsx); }
+            }
+        }
+        if (act) {
             const float c = q[R];
             float lap = 2.0f * p.w[0] * c;
 #pragma unroll
             for (int k = 1; k <= R; ++k)
-                lap += p.w[k] * ((q[R - k] + q[R + k]) + (row[tz + R - k] + row[tz + R + k]));
-            finish_point<R, ADJ>(p, x, 0, z, (long)x * p.psx + z, c, lap);
+                lap += p.w[k] * ((q[R - k] + q[R + k]) + (row[cur][tz + R - k] + row[cur][tz + R + k]));
+            const int dx = layer_depth(x, p.nx, p.nbl);
+            const float o = update<ADJ>(p, dx * dx + dz * dz, pa == srcb, c, lap, u2v, bb);
+            st(p.out, pa, o);
+            if (ADJ) st(p.g, pa, gv - ukv * (o - 2.0f * c + u2v) * p.inv_dt2);
         }
+        if (!nxt) break;
+#pragma unroll
+        for (int i = 0; i < 2 * R; ++i) q[i] = q[i + 1];
+        q[2 * R] = nq;
+        row[cur ^ 1][tz + R] = q[R];
+        if (hzl || hzr) row[cur ^ 1][hzl ? tz : tz + 2 * R] = nh;
+        u2v = nu2; bb = nbv;
+        if (ADJ) { ukv = nuk; gv = ng; }
+        pa += bsx;
+        __syncthreads();
     }
 }
 
@@ -150,24 +340,63 @@ template <int R, bool ADJ>
 void launch_r(const StepParams &p, int ndim, hipStream_t st)
 {
     const int nchunk = (p.nx + p.xchunk - 1) / p.xchunk;
+    const bool gather = !ADJ && p.grow && p.nrec > 0;
     if (ndim == 3) {
-        dim3 grid((p.nz + TILE_Z - 1) / TILE_Z, (p.ny + TILE_Y - 1) / TILE_Y, nchunk);
-        dim3 block(TILE_Z, TILE_Y, 1);
-        hipLaunchKernelGGL((step3d_kernel<R, ADJ>), grid, block, 0, st, p);
+        const int ntz = (p.nz + TILE_Z - 1) / TILE_Z;
+        const int nty = (p.ny + T3_ROWS - 1) / T3_ROWS;
+        const int nwg = ntz * nty * nchunk;
+        const int launched = ((nwg + 7) / 8) * 8;
+        const int ng = gather ? (p.nrec + 511) / 512 : 0;
+        hipLaunchKernelGGL((step3d_kernel<R, ADJ>), dim3(launched + ng), dim3(TILE_Z, 8, 1), 0, st,
+                           p, ntz, nty, nwg, launched);
     } else {
-        dim3 grid((p.nz + TILE_Z2 - 1) / TILE_Z2, 1, nchunk);
-        hipLaunchKernelGGL((step2d_kernel<R, ADJ>), grid, dim3(TILE_Z2), 0, st, p);
+        const int ntz = (p.nz + TILE_Z2 - 1) / TILE_Z2;
+        const int nwg = ntz * nchunk;
+        const int ng = gather ? (p.nrec + TILE_Z2 - 1) / TILE_Z2 : 0;
+        hipLaunchKernelGGL((step2d_kernel<R, ADJ>), dim3(nwg + ng), dim3(TILE_Z2), 0, st, p, ntz, nwg);
     }
 }
 
 // ------------------------------------------------------------- small kernels
-__global__ void coef_kernel(const float *m, float *b, size_t n, float dt2)
+// streams with the stencil's access width (one float per lane): dst = src
+// (nsrc = 1) or dst = src + src2 + src3 (nsrc = 3)
+__global__ __launch_bounds__(256) void probe_kernel(const float *__restrict__ a, const float *__restrict__ b,
+                                                    const float *__restrict__ c, float *__restrict__ d,
+                                                    size_t n, int nsrc)
 {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i < n; i += (size_t)gridDim.x * blockDim.x) b[i] = dt2 / m[i];
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t step = (size_t)gridDim.x * 256;
+    if (nsrc == 1)
+        for (; i < n; i += step) d[i] = a[i];
+    else
+        for (; i < n; i += step) d[i] = a[i] + b[i] + c[i];
 }
 
-__global__ void gather_kernel(const float *f, const long *off, int n, float *out)
+// b = dt^2/m from the unpadded model into the padded layout
+__global__ void coef_kernel(const float *m, float *b, PadMap pm, float dt2)
+{
+    const size_t n = (size_t)pm.nx * pm.ny * pm.nz;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t z = i % pm.nz, r = i / pm.nz;
+        const size_t y = r % pm.ny, x = r / pm.ny;
+        b[pm.origin + x * pm.sx + y * pm.sy + z] = dt2 / m[i];
+    }
+}
+
+// grad (unpadded) = accumulator (padded)
+__global__ void unpad_kernel(const float *acc, float *g, PadMap pm)
+{
+    const size_t n = (size_t)pm.nx * pm.ny * pm.nz;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t z = i % pm.nz, r = i / pm.nz;
+        const size_t y = r % pm.ny, x = r / pm.ny;
+        g[i] = acc[pm.origin + x * pm.sx + y * pm.sy + z];
+    }
+}
+
+__global__ void gather_kernel(const float *f, const int *off, int n, float *out)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = f[off[i]];
@@ -215,17 +444,16 @@ __global__ void inject_kernel(InjectParams p)
     if (j >= p.nnode) return;
     float s = 0.0f;
     for (int r = p.rec_ptr[j]; r < p.rec_ptr[j + 1]; ++r) s += p.res_row[p.rec_idx[r]];
-    const long pi = p.node_pad[j];
-    const long ui = p.node_unp[j];
+    const int pi = p.node_pad[j];
     const int x = p.node_xyz[3 * j], y = p.node_xyz[3 * j + 1], z = p.node_xyz[3 * j + 2];
     const int dx = layer_depth(x, p.nx, p.nbl);
     const int dy = p.ndim == 3 ? layer_depth(y, p.ny, p.nbl) : 0;
     const int dz = layer_depth(z, p.nz, p.nbl);
-    const float bb = p.b[ui];
+    const float bb = p.b[pi];
     const float e = p.kappa * bb * (float)(dx * dx + dy * dy + dz * dz);
     const float delta = bb * s / (1.0f + e);
     p.lam[pi] += delta;
-    p.g[ui] -= p.uk[pi] * delta * p.inv_dt2;
+    p.g[pi] -= p.uk[pi] * delta * p.inv_dt2;
 }
 
 }  // namespace
@@ -243,14 +471,31 @@ void launch_step(const StepParams &p, int ndim, int radius, bool adjoint, hipStr
     }
 }
 
-void launch_coef(const float *m, float *b, size_t n, double dt, hipStream_t st)
+static int grid_for(size_t n)
 {
-    int blocks = (int)((n + 255) / 256);
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(coef_kernel, dim3(blocks), dim3(256), 0, st, m, b, n, (float)(dt * dt));
+    size_t blocks = (n + 255) / 256;
+    return (int)(blocks > 65536 ? 65536 : blocks);
 }
 
-void launch_gather(const float *field, const long *off, int n, float *out, hipStream_t st)
+void launch_probe(const float *a, const float *b, const float *c, float *d, size_t n, int nsrc,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL(probe_kernel, dim3(256 * 32), dim3(256), 0, st, a, b, c, d, n, nsrc);
+}
+
+void launch_coef(const float *m, float *b, const PadMap &pm, double dt, hipStream_t st)
+{
+    hipLaunchKernelGGL(coef_kernel, dim3(grid_for((size_t)pm.nx * pm.ny * pm.nz)), dim3(256), 0, st, m, b,
+                       pm, (float)(dt * dt));
+}
+
+void launch_unpad(const float *acc, float *g, const PadMap &pm, hipStream_t st)
+{
+    hipLaunchKernelGGL(unpad_kernel, dim3(grid_for((size_t)pm.nx * pm.ny * pm.nz)), dim3(256), 0, st, acc,
+                       g, pm);
+}
+
+void launch_gather(const float *field, const int *off, int n, float *out, hipStream_t st)
 {
     if (n <= 0) return;
     hipLaunchKernelGGL(gather_kernel, dim3((n + 255) / 256), dim3(256), 0, st, field, off, n, out);
@@ -278,7 +523,7 @@ Padded make_padded(int ndim, const int *comp)
     f.nz = ndim == 3 ? comp[2] : comp[1];
     f.px = f.nx + 2 * PAD_X;
     const int tz = ndim == 3 ? TILE_Z : TILE_Z2;
-    f.pz = PAD_Z0 + (long)((f.nz + tz - 1) / tz) * tz + 16;
+    f.pz = PAD_Z0 + (long)((f.nz + tz - 1) / tz) * tz + PAD_Z0;
     if (ndim == 3) {
         f.py = (long)((f.ny + TILE_Y - 1) / TILE_Y) * TILE_Y + 2 * PAD_Y;
         f.origin = (long)PAD_X * f.py * f.pz + (long)PAD_Y * f.pz + PAD_Z0;

@@ -62,7 +62,7 @@ _lib = None
 EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_stats",
            "fwi_last_error", "fwi_forward", "fwi_gradient", "fwi_forward_ckpt",
            "fwi_backward", "fwi_tape_free", "ckpt_bound", "ckpt_compress",
-           "ckpt_decompress", "fwi_revolve_plan"]
+           "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe"]
 
 
 def lib():
@@ -94,6 +94,7 @@ def lib():
     L.ckpt_decompress.argtypes = [P, P, ctypes.c_size_t, P, I, ctypes.POINTER(ctypes.c_int), P]
     L.fwi_revolve_plan.argtypes = [I, I, ctypes.POINTER(fwi_action), I, ctypes.POINTER(I),
                                    ctypes.POINTER(ctypes.c_longlong)]
+    L.fwi_bandwidth_probe.argtypes = [P, P, P, P, ctypes.c_size_t, I, P]
     _lib = L
     return L
 
@@ -117,6 +118,11 @@ def _ptr(t):
     if not t.is_cuda or not t.is_contiguous():
         raise ValueError("expected a contiguous device tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def fwi_bandwidth_probe(a, d, b=None, c=None):
+    nsrc = 1 if b is None else 3
+    check(lib().fwi_bandwidth_probe(_ptr(a), _ptr(b), _ptr(c), _ptr(d), a.numel(), nsrc, _stream()))
 
 
 # ---------------------------------------------------------- host-only calls

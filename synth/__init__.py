@@ -228,20 +228,25 @@ def thrust_3d_torch(shape, device, nlayer=10, vmin=2200.0, vmax=6000.0, seed=126
 
 
 def gauss_smooth_torch(v, sigma, truncate=4.0):
-    """Separable Gaussian smoothing with edge replication (torch)."""
+    """Separable Gaussian smoothing with edge replication (torch): a weighted
+    sum of shifted copies along each axis."""
     import torch
-    import torch.nn.functional as Fn
     r = int(truncate * sigma + 0.5)
-    t = torch.arange(-r, r + 1, dtype=v.dtype, device=v.device)
+    t = torch.arange(-r, r + 1, dtype=torch.float64)
     w = torch.exp(-0.5 * (t / sigma) ** 2)
-    w = (w / w.sum()).view(1, 1, -1)
+    w = (w / w.sum()).tolist()
     out = v
     for ax in range(v.dim()):
-        moved = out.movedim(ax, -1)
-        shp = moved.shape
-        flat = moved.reshape(-1, 1, shp[-1])
-        flat = Fn.conv1d(Fn.pad(flat, (r, r), mode="replicate"), w)
-        out = flat.reshape(shp).movedim(-1, ax)
+        n = out.shape[ax]
+        first = out.narrow(ax, 0, 1)
+        last = out.narrow(ax, n - 1, 1)
+        padded = torch.cat([first.expand(*[r if d == ax else -1 for d in range(v.dim())]),
+                            out,
+                            last.expand(*[r if d == ax else -1 for d in range(v.dim())])], dim=ax)
+        acc = torch.zeros_like(out)
+        for k in range(2 * r + 1):
+            acc.add_(padded.narrow(ax, k, n), alpha=w[k])
+        out = acc
     return out.contiguous()
 
 

@@ -82,6 +82,23 @@ def test_gradient_matches_oracle(ctx, ndim, n, so, nbl, nt):
     assert abs(phi - phi_ref) <= 1e-4 * phi_ref
 
 
+@pytest.mark.parametrize("xchunk", [3, 7, 64])
+@pytest.mark.parametrize("so", [4, 8, 16])
+def test_3d_stencil_xchunks_match_oracle(xchunk, so, monkeypatch):
+    monkeypatch.setenv("FWI_XCHUNK", str(xchunk))
+    c = F.Context(0, pool_bytes=1 << 28)
+    shot = synth.tiny_shot(3, n=23, so=so, nbl=5, nt=35)
+    m0, mt, q = inputs(shot)
+    p0 = oracle_problem(shot, m0, q)
+    dobs = solver.forward(oracle_problem(shot, mt, q))
+    phi_ref, gref, dref = solver.gradient(p0, dobs)
+    d = c.forward(shot, dev(m0), dev(q)).cpu().numpy()
+    assert metrics.rel_l2(d, dref) <= 1e-4
+    phi, g = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=3)
+    assert metrics.rel_l2(g.cpu().numpy(), gref) <= 1e-4
+    c.close()
+
+
 @pytest.mark.parametrize("nslots", [0, 1, 3, 7])
 @pytest.mark.parametrize("ndim", [2, 3])
 def test_revolve_is_bitwise_store_all(ctx, ndim, nslots):
