@@ -177,9 +177,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (HBM counter calibration)")
-    ap.add_argument("--sweep", default="",
-                    help="comma list of variant:xchunk pairs for the 3D stencil; times forward "
-                         "and adjoint steps per pair")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the library's default stencil launch shape")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path shards by shot with one gradient "
@@ -216,32 +215,16 @@ def main():
     nt = args.nt or (2000 if args.workload == "c3" else 500)
     shot, m0, mt, name, s_unc = wl(torch, dev, nt)
     q = torch.from_numpy(shot.wavelet().astype(np.float32)).to(dev)
-    if args.sweep:
-        npts = int(np.prod(shot.comp_shape))
-        rows = []
-        for item in args.sweep.split(","):
-            var, xc = item.split(":")
-            os.environ["FWI_XCHUNK"] = xc
-            c = F.Context(0, pool_bytes=40 << 30)
-            c.set_timing(True)
-            d = c.forward(shot, mt, q)
-            c.gradient(shot, m0, q, d, nslots=8)
-            st = c.stats()
-            tf = st["ms_forward"] / st["n_forward"]
-            ta = st["ms_adjoint"] / st["n_adjoint"]
-            rows.append({"variant": int(var), "xchunk": int(xc), "fwd_ms": round(tf, 4),
-                         "adj_ms": round(ta, 4),
-                         "fwd_GBs": round(16 * npts / tf / 1e6, 1),
-                         "adj_GBs": round(28 * npts / ta / 1e6, 1)})
-            log(rows[-1])
-            c.close()
-        print(json.dumps({"sweep": rows, "nt": nt}))
-        return
     npts = int(np.prod(shot.comp_shape))
     nphys = int(np.prod(shot.shape))
 
     ctx = F.Context(0, pool_bytes=int(os.environ.get("FWI_POOL_BYTES", 140 << 30)))
     ctx.set_timing(True)
+    tune = None
+    if not args.no_autotune:
+        t0 = time.time()
+        tune = ctx.autotune(shot, m0, q, steps=4)
+        log("autotune (%d shapes, %.1f s): %s" % (tune["ncand"], time.time() - t0, tune))
     t0 = time.time()
     d_obs = ctx.forward(shot, mt, q)
     torch.cuda.synchronize()
@@ -341,6 +324,10 @@ def main():
             "nslots_compressed": s_c,
             "nslots_uncompressed": s_unc,
             "hbm_budget_gb": round(budget / 1e9, 2),
+            "stencil_shape": None if tune is None else {
+                "forward": [tune["fwd_xchunk"], tune["fwd_rows_per_lane"], tune["fwd_xcd_order"]],
+                "adjoint": [tune["adj_xchunk"], tune["adj_rows_per_lane"], tune["adj_xcd_order"]],
+                "fields": ["x_planes_per_workgroup", "rows_per_lane", "xcd_contiguous"]},
         },
         "roofline": roof,
         "stencil_gpts": {"forward": round(npts / (fwd_avg * 1e-3) / 1e9, 2),

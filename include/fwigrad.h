@@ -180,6 +180,22 @@ int ckpt_decompress(fwi_ctx *ctx, const void *stream_bytes, size_t nbytes,
 int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
                      int *nactions, long long *nforward);
 
+/* Autotuner: times every candidate launch shape of the stencil kernels on
+ * this grid (3D: x planes per workgroup in {8,16,32,64} x rows per lane in
+ * {2,4} x tile order round-robin / XCD-contiguous; 2D: x planes in
+ * {4..64}) for `steps` forward and `steps` adjoint launches on the model m
+ * [device], and keeps the fastest forward and adjoint shapes in the context
+ * for later calls on a grid of the same dims and order.  Results [host]. */
+typedef struct {
+    int ncand;
+    int fwd_xchunk, fwd_rows_per_lane, fwd_xcd_order;
+    int adj_xchunk, adj_rows_per_lane, adj_xcd_order;
+    double fwd_ms, adj_ms;
+} fwi_tune_result;
+int fwi_autotune(fwi_ctx *ctx, const fwi_grid *g, const float *m,
+                 const fwi_shot *shot, int steps, fwi_tune_result *out,
+                 hipStream_t stream);
+
 /* Bandwidth probe with the stencils' access width (one float per lane):
  * d = a (nsrc = 1) or d = a + b + c (nsrc = 3), n floats, all [device].
  * Measures the practical streaming ceiling and calibrates HBM counters

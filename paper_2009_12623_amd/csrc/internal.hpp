@@ -17,7 +17,7 @@ constexpr int PAD_X = 8;
 constexpr int PAD_Y = 8;
 constexpr int PAD_Z0 = 32;
 constexpr int TILE_Z = 64;     // one wave64 along z
-constexpr int TILE_Y = 16;     // y rows of a 3D stencil tile (8 waves, 2 rows each)
+constexpr int TILE_Y = 32;     // y rounding of padded 3D arrays (largest stencil tile height)
 constexpr int TILE_Z2 = 256;   // z extent of a 2D stencil workgroup
 
 struct Padded {
@@ -50,6 +50,8 @@ struct StepParams {
     const float *wav;       // wavelet (device)
     int step;               // wavelet sample injected by this step
     int xchunk;             // x planes per workgroup
+    int rpl;                // 3D: rows per lane (tile height 8 rpl), 2 or 4
+    int remap;              // 3D: XCD-contiguous tile order
     // forward only: sample u1 at the receivers into grow (nullptr: skip)
     const int *rec_off;     // padded offsets from the allocation base
     int nrec;

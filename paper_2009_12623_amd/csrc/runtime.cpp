@@ -99,7 +99,14 @@ struct fwi_ctx {
     DevBuf<float> dsim, res;
     // timing
     bool timing = false;
-    int xchunk3 = 0;           // 3D stencil x planes per workgroup (0: automatic)
+    // stencil launch shape; overridden per grid by fwi_autotune
+    int xchunk3 = 0;           // 3D x planes per workgroup (0: default)
+    int rpl3 = 2;              // 3D rows per lane
+    int remap3 = 0;            // 3D XCD-contiguous tile order
+    struct Shape {
+        int xchunk, rpl, remap;
+    };
+    std::map<std::vector<int>, std::pair<Shape, Shape>> tuned;   // grid key -> (forward, adjoint)
     fwi_stats stats{};
     std::vector<hipEvent_t> evpool;
     size_t evused = 0;
@@ -444,6 +451,21 @@ struct Exec {
         upload(c->rec_idx, S.rec_idx, st);
     }
 
+    std::vector<int> grid_key() const
+    {
+        return {S.ndim, S.pad.nx, S.pad.ny, S.pad.nz, S.R};
+    }
+
+    void apply_shape(StepParams &p, bool adjoint) const
+    {
+        auto it = c->tuned.find(grid_key());
+        if (it == c->tuned.end()) return;
+        const fwi_ctx::Shape &sh = adjoint ? it->second.second : it->second.first;
+        p.xchunk = sh.xchunk;
+        p.rpl = sh.rpl;
+        p.remap = sh.remap;
+    }
+
     StepParams params() const
     {
         StepParams p{};
@@ -459,15 +481,11 @@ struct Exec {
         p.inv_dt2 = S.inv_dt2;
         for (int k = 0; k < 9; ++k) p.w[k] = S.w[k];
         p.src = -1;
-        if (S.ndim == 3) {
-            // short x chunks: many workgroups in flight; the 2R halo planes
-            // re-read per chunk come from L2
-            int xc = 32;
-            if (c->xchunk3 > 0) xc = c->xchunk3;
-            p.xchunk = std::max(xc, std::min(16, S.pad.nx));
-        } else {
-            p.xchunk = 16;
-        }
+        p.rpl = c->rpl3;
+        p.remap = c->remap3;
+        // short x chunks: many workgroups in flight; the 2R halo planes
+        // re-read per chunk come from L2
+        p.xchunk = c->xchunk3 > 0 ? c->xchunk3 : 16;
         return p;
     }
 
@@ -477,6 +495,7 @@ struct Exec {
         if (!prev_valid) throw Error{FWI_EINVAL, "internal: advance without the older level"};
         Timer tm(c, st, K_FWD);
         StepParams p = params();
+        apply_shape(p, false);
         p.src = S.src_pad;
         p.wav = shot->wavelet;
         p.rec_off = c->rec_off.p;
@@ -599,6 +618,7 @@ struct Exec {
         }
         Timer tm(c, st, K_ADJ);
         StepParams p = params();
+        apply_shape(p, true);
         p.u1 = l1;
         p.u2 = l2;
         p.out = l2;
@@ -776,6 +796,8 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         c->device = device;
         c->pool_default = pool_bytes;
         if (const char *e = std::getenv("FWI_XCHUNK")) c->xchunk3 = std::atoi(e);
+        if (const char *e = std::getenv("FWI_RPL")) c->rpl3 = std::atoi(e) == 4 ? 4 : 2;
+        if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::atoi(e) != 0;
         *ctx = c;
     });
 }
@@ -1072,6 +1094,71 @@ int ckpt_decompress(fwi_ctx *c, const void *stream, size_t nbytes, float *field,
         finish_status(c, st);
         c->stats.n_decode = 1;
         end_call(c, st);
+    });
+}
+
+int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot, int steps,
+                 fwi_tune_result *out, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !m || !out) throw Error{FWI_EINVAL, "null argument"};
+        if (steps < 1) throw Error{FWI_EINVAL, "steps must be >= 1"};
+        HIPCHK(hipSetDevice(c->device));
+        Exec ex{c, make_setup(g, shot, true), st, m, shot};
+        ensure_fields(c, ex.S);
+        ex.init_fields();
+        HIPCHK(hipMemsetAsync(c->la.p, 0, c->padded_elems * sizeof(float), st));
+        HIPCHK(hipMemsetAsync(c->lb.p, 0, c->padded_elems * sizeof(float), st));
+        HIPCHK(hipMemsetAsync(c->gacc.p, 0, c->padded_elems * sizeof(float), st));
+        std::vector<fwi_ctx::Shape> cands;
+        const int xcs3[] = {8, 16, 32, 64};
+        const int xcs2[] = {4, 8, 16, 32, 64};
+        if (ex.S.ndim == 3) {
+            for (int xc : xcs3)
+                for (int rpl : {2, 4})
+                    for (int remap : {0, 1}) cands.push_back({xc, rpl, remap});
+        } else {
+            for (int xc : xcs2) cands.push_back({xc, 2, 0});
+        }
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        auto time_it = [&](const fwi_ctx::Shape &sh, bool adj) {
+            StepParams p = ex.params();
+            p.xchunk = sh.xchunk;
+            p.rpl = sh.rpl;
+            p.remap = sh.remap;
+            if (adj) {
+                p.u1 = c->la.p; p.u2 = c->lb.p; p.out = c->lb.p; p.uk = c->fa.p; p.g = c->gacc.p;
+            } else {
+                p.u1 = c->fa.p; p.u2 = c->fb.p; p.out = c->fb.p; p.wav = shot->wavelet; p.step = 0;
+            }
+            launch_step(p, ex.S.ndim, ex.S.R, adj, st);          // warm-up
+            HIPCHK(hipEventRecord(e0, st));
+            for (int i = 0; i < steps; ++i) launch_step(p, ex.S.ndim, ex.S.R, adj, st);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            return (double)ms / steps;
+        };
+        double bf = 1e30, ba = 1e30;
+        fwi_ctx::Shape sf = cands[0], sa = cands[0];
+        for (const auto &sh : cands) {
+            const double tf = time_it(sh, false), ta = time_it(sh, true);
+            if (tf < bf) { bf = tf; sf = sh; }
+            if (ta < ba) { ba = ta; sa = sh; }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->tuned[ex.grid_key()] = {sf, sa};
+        out->ncand = (int)cands.size();
+        out->fwd_xchunk = sf.xchunk; out->fwd_rows_per_lane = sf.rpl; out->fwd_xcd_order = sf.remap;
+        out->adj_xchunk = sa.xchunk; out->adj_rows_per_lane = sa.rpl; out->adj_xcd_order = sa.remap;
+        out->fwd_ms = bf;
+        out->adj_ms = ba;
+        HIPCHK(hipMemsetAsync(c->fa.p, 0, c->padded_elems * sizeof(float), st));
+        HIPCHK(hipMemsetAsync(c->fb.p, 0, c->padded_elems * sizeof(float), st));
     });
 }
 

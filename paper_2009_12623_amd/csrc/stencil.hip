@@ -78,18 +78,17 @@ __device__ __forceinline__ void gather_block(const StepParams &p, int blk)
 }
 
 // ------------------------------------------------------------------- 3D
-// Workgroup = 64 (z) x 8 (y) lanes; each lane owns two rows of a 64 x 16
-// (z, y) tile.  Tiles are numbered z fastest, then y, then x chunk, and
-// handed out so that each XCD (workgroups are dealt to the 8 XCDs round
-// robin) works on one contiguous range, keeping halo reuse inside its L2.
-// Read-once streams (u2, b, u^k, g) use non-temporal loads.
-constexpr int T3_ROWS = 16;
-
-__device__ __forceinline__ void tile_coords(int hw, int nwg, int ntz, int nty, int &tzi, int &tyi,
-                                            int &txi, bool &valid)
+// Workgroup = 64 (z) x 8 (y) lanes; each lane owns RPL rows (ty + 8 j) of a
+// 64 x 8 RPL (z, y) tile.  Tiles are numbered z fastest, then y, then x
+// chunk; with `remap` they are handed out so that each XCD (workgroups are
+// dealt to the 8 XCDs round robin) works on one contiguous range, keeping
+// halo reuse inside its L2.  Read-once streams (u2, b, u^k, g) use
+// non-temporal loads.
+__device__ __forceinline__ void tile_coords(int hw, int nwg, int ntz, int nty, bool remap, int &tzi,
+                                            int &tyi, int &txi, bool &valid)
 {
     const int per = (nwg + 7) >> 3;
-    const int logical = (hw & 7) * per + (hw >> 3);
+    const int logical = remap ? (hw & 7) * per + (hw >> 3) : hw;
     valid = logical < nwg;
     tzi = logical % ntz;
     const int rest = logical / ntz;
@@ -97,11 +96,12 @@ __device__ __forceinline__ void tile_coords(int hw, int nwg, int ntz, int nty, i
     txi = rest / nty;
 }
 
-template <int R, bool ADJ>
+template <int R, bool ADJ, int RPL>
 __global__ __launch_bounds__(TILE_Z * 8)
 void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
 {
-    __shared__ float tile[2][T3_ROWS + 2 * R][TILE_Z + 2 * R];
+    constexpr int ROWS = 8 * RPL;
+    __shared__ float tile[2][ROWS + 2 * R][TILE_Z + 2 * R];
     const int hw = blockIdx.x;
     if (hw >= launched) {                          // receiver sampling blocks
         gather_block(p, hw - launched);
@@ -109,21 +109,17 @@ void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
     }
     int tzi, tyi, txi;
     bool valid;
-    tile_coords(hw, nwg, ntz, nty, tzi, tyi, txi, valid);
+    tile_coords(hw, nwg, ntz, nty, p.remap != 0, tzi, tyi, txi, valid);
     if (!valid) return;                            // whole workgroup, before any barrier
 
     const int tz = threadIdx.x;
     const int ty = threadIdx.y;
     const int z0 = tzi * TILE_Z;
-    const int y0 = tyi * T3_ROWS;
+    const int y0 = tyi * ROWS;
     const int z = z0 + tz;
-    const int ya = y0 + ty;
-    const int yb = ya + 8;
     const int xb = txi * p.xchunk;
     const int xe = min(xb + p.xchunk, p.nx);
     const bool zin = z < p.nz;
-    const bool act_a = zin && ya < p.ny;
-    const bool act_b = zin && yb < p.ny;
     // byte strides and offsets (unsigned arithmetic; every result is in range)
     const unsigned bsx = 4u * (unsigned)p.psx, bsy = 4u * (unsigned)p.psy;
     const unsigned org = 4u * (unsigned)p.origin;
@@ -133,48 +129,52 @@ void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
     const float *__restrict__ bq = p.b;
     const bool hy = ty < R;
     const unsigned hy_top = org + (unsigned)(y0 - R + ty) * bsy + 4u * z;
-    const unsigned hy_bot = org + (unsigned)(y0 + T3_ROWS + ty) * bsy + 4u * z;
+    const unsigned hy_bot = org + (unsigned)(y0 + ROWS + ty) * bsy + 4u * z;
     const bool hzl = tz < R, hzr = tz >= TILE_Z - R;
     const bool hz = hzl || hzr;
     const unsigned hz_off = 4u * (unsigned)(hzl ? (z0 - R + tz) : (z + R));
-    const unsigned hza = org + (unsigned)ya * bsy + hz_off;
-    const unsigned hzb = org + (unsigned)yb * bsy + hz_off;
     const int hcol = hzl ? tz : tz + 2 * R;
-    const unsigned cola = org + (unsigned)ya * bsy + 4u * z;
-    const unsigned colb = cola + 8u * bsy;
-    const int dy_a = layer_depth(ya, p.ny, p.nbl), dy_b = layer_depth(yb, p.ny, p.nbl);
+    const unsigned col0 = org + (unsigned)(y0 + ty) * bsy + 4u * z;   // row j at + 8 j bsy
+    const unsigned hz0 = org + (unsigned)(y0 + ty) * bsy + hz_off;
+    const unsigned rstep = 8u * bsy;
     const int dz = layer_depth(z, p.nz, p.nbl);
-    const int dyz_a = dy_a * dy_a + dz * dz, dyz_b = dy_b * dy_b + dz * dz;
-
-    float qa[2 * R + 1], qb[2 * R + 1];
+    bool act[RPL];
+    int dyz[RPL];
 #pragma unroll
-    for (int i = 0; i <= 2 * R; ++i) {
-        qa[i] = ld(u1, cola + (unsigned)(xb - R + i) * bsx);
-        qb[i] = ld(u1, colb + (unsigned)(xb - R + i) * bsx);
+    for (int j = 0; j < RPL; ++j) {
+        const int y = y0 + ty + 8 * j;
+        act[j] = zin && y < p.ny;
+        const int dy = layer_depth(y, p.ny, p.nbl);
+        dyz[j] = dy * dy + dz * dz;
     }
+
+    float q[RPL][2 * R + 1];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+#pragma unroll
+        for (int i = 0; i <= 2 * R; ++i) q[j][i] = ld(u1, col0 + j * rstep + (unsigned)(xb - R + i) * bsx);
     {
         const unsigned pl = (unsigned)xb * bsx;
-        tile[0][ty + R][tz + R] = qa[R];
-        tile[0][ty + 8 + R][tz + R] = qb[R];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) tile[0][ty + 8 * j + R][tz + R] = q[j][R];
         if (hy) {
             tile[0][ty][tz + R] = ld(u1, pl + hy_top);
-            tile[0][ty + T3_ROWS + R][tz + R] = ld(u1, pl + hy_bot);
+            tile[0][ty + ROWS + R][tz + R] = ld(u1, pl + hy_bot);
         }
         if (hz) {
-            tile[0][ty + R][hcol] = ld(u1, pl + hza);
-            tile[0][ty + 8 + R][hcol] = ld(u1, pl + hzb);
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) tile[0][ty + 8 * j + R][hcol] = ld(u1, pl + hz0 + j * rstep);
         }
     }
-    unsigned pa = cola + (unsigned)xb * bsx;           // row a; row b at + 8 rows
-    const unsigned boff = 8u * bsy;
-    float u2a = act_a ? ldnt(u2, pa) : 0.f, u2b = act_b ? ldnt(u2, pa + boff) : 0.f;
-    float ba = act_a ? ldnt(bq, pa) : 0.f, bbv = act_b ? ldnt(bq, pa + boff) : 0.f;
-    float uka = 0.f, ukb = 0.f, ga = 0.f, gb = 0.f;
-    if (ADJ) {
-        uka = act_a ? ldnt(p.uk, pa) : 0.f;
-        ukb = act_b ? ldnt(p.uk, pa + boff) : 0.f;
-        ga = act_a ? ldnt(p.g, pa) : 0.f;
-        gb = act_b ? ldnt(p.g, pa + boff) : 0.f;
+    unsigned pa = col0 + (unsigned)xb * bsx;            // row j at + j rstep
+    float u2v[RPL], bv[RPL], ukv[RPL], gv[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+        const unsigned o = pa + j * rstep;
+        u2v[j] = act[j] ? ldnt(u2, o) : 0.f;
+        bv[j] = act[j] ? ldnt(bq, o) : 0.f;
+        ukv[j] = (ADJ && act[j]) ? ldnt(p.uk, o) : 0.f;
+        gv[j] = (ADJ && act[j]) ? ldnt(p.g, o) : 0.f;
     }
     __syncthreads();
 
@@ -182,8 +182,10 @@ void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
         const int cur = (x - xb) & 1;
         const bool nxt = x + 1 < xe;
         // ---- issue the loads of plane x+1 (halo first: needed soonest)
-        float nqa = 0.f, nqb = 0.f, nht = 0.f, nhb = 0.f, nza = 0.f, nzb = 0.f;
-        float nu2a = 0.f, nu2b = 0.f, nba = 0.f, nbb = 0.f, nuka = 0.f, nukb = 0.f, nga = 0.f, ngb = 0.f;
+        float nq[RPL], nhz[RPL], nu2[RPL], nb_[RPL], nuk[RPL], ng[RPL];
+        float nht = 0.f, nhb = 0.f;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) nq[j] = nhz[j] = nu2[j] = nb_[j] = nuk[j] = ng[j] = 0.f;
         if (nxt) {
             const unsigned pl = (unsigned)(x + 1) * bsx;
             if (hy) {
@@ -191,71 +193,57 @@ void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
                 nhb = ld(u1, pl + hy_bot);
             }
             if (hz) {
-                nza = ld(u1, pl + hza);
-                nzb = ld(u1, pl + hzb);
+#pragma unroll
+                for (int j = 0; j < RPL; ++j) nhz[j] = ld(u1, pl + hz0 + j * rstep);
             }
-            nqa = ld(u1, cola + pl + (unsigned)R * bsx);
-            nqb = ld(u1, colb + pl + (unsigned)R * bsx);
-            const unsigned na = pa + bsx;
-            if (act_a) {
-                nu2a = ldnt(u2, na);
-                nba = ldnt(bq, na);
-                if (ADJ) { nuka = ldnt(p.uk, na); nga = ldnt(p.g, na); }
-            }
-            if (act_b) {
-                nu2b = ldnt(u2, na + boff);
-                nbb = ldnt(bq, na + boff);
-                if (ADJ) { nukb = ldnt(p.uk, na + boff); ngb = ldnt(p.g, na + boff); }
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) nq[j] = ld(u1, col0 + j * rstep + pl + (unsigned)R * bsx);
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) {
+                const unsigned na = pa + bsx + j * rstep;
+                if (act[j]) {
+                    nu2[j] = ldnt(u2, na);
+                    nb_[j] = ldnt(bq, na);
+                    if (ADJ) { nuk[j] = ldnt(p.uk, na); ng[j] = ldnt(p.g, na); }
+                }
             }
         }
         // ---- plane x
         const int dx = layer_depth(x, p.nx, p.nbl);
-        if (act_a) {
-            const float c = qa[R];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            if (!act[j]) continue;
+            const int r = ty + 8 * j + R;
+            const float c = q[j][R];
             float lap = 3.0f * p.w[0] * c;
 #pragma unroll
             for (int k = 1; k <= R; ++k)
-                lap += p.w[k] * ((qa[R - k] + qa[R + k]) +
-                                 (tile[cur][ty + R - k][tz + R] + tile[cur][ty + R + k][tz + R]) +
-                                 (tile[cur][ty + R][tz + R - k] + tile[cur][ty + R][tz + R + k]));
-            const float o = update<ADJ>(p, dx * dx + dyz_a, pa == srcb, c, lap, u2a, ba);
-            st(p.out, pa, o);
-            if (ADJ) st(p.g, pa, ga - uka * (o - 2.0f * c + u2a) * p.inv_dt2);
-        }
-        if (act_b) {
-            const float c = qb[R];
-            float lap = 3.0f * p.w[0] * c;
-#pragma unroll
-            for (int k = 1; k <= R; ++k)
-                lap += p.w[k] * ((qb[R - k] + qb[R + k]) +
-                                 (tile[cur][ty + 8 + R - k][tz + R] + tile[cur][ty + 8 + R + k][tz + R]) +
-                                 (tile[cur][ty + 8 + R][tz + R - k] + tile[cur][ty + 8 + R][tz + R + k]));
-            const float o = update<ADJ>(p, dx * dx + dyz_b, pa + boff == srcb, c, lap, u2b, bbv);
-            st(p.out, pa + boff, o);
-            if (ADJ) st(p.g, pa + boff, gb - ukb * (o - 2.0f * c + u2b) * p.inv_dt2);
+                lap += p.w[k] * ((q[j][R - k] + q[j][R + k]) +
+                                 (tile[cur][r - k][tz + R] + tile[cur][r + k][tz + R]) +
+                                 (tile[cur][r][tz + R - k] + tile[cur][r][tz + R + k]));
+            const unsigned o = pa + j * rstep;
+            const float ov = update<ADJ>(p, dx * dx + dyz[j], o == srcb, c, lap, u2v[j], bv[j]);
+            st(p.out, o, ov);
+            if (ADJ) st(p.g, o, gv[j] - ukv[j] * (ov - 2.0f * c + u2v[j]) * p.inv_dt2);
         }
         if (!nxt) break;
         // ---- advance the queues and stage plane x+1 in the other buffer
-#pragma unroll
-        for (int i = 0; i < 2 * R; ++i) {
-            qa[i] = qa[i + 1];
-            qb[i] = qb[i + 1];
-        }
-        qa[2 * R] = nqa;
-        qb[2 * R] = nqb;
         const int nb = cur ^ 1;
-        tile[nb][ty + R][tz + R] = qa[R];
-        tile[nb][ty + 8 + R][tz + R] = qb[R];
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i) q[j][i] = q[j][i + 1];
+            q[j][2 * R] = nq[j];
+            tile[nb][ty + 8 * j + R][tz + R] = q[j][R];
+            if (hz) tile[nb][ty + 8 * j + R][hcol] = nhz[j];
+            u2v[j] = nu2[j];
+            bv[j] = nb_[j];
+            if (ADJ) { ukv[j] = nuk[j]; gv[j] = ng[j]; }
+        }
         if (hy) {
             tile[nb][ty][tz + R] = nht;
-            tile[nb][ty + T3_ROWS + R][tz + R] = nhb;
+            tile[nb][ty + ROWS + R][tz + R] = nhb;
         }
-        if (hz) {
-            tile[nb][ty + R][hcol] = nza;
-            tile[nb][ty + 8 + R][hcol] = nzb;
-        }
-        u2a = nu2a; u2b = nu2b; ba = nba; bbv = nbb;
-        if (ADJ) { uka = nuka; ukb = nukb; ga = nga; gb = ngb; }
         pa += bsx;
         __syncthreads();
     }
@@ -342,13 +330,18 @@ void launch_r(const StepParams &p, int ndim, hipStream_t st)
     const int nchunk = (p.nx + p.xchunk - 1) / p.xchunk;
     const bool gather = !ADJ && p.grow && p.nrec > 0;
     if (ndim == 3) {
+        const int rows = 8 * p.rpl;
         const int ntz = (p.nz + TILE_Z - 1) / TILE_Z;
-        const int nty = (p.ny + T3_ROWS - 1) / T3_ROWS;
+        const int nty = (p.ny + rows - 1) / rows;
         const int nwg = ntz * nty * nchunk;
         const int launched = ((nwg + 7) / 8) * 8;
         const int ng = gather ? (p.nrec + 511) / 512 : 0;
-        hipLaunchKernelGGL((step3d_kernel<R, ADJ>), dim3(launched + ng), dim3(TILE_Z, 8, 1), 0, st,
-                           p, ntz, nty, nwg, launched);
+        if (p.rpl == 4)
+            hipLaunchKernelGGL((step3d_kernel<R, ADJ, 4>), dim3(launched + ng), dim3(TILE_Z, 8, 1), 0, st,
+                               p, ntz, nty, nwg, launched);
+        else
+            hipLaunchKernelGGL((step3d_kernel<R, ADJ, 2>), dim3(launched + ng), dim3(TILE_Z, 8, 1), 0, st,
+                               p, ntz, nty, nwg, launched);
     } else {
         const int ntz = (p.nz + TILE_Z2 - 1) / TILE_Z2;
         const int nwg = ntz * nchunk;

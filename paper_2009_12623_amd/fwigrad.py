@@ -53,6 +53,14 @@ class fwi_stats(ctypes.Structure):
                  "ckpt_raw_bytes", "pool_high")]
 
 
+class fwi_tune_result(ctypes.Structure):
+    _fields_ = [("ncand", ctypes.c_int), ("fwd_xchunk", ctypes.c_int),
+                ("fwd_rows_per_lane", ctypes.c_int), ("fwd_xcd_order", ctypes.c_int),
+                ("adj_xchunk", ctypes.c_int), ("adj_rows_per_lane", ctypes.c_int),
+                ("adj_xcd_order", ctypes.c_int), ("fwd_ms", ctypes.c_double),
+                ("adj_ms", ctypes.c_double)]
+
+
 class fwi_action(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int), ("a", ctypes.c_int), ("b", ctypes.c_int)]
 
@@ -62,7 +70,7 @@ _lib = None
 EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_stats",
            "fwi_last_error", "fwi_forward", "fwi_gradient", "fwi_forward_ckpt",
            "fwi_backward", "fwi_tape_free", "ckpt_bound", "ckpt_compress",
-           "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe"]
+           "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune"]
 
 
 def lib():
@@ -95,6 +103,8 @@ def lib():
     L.fwi_revolve_plan.argtypes = [I, I, ctypes.POINTER(fwi_action), I, ctypes.POINTER(I),
                                    ctypes.POINTER(ctypes.c_longlong)]
     L.fwi_bandwidth_probe.argtypes = [P, P, P, P, ctypes.c_size_t, I, P]
+    L.fwi_autotune.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), I,
+                               ctypes.POINTER(fwi_tune_result), P]
     _lib = L
     return L
 
@@ -218,6 +228,14 @@ class Context:
         s = fwi_stats()
         check(lib().fwi_ctx_stats(self.h, ctypes.byref(s)))
         return {k: getattr(s, k) for k, _ in fwi_stats._fields_}
+
+    def autotune(self, shot, m, wavelet, steps=4) -> dict:
+        sa = ShotArgs(shot, wavelet)
+        g = grid_of(shot)
+        r = fwi_tune_result()
+        check(lib().fwi_autotune(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), int(steps),
+                                 ctypes.byref(r), _stream()))
+        return {k: getattr(r, k) for k, _ in fwi_tune_result._fields_}
 
     # Eq. (2)
     def forward(self, shot, m: torch.Tensor, wavelet: torch.Tensor) -> torch.Tensor:

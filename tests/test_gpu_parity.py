@@ -82,10 +82,13 @@ def test_gradient_matches_oracle(ctx, ndim, n, so, nbl, nt):
     assert abs(phi - phi_ref) <= 1e-4 * phi_ref
 
 
-@pytest.mark.parametrize("xchunk", [3, 7, 64])
+@pytest.mark.parametrize("xchunk,rpl,remap", [(3, 2, 0), (7, 4, 1), (64, 2, 1), (16, 4, 0)])
 @pytest.mark.parametrize("so", [4, 8, 16])
-def test_3d_stencil_xchunks_match_oracle(xchunk, so, monkeypatch):
+def test_3d_stencil_launch_shapes_match_oracle(xchunk, rpl, remap, so, monkeypatch):
+    """every launch shape (x planes per workgroup, rows per lane, tile order)"""
     monkeypatch.setenv("FWI_XCHUNK", str(xchunk))
+    monkeypatch.setenv("FWI_RPL", str(rpl))
+    monkeypatch.setenv("FWI_REMAP", str(remap))
     c = F.Context(0, pool_bytes=1 << 28)
     shot = synth.tiny_shot(3, n=23, so=so, nbl=5, nt=35)
     m0, mt, q = inputs(shot)
@@ -96,6 +99,29 @@ def test_3d_stencil_xchunks_match_oracle(xchunk, so, monkeypatch):
     assert metrics.rel_l2(d, dref) <= 1e-4
     phi, g = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=3)
     assert metrics.rel_l2(g.cpu().numpy(), gref) <= 1e-4
+    c.close()
+
+
+@pytest.mark.parametrize("ndim,n,so", [(2, 150, 16), (3, 40, 8)])
+def test_autotuned_shapes_keep_the_gradient(ndim, n, so):
+    """the autotuner picks a listed shape; the gradient it then computes
+    equals the oracle's like the default shape's does"""
+    c = F.Context(0, pool_bytes=1 << 28)
+    shot = synth.tiny_shot(ndim, n=n, so=so, nbl=6, nt=40)
+    m0, mt, q = inputs(shot)
+    p0 = oracle_problem(shot, m0, q)
+    dobs = solver.forward(oracle_problem(shot, mt, q))
+    _, gref, _ = solver.gradient(p0, dobs)
+    _, g_def = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=4)
+    r = c.autotune(shot, dev(m0), dev(q), steps=2)
+    print("autotune", ndim, r)
+    assert r["ncand"] == (16 if ndim == 3 else 5)
+    assert r["fwd_xchunk"] in (4, 8, 16, 32, 64) and r["adj_xchunk"] in (4, 8, 16, 32, 64)
+    assert r["fwd_rows_per_lane"] in (2, 4) and r["fwd_ms"] > 0 and r["adj_ms"] > 0
+    _, g = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=4)
+    g, g_def = g.cpu().numpy(), g_def.cpu().numpy()
+    assert metrics.rel_l2(g, gref) <= 1e-4
+    assert metrics.rel_l2(g, g_def) <= 1e-6
     c.close()
 
 
