@@ -223,7 +223,7 @@ def main():
     tune = None
     if not args.no_autotune:
         t0 = time.time()
-        tune = ctx.autotune(shot, m0, q, steps=4)
+        tune = ctx.autotune(shot, m0, q, steps=8)
         log("autotune (%d shapes, %.1f s): %s" % (tune["ncand"], time.time() - t0, tune))
     t0 = time.time()
     d_obs = ctx.forward(shot, mt, q)

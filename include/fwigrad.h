@@ -183,9 +183,11 @@ int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
 /* Autotuner: times every candidate launch shape of the stencil kernels on
  * this grid (3D: x planes per workgroup in {8,16,32,64} x rows per lane in
  * {2,4} x tile order round-robin / XCD-contiguous; 2D: x planes in
- * {4..64}) for `steps` forward and `steps` adjoint launches on the model m
- * [device], and keeps the fastest forward and adjoint shapes in the context
- * for later calls on a grid of the same dims and order.  Results [host]. */
+ * {4..64}), `steps` forward and `steps` adjoint launches each on the model
+ * m [device], with the buffer roles alternating as in a sweep, and keeps
+ * the fastest forward and adjoint shapes for later calls on a grid of the
+ * same dims and order.  Results [host].  Synchronises the stream; the context's
+ * working fields are cleared (tapes keep their own state). */
 typedef struct {
     int ncand;
     int fwd_xchunk, fwd_rows_per_lane, fwd_xcd_order;

@@ -76,6 +76,18 @@ struct DevBuf {
     }
 };
 
+// a padded array inside the field arena
+struct FieldPtr {
+    float *p = nullptr;
+    void release() { p = nullptr; }
+};
+
+// Array i of the arena starts at i * (stride + ARENA_STAGGER), stride = its
+// bytes rounded up to 2 MiB, so the same element of the streams a step
+// touches does not sit at the same offset within a 2 MiB page.
+constexpr size_t ARENA_ALIGN = size_t(2) << 20;
+constexpr size_t ARENA_STAGGER = size_t(12) << 10;
+
 enum Kind { K_FWD = 0, K_ADJ = 1, K_ENC = 2, K_DEC = 3, K_NKIND = 4 };
 
 }  // namespace
@@ -86,7 +98,10 @@ struct fwi_ctx {
     DevBuf<unsigned char> pool;
     // working fields, coefficient b = dt^2/m and gradient accumulator, all
     // in the padded layout
-    DevBuf<float> fa, fb, la, lb, coef, gacc;
+    // the six padded arrays a time step touches, carved from one arena
+    DevBuf<char> arena;
+    size_t arena_stride = 0;
+    FieldPtr fa, fb, la, lb, coef, gacc;
     size_t padded_elems = 0;
     // codec scratch
     DevBuf<unsigned long long> scratch, chunk_bits, chunk_off, misc;
@@ -286,19 +301,24 @@ void upload(DevBuf<T> &b, const std::vector<T> &v, hipStream_t st)
     if (!v.empty()) HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
 }
 
+// point the six arrays into the arena
+void carve_fields(fwi_ctx *c)
+{
+    FieldPtr *arr[6] = {&c->fa, &c->fb, &c->la, &c->lb, &c->coef, &c->gacc};
+    for (int i = 0; i < 6; ++i)
+        arr[i]->p = (float *)(c->arena.p + (size_t)i * (c->arena_stride + ARENA_STAGGER));
+}
+
 void ensure_fields(fwi_ctx *c, const Setup &s)
 {
     const size_t pe = s.pad.elems();
     if (pe != c->padded_elems) {
-        c->fa.release(); c->fb.release(); c->la.release(); c->lb.release();
-        c->coef.release(); c->gacc.release();
-        c->fa.ensure(pe, true);
-        c->fb.ensure(pe, true);
-        c->la.ensure(pe, true);
-        c->lb.ensure(pe, true);
-        c->coef.ensure(pe, true);
-        c->gacc.ensure(pe, true);
+        c->arena.release();
+        c->padded_elems = 0;
+        c->arena_stride = (pe * sizeof(float) + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
+        c->arena.ensure(6 * (c->arena_stride + ARENA_STAGGER), true);
         c->padded_elems = pe;
+        carve_fields(c);
     }
 }
 
@@ -811,7 +831,7 @@ int fwi_ctx_destroy(fwi_ctx *c)
         for (auto e : c->evpool) (void)hipEventDestroy(e);
         if (c->t0) (void)hipEventDestroy(c->t0);
         if (c->t1) (void)hipEventDestroy(c->t1);
-        c->pool.release(); c->fa.release(); c->fb.release(); c->la.release(); c->lb.release();
+        c->pool.release(); c->arena.release(); c->fa.release(); c->fb.release(); c->la.release(); c->lb.release();
         c->coef.release(); c->scratch.release(); c->chunk_bits.release(); c->chunk_off.release();
         c->misc.release(); c->slots.release(); c->flags.release(); c->partials.release();
         c->phi.release(); c->rec_off.release(); c->node_pad.release(); c->gacc.release();
@@ -1106,10 +1126,7 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         HIPCHK(hipSetDevice(c->device));
         Exec ex{c, make_setup(g, shot, true), st, m, shot};
         ensure_fields(c, ex.S);
-        ex.init_fields();
-        HIPCHK(hipMemsetAsync(c->la.p, 0, c->padded_elems * sizeof(float), st));
-        HIPCHK(hipMemsetAsync(c->lb.p, 0, c->padded_elems * sizeof(float), st));
-        HIPCHK(hipMemsetAsync(c->gacc.p, 0, c->padded_elems * sizeof(float), st));
+        const size_t arena_bytes = c->arena.n;
         std::vector<fwi_ctx::Shape> cands;
         const int xcs3[] = {8, 16, 32, 64};
         const int xcs2[] = {4, 8, 16, 32, 64};
@@ -1123,25 +1140,36 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
+        // steps alternate the buffer roles the way the sweeps rotate them
         auto time_it = [&](const fwi_ctx::Shape &sh, bool adj) {
             StepParams p = ex.params();
             p.xchunk = sh.xchunk;
             p.rpl = sh.rpl;
             p.remap = sh.remap;
-            if (adj) {
-                p.u1 = c->la.p; p.u2 = c->lb.p; p.out = c->lb.p; p.uk = c->fa.p; p.g = c->gacc.p;
-            } else {
-                p.u1 = c->fa.p; p.u2 = c->fb.p; p.out = c->fb.p; p.wav = shot->wavelet; p.step = 0;
-            }
-            launch_step(p, ex.S.ndim, ex.S.R, adj, st);          // warm-up
+            auto one = [&](int i) {
+                float *a = (i & 1) ? c->fb.p : c->fa.p, *b = (i & 1) ? c->fa.p : c->fb.p;
+                if (adj) {
+                    float *l1 = (i & 1) ? c->lb.p : c->la.p, *l2 = (i & 1) ? c->la.p : c->lb.p;
+                    p.u1 = l1; p.u2 = l2; p.out = l2; p.uk = a; p.g = c->gacc.p;
+                } else {
+                    p.u1 = a; p.u2 = b; p.out = b; p.wav = shot->wavelet; p.step = 0;
+                }
+                launch_step(p, ex.S.ndim, ex.S.R, adj, st);
+            };
+            one(0);                                              // warm-up
             HIPCHK(hipEventRecord(e0, st));
-            for (int i = 0; i < steps; ++i) launch_step(p, ex.S.ndim, ex.S.R, adj, st);
+            for (int i = 0; i < steps; ++i) one(i + 1);
             HIPCHK(hipEventRecord(e1, st));
             HIPCHK(hipEventSynchronize(e1));
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             return (double)ms / steps;
         };
+        auto reset = [&] {
+            HIPCHK(hipMemsetAsync(c->arena.p, 0, arena_bytes, st));
+            ex.init_fields();
+        };
+        reset();
         double bf = 1e30, ba = 1e30;
         fwi_ctx::Shape sf = cands[0], sa = cands[0];
         for (const auto &sh : cands) {
@@ -1157,8 +1185,8 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         out->adj_xchunk = sa.xchunk; out->adj_rows_per_lane = sa.rpl; out->adj_xcd_order = sa.remap;
         out->fwd_ms = bf;
         out->adj_ms = ba;
-        HIPCHK(hipMemsetAsync(c->fa.p, 0, c->padded_elems * sizeof(float), st));
-        HIPCHK(hipMemsetAsync(c->fb.p, 0, c->padded_elems * sizeof(float), st));
+        HIPCHK(hipMemsetAsync(c->arena.p, 0, arena_bytes, st));
+        HIPCHK(hipStreamSynchronize(st));
     });
 }
 
