@@ -164,6 +164,36 @@ def cpu_baseline(shot, m0_host, counts, seconds=8.0):
             "sample": sample}
 
 
+# ------------------------------------------------------------------ traffic
+COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                        "c3_stencil_hbm_counters.txt")
+
+
+def stencil_source_hash():
+    import hashlib
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2009_12623_amd", "csrc")
+    return ":".join(hashlib.sha256(open(os.path.join(here, f), "rb").read()).hexdigest()
+                    for f in ("stencil.hip", "internal.hpp"))
+
+
+def counted_traffic(kernel, shape):
+    """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary,
+    scaled by the copy-kernel calibration; None unless the kernel, its launch
+    shape and the stencil source are the ones the counters were taken on."""
+    if not os.path.exists(COUNTERS) or shape is None:
+        return None
+    want = stencil_source_hash()
+    for line in open(COUNTERS):
+        if not line.startswith("traffic "):
+            continue
+        kv = dict(t.split("=", 1) for t in line.split()[1:])
+        if (kv["kernel"] == kernel and kv["shape"] == ",".join(map(str, shape))
+                and kv["source"] == want):
+            return (float(kv["fetch_kib"]) * 1024 * float(kv["fetch_factor"])
+                    + float(kv["write_kib"]) * 1024 * float(kv["write_factor"]))
+    return None
+
+
 # ------------------------------------------------------------------ main
 def main():
     ap = argparse.ArgumentParser()
@@ -298,8 +328,15 @@ def main():
     ms, n, bytes_per = kinds[dom]
     avg_ms = ms / max(n, 1)
     achieved = bytes_per / (avg_ms * 1e-3) / 1e9
+    shape = None
+    if tune is not None and dom in ("forward_step", "adjoint_imaging_step"):
+        pre = "fwd" if dom == "forward_step" else "adj"
+        shape = (tune[pre + "_xchunk"], tune[pre + "_rows_per_lane"], tune[pre + "_xcd_order"])
+    traffic = counted_traffic(dom, shape) if args.workload == "c3" else None
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / bytes_per, 3),
             "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": bytes_per}
     fwd_avg = st["ms_forward"] / max(st["n_forward"], 1)
     out = {
