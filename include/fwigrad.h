@@ -156,6 +156,11 @@ int fwi_forward_ckpt(fwi_ctx *ctx, const fwi_grid *g, const float *m,
 int fwi_backward(fwi_ctx *ctx, fwi_tape *tape, const float *dd, float *grad,
                  hipStream_t stream);
 int fwi_tape_free(fwi_tape *tape);
+/* Pool bytes [host] that the checkpoints of cfg.nslots slots on grid g can
+ * take: exact checkpoints need exactly this much; for compressed ones it is
+ * the worst case (every stream at ckpt_bound), so callers usually size a
+ * compressed pool from an earlier call's fwi_stats.pool_high instead. */
+int fwi_ckpt_pool_bytes(const fwi_grid *g, const fwi_ckpt_cfg *cfg, size_t *bytes);
 
 /* Codec (Sec. 1.4 / Sec. 3: ZFP-style fixed accuracy).  field [device]
  * float32, C order, ndim in {2, 3}; every decoded value is within atol of

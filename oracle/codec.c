@@ -41,8 +41,10 @@
  *  9 stream: 64-byte header, then one u64 bit offset per super-chunk of 256
  *    chunks, one u32 offset per chunk relative to its super-chunk, padding
  *    to 8 bytes, then the payload packed LSB first into little-endian u64
- *    words.  A chunk holds K = 16 (3D) or 64 (2D) blocks: chunk c = 64 g + l
- *    takes blocks g*64K + j*64 + l, j = 0..K-1, that exist;
+ *    words.  A chunk holds K blocks, K = 16 (3D) or 64 (2D), halved while
+ *    the field would have fewer than 16384 chunks (down to K = 1), so small
+ *    fields still split into many independently decodable pieces; chunk
+ *    c = 64 g + l takes blocks g*64K + j*64 + l, j = 0..K-1, that exist;
  * 10 decode mirrors 8..4; the int32 result is converted to float32 with
  *    round-to-nearest-even and scaled by 2^(emax-Q) through the exponent
  *    field; results below 2^-126 become +0, above FLT_MAX saturate.
@@ -92,6 +94,7 @@ static int geom_init(geom_t *g, int ndim, const long *n)
     g->tp = ndim == 3 ? 31 : 29;
     g->guard = ndim == 3 ? 5 : 4;
     g->kblk = ndim == 3 ? 16 : 64;
+    while (g->kblk > 1 && (g->nblocks + g->kblk - 1) / g->kblk < 16384) g->kblk >>= 1;
     long per_group = 64L * g->kblk;
     g->nchunks = 64L * ((g->nblocks + per_group - 1) / per_group);
     g->nsuper = (g->nchunks + 255) / 256;

@@ -56,7 +56,6 @@ struct GeomC {
     static constexpr int SZ = D == 3 ? 64 : 16;
     static constexpr int TP = D == 3 ? 31 : 29;
     static constexpr int G = D == 3 ? 5 : 4;
-    static constexpr int K = D == 3 ? 16 : 64;
 };
 
 __device__ __forceinline__ int asr1(uint32_t v) { return (int)v >> 1; }
@@ -259,7 +258,7 @@ __device__ __forceinline__ void block_coords(long b, const long *nb, long &bx, l
 template <int D>
 __global__ __launch_bounds__(64)
 void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, long nblocks,
-                   long nchunks, int minexp, unsigned long long *scratch, long chunk_words,
+                   long nchunks, int kblk, int minexp, unsigned long long *scratch, long chunk_words,
                    unsigned long long *chunk_bits, unsigned int *flags)
 {
     using GC = GeomC<D>;
@@ -270,8 +269,8 @@ void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, 
     const long nb[3] = {nb0, nb1, nb2};
     BitWriter bw{0ull, 0, scratch + c * chunk_words, 0};
     bool nonfinite = false;
-    for (int j = 0; j < GC::K; ++j) {
-        const long b = chunk_block(c, j, GC::K, nblocks);
+    for (int j = 0; j < kblk; ++j) {
+        const long b = chunk_block(c, j, kblk, nblocks);
         if (b < 0) break;
         long bx, by, bz;
         block_coords(b, nb, bx, by, bz);
@@ -559,7 +558,8 @@ template <int D>
 __global__ __launch_bounds__(64)
 void decode_kernel(FieldView f, float *dst, const unsigned char *stream, const unsigned char *pool,
                    const StreamSlot *slots, int slot_index, long nb0, long nb1, long nb2,
-                   long nblocks, long nchunks, long nsuper, long table_bytes, unsigned int *flags)
+                   long nblocks, long nchunks, int kblk, long nsuper, long table_bytes,
+                   unsigned int *flags)
 {
     using GC = GeomC<D>;
     constexpr int SZ = GC::SZ;
@@ -584,8 +584,8 @@ void decode_kernel(FieldView f, float *dst, const unsigned char *stream, const u
     br.w = (const unsigned long long *)(s + 64 + table_bytes);
     br.nw = (long)((pbits + 63) / 64);
     br.seek(sup + rel);
-    for (int j = 0; j < GC::K; ++j) {
-        const long b = chunk_block(c, j, GC::K, nblocks);
+    for (int j = 0; j < kblk; ++j) {
+        const long b = chunk_block(c, j, kblk, nblocks);
         if (b < 0) break;
         float vals[SZ];
         if (br.pos >= pbits) { atomicOr(flags, 4u); return; }
@@ -674,7 +674,10 @@ CodecGeom codec_geom(int ndim, const long n[3])
         g.nb[d] = (n[d] + 3) / 4;
         g.nblocks *= g.nb[d];
     }
+    // K blocks per chunk: 16 (3D) / 64 (2D), halved while the field would
+    // have fewer than 16384 chunks (one lane each), down to 1
     g.kblk = ndim == 3 ? 16 : 64;
+    while (g.kblk > 1 && (g.nblocks + g.kblk - 1) / g.kblk < 16384) g.kblk >>= 1;
     g.size = ndim == 3 ? 64 : 16;
     g.tp = ndim == 3 ? 31 : 29;
     g.guard = ndim == 3 ? 5 : 4;
@@ -705,11 +708,11 @@ void codec_encode(const EncodeArgs &e, hipStream_t st)
     const int nwaves = (int)(g.nchunks / 64);
     if (e.f.ndim == 3)
         hipLaunchKernelGGL(encode_kernel<3>, dim3(nwaves), dim3(64), 0, st, e.f, e.src, g.nb[0], g.nb[1],
-                           g.nb[2], g.nblocks, g.nchunks, minexp, e.scratch, g.max_chunk_words,
+                           g.nb[2], g.nblocks, g.nchunks, g.kblk, minexp, e.scratch, g.max_chunk_words,
                            e.chunk_bits, e.flags);
     else
         hipLaunchKernelGGL(encode_kernel<2>, dim3(nwaves), dim3(64), 0, st, e.f, e.src, g.nb[0], g.nb[1],
-                           g.nb[2], g.nblocks, g.nchunks, minexp, e.scratch, g.max_chunk_words,
+                           g.nb[2], g.nblocks, g.nchunks, g.kblk, minexp, e.scratch, g.max_chunk_words,
                            e.chunk_bits, e.flags);
     const int ntiles = (int)((g.nchunks + TILE - 1) / TILE);
     unsigned long long *tile = e.chunk_off;   // ntiles entries
@@ -767,11 +770,11 @@ void codec_decode(const DecodeArgs &d, hipStream_t st)
     if (d.f.ndim == 3)
         hipLaunchKernelGGL(decode_kernel<3>, dim3(nwaves), dim3(64), 0, st, d.f, d.dst, d.stream, d.pool,
                            d.slots, d.slot_index, g.nb[0], g.nb[1], g.nb[2], g.nblocks, g.nchunks,
-                           g.nsuper, g.table_bytes, d.flags);
+                           g.kblk, g.nsuper, g.table_bytes, d.flags);
     else
         hipLaunchKernelGGL(decode_kernel<2>, dim3(nwaves), dim3(64), 0, st, d.f, d.dst, d.stream, d.pool,
                            d.slots, d.slot_index, g.nb[0], g.nb[1], g.nb[2], g.nblocks, g.nchunks,
-                           g.nsuper, g.table_bytes, d.flags);
+                           g.kblk, g.nsuper, g.table_bytes, d.flags);
 }
 
 }  // namespace fwi

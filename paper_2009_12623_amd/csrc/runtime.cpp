@@ -1018,6 +1018,30 @@ int ckpt_bound(int ndim, const int n[3], size_t *max_bytes)
     });
 }
 
+int fwi_ckpt_pool_bytes(const fwi_grid *g, const fwi_ckpt_cfg *cfg, size_t *bytes)
+{
+    return guarded([&] {
+        if (!g || !bytes) throw Error{FWI_EINVAL, "null argument"};
+        check_cfg(cfg);
+        if (g->ndim != 2 && g->ndim != 3) throw Error{FWI_EINVAL, "ndim must be 2 or 3"};
+        if (g->nt < 1 || g->nbl < 0) throw Error{FWI_EINVAL, "nt must be >= 1 and nbl >= 0"};
+        int comp[3] = {1, 1, 1};
+        for (int d = 0; d < g->ndim; ++d) {
+            if (g->n[d] < 1) throw Error{FWI_EINVAL, "dims must be >= 1"};
+            comp[d] = g->n[d] + 2 * g->nbl;
+        }
+        const int used = max_slot_used(revolve_plan(g->nt, cfg->nslots));
+        size_t per;
+        if (cfg->compress) {
+            const long dims[3] = {comp[0], g->ndim == 3 ? comp[1] : 1, g->ndim == 3 ? comp[2] : comp[1]};
+            per = (size_t)codec_bound(codec_geom(g->ndim, dims)) + 512;    // placement alignment
+        } else {
+            per = make_padded(g->ndim, comp).elems() * sizeof(float);
+        }
+        *bytes = (size_t)2 * (size_t)used * per;
+    });
+}
+
 static FieldView dense_view(int ndim, const int n[3])
 {
     FieldView f;

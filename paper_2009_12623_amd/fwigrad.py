@@ -70,7 +70,7 @@ _lib = None
 EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_stats",
            "fwi_last_error", "fwi_forward", "fwi_gradient", "fwi_forward_ckpt",
            "fwi_backward", "fwi_tape_free", "ckpt_bound", "ckpt_compress",
-           "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune"]
+           "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune", "fwi_ckpt_pool_bytes"]
 
 
 def lib():
@@ -103,6 +103,8 @@ def lib():
     L.fwi_revolve_plan.argtypes = [I, I, ctypes.POINTER(fwi_action), I, ctypes.POINTER(I),
                                    ctypes.POINTER(ctypes.c_longlong)]
     L.fwi_bandwidth_probe.argtypes = [P, P, P, P, ctypes.c_size_t, I, P]
+    L.fwi_ckpt_pool_bytes.argtypes = [ctypes.POINTER(fwi_grid), ctypes.POINTER(fwi_ckpt_cfg),
+                                      ctypes.POINTER(ctypes.c_size_t)]
     L.fwi_autotune.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), I,
                                ctypes.POINTER(fwi_tune_result), P]
     _lib = L
@@ -160,6 +162,16 @@ def fwi_revolve_plan(nsteps: int, nslots: int):
 
 
 # ---------------------------------------------------------------- helpers
+def ckpt_pool_bytes(shot, nslots: int, compress: bool) -> int:
+    """Checkpoint bytes of nslots slots on this shot's grid (exact: exact
+    need; compressed: worst case)."""
+    g = grid_of(shot)
+    cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), 1.0, 0)
+    out = ctypes.c_size_t()
+    check(lib().fwi_ckpt_pool_bytes(ctypes.byref(g), ctypes.byref(cfg), ctypes.byref(out)))
+    return out.value
+
+
 def grid_of(shot) -> fwi_grid:
     """fwi_grid from an object with ndim, shape, h, so, nbl, nt, dt, vmax."""
     g = fwi_grid()
@@ -287,3 +299,76 @@ class Context:
         check(lib().ckpt_decompress(self.h, _ptr(stream), stream.numel(), _ptr(out), len(shape),
                                     _dims3(shape), _stream()))
         return out
+
+
+# ------------------------------------------------------- autograd (Eq. 4)
+class FwiFunction(torch.autograd.Function):
+    """d_sim = F(m) (Eq. 2) as a differentiable torch op.
+
+    forward runs fwi_forward_ckpt, which records d_sim and keeps the
+    checkpoints of the binomial schedule (compressed with atol when
+    ``compress``) in a tape; backward runs fwi_backward, the hand-written
+    adjoint with recomputation from those checkpoints, and returns
+    J^T dd (Eq. 4) on the computational grid.  Only m is differentiable."""
+
+    @staticmethod
+    def forward(fctx, m, wavelet, context, shot, nslots, compress, atol, pool_bytes):
+        if fctx.needs_input_grad[1]:
+            raise NotImplementedError("FwiFunction differentiates with respect to m only")
+        d, tape = context.forward_ckpt(shot, m.detach().contiguous(), wavelet.detach().contiguous(),
+                                       nslots=nslots, compress=compress, atol=atol,
+                                       pool_bytes=pool_bytes)
+        fctx.context, fctx.tape = context, tape
+        # autograd's version counter then rejects in-place changes of m or
+        # the wavelet before backward (the tape reads both)
+        fctx.save_for_backward(m, wavelet)
+        return d
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(fctx, dd):
+        fctx.saved_tensors                     # version check
+        g = fctx.context.backward(fctx.tape, dd.contiguous())
+        fctx.tape.free()
+        fctx.tape = None
+        return g, None, None, None, None, None, None, None
+
+
+class FwiOperator:
+    """Differentiable forward modelling with checkpoint pools sized from use.
+
+    ``op(m, shot, wavelet)`` returns d_sim for one shot; summing a loss over
+    shots and calling ``backward`` gives the FWI gradient with respect to m.
+    Exact checkpoints get exactly the pool they need; compressed ones start
+    from a quarter of the exact size, grow on overflow (the forward pass is
+    then repeated) and afterwards use 1.25x the largest pool seen for the
+    same grid."""
+
+    def __init__(self, context, nslots=40, compress=True, atol=1e-4):
+        self.context, self.nslots, self.compress, self.atol = context, nslots, compress, atol
+        self._pool = {}
+
+    def _key(self, shot):
+        return (shot.ndim, tuple(shot.shape), shot.nbl, shot.nt, self.nslots)
+
+    def __call__(self, m, shot, wavelet):
+        key = self._key(shot)
+        exact = ckpt_pool_bytes(shot, self.nslots, False)
+        if not self.compress:
+            return FwiFunction.apply(m, wavelet, self.context, shot, self.nslots, False,
+                                     self.atol, exact)
+        worst = ckpt_pool_bytes(shot, self.nslots, True)
+        pool = self._pool.get(key, min(worst, max(exact // 4, 1 << 20)))
+        while True:
+            try:
+                d = FwiFunction.apply(m, wavelet, self.context, shot, self.nslots, True,
+                                      self.atol, pool)
+                break
+            except FwiError as e:
+                if e.code != FWI_ECAPACITY or pool >= worst:
+                    raise
+                pool = min(worst, 2 * pool)
+        used = self.context.stats()["pool_high"]
+        grown = int(1.25 * used) + (1 << 20) if used else pool
+        self._pool[key] = min(worst, max(self._pool.get(key, 0), grown))
+        return d

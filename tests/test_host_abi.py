@@ -72,3 +72,25 @@ def test_context_creation_without_device_fails_cleanly():
     h = ctypes.c_void_p()
     rc = F.lib().fwi_ctx_create(ctypes.byref(h), 0, 0)
     assert rc in (F.FWI_EHIP, F.FWI_EINVAL)
+
+
+def test_ckpt_pool_bytes():
+    """exact need = 2 levels x slots in use x one padded level; the
+    compressed worst case covers 2 x slots streams of ckpt_bound bytes; both
+    grow with the slots the schedule uses and stop at nt slots"""
+    import synth
+    shot = synth.tiny_shot(2, n=50, so=8, nbl=6, nt=40)
+    comp = shot.comp_shape
+    e = [F.ckpt_pool_bytes(shot, s, False) for s in (0, 1, 3, 7, 40, 80)]
+    assert e[0] == 0 and e[1] > 0
+    assert e == sorted(e) and e[-1] == e[-2]
+    assert e[1] % 2 == 0 and e[1] // 2 >= 4 * comp[0] * comp[1]   # one padded level
+    for s in (1, 3, 7):
+        used = max((a for op, a, *_ in F.fwi_revolve_plan(40, s)[0] if op == "takeshot"),
+                   default=-1) + 1
+        assert e[[0, 1, 3, 7].index(s)] == used * e[1]
+        w = F.ckpt_pool_bytes(shot, s, True)
+        assert w >= 2 * used * F.ckpt_bound(comp)
+    bad = synth.Shot(2, (0, 10), 10.0, 8, 6, 40, 1e-3, 2500.0, 10.0, (0, 0), shot.rec)
+    with pytest.raises(F.FwiError):
+        F.ckpt_pool_bytes(bad, 3, False)
