@@ -36,6 +36,13 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+def rel_l2(a, b):
+    """||a - b|| / ||b|| in FP64 (device tensors)"""
+    a, b = a.double(), b.double()
+    den = float(b.norm())
+    return float((a - b).norm()) / den if den else (0.0 if float(a.norm()) == 0 else float("inf"))
+
+
 # ------------------------------------------------------------- workloads
 def workload_c3(torch, dev, nt):
     import synth
@@ -197,8 +204,198 @@ def counted_traffic(kernel, shape):
     return None
 
 
+# ------------------------------------------------------------------ C2
+def cpu_codec_baseline(shape, atol, gpu_streams):
+    """Oracle codec (integer-exact C, one thread) on the synthetic 256^3
+    stand-in field; its streams are also compared byte for byte with the
+    GPU's on the same field."""
+    import synth
+    from oracle import codec as ocodec
+    x = synth.wavefield_like(shape, seed=7)
+    t0 = time.time()
+    ref = ocodec.compress(x, atol)
+    te = time.time() - t0
+    t0 = time.time()
+    ocodec.decompress(ref, shape)
+    td = time.time() - t0
+    gb = 4.0 * x.size / 1e9
+    return {"value": round(gb / te, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle compress (%.2f s) and decompress (%.2f s) of a %s synthetic "
+                      "wavefield at atol %g; GB/s of uncompressed input" % (te, td, "x".join(map(str, shape)), atol),
+            "decode_GBs": round(gb / td, 3),
+            "streams_bit_exact": gpu_streams(x) == ref}
+
+
+def run_c2(args, torch, F, dev):
+    """Codec alone: 256^3 snapshots of a 15 Hz point source after 100, 200,
+    300 steps in a layered medium (336^3 propagation grid, SO8); atol swept
+    1e-1 .. 1e-6: ratio, max error, PSNR, compress and decompress GB/s."""
+    import synth
+    shot300 = synth.config2_shot()
+    v = synth.layered_undulating_3d(shot300.shape)
+    m = torch.from_numpy(synth.slowness2(synth.extend(v, shot300.nbl)).astype(np.float32)).to(dev)
+    ctx = F.Context(0, pool_bytes=1 << 30)
+    nb = shot300.nbl
+    snaps = {}
+    for k in (100, 200, 300):
+        sh = synth.config2_shot(nt=k)
+        q = torch.from_numpy(sh.wavelet().astype(np.float32)).to(dev)
+        _, u, _ = ctx.forward_state(sh, m, q)
+        snaps[k] = u[nb:-nb, nb:-nb, nb:-nb].contiguous()
+    x = snaps[300]
+    n = x.numel()
+    ctx.set_timing(True)
+
+    def timed(fn, key, reps):
+        """mean kernel time of one call from the library's HIP events on the
+        launch stream (each call synchronises to return its host outputs)"""
+        for _ in range(2):
+            r = fn()
+        ms = 0.0
+        for _ in range(reps):
+            r = fn()
+            ms += ctx.stats()[key]
+        return r, ms / reps
+
+    rows = []
+    for atol in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        st, te = timed(lambda: ctx.compress(x, atol), "ms_encode", max(args.steps, 5))
+        y, td = timed(lambda: ctx.decompress(st, x.shape), "ms_decode", max(args.steps, 5))
+        err = (y - x).abs().max().item()
+        rng = (x.max() - x.min()).item()
+        mse = ((y.double() - x.double()) ** 2).mean().item()
+        rows.append({"atol": atol, "ratio": round(4.0 * n / st.numel(), 3),
+                     "max_err": float("%.4g" % err), "max_err_over_atol": round(err / atol, 4),
+                     "psnr_db": round(10 * math.log10(rng * rng / mse), 2) if mse else None,
+                     "compress_GBs": round(4.0 * n / (te * 1e-3) / 1e9, 1),
+                     "decompress_GBs": round(4.0 * n / (td * 1e-3) / 1e9, 1),
+                     "compress_ms": round(te, 4), "decompress_ms": round(td, 4)})
+        log(rows[-1])
+        assert err <= atol, (atol, err)
+    trend = {}
+    for k, u in snaps.items():
+        trend[k] = round(4.0 * n / ctx.compress(u, 1e-4).numel(), 3)
+    main = next(r for r in rows if r["atol"] == 1e-4)
+    bytes_enc = 4.0 * n * (1 + 1 / main["ratio"])
+    achieved = bytes_enc / (main["compress_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": main["compress_GBs"], "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 2, "ms_per_step": main["compress_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "codec alone: 256^3 float32 snapshot of a 15 Hz Ricker point source "
+                               "after 300 steps in a 4-layer medium with undulating interfaces "
+                               "(336^3 propagation, SO8), fixed accuracy atol 1e-4; value = "
+                               "compress GB/s of uncompressed input",
+                   "atol_sweep": [r["atol"] for r in rows]},
+        "roofline": {"kernel": "codec_encode (encode + scan + pack)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": bytes_enc,
+                     "note": "algorithmic bytes 4 (1 + 1/CF) per value; the codec is bound by "
+                             "per-lane bit work, not HBM"},
+        "sweep": rows,
+        "ratio_by_step_atol_1e-4": trend,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_codec_baseline(
+            (256, 256, 256), 1e-4,
+            lambda xs: ctx.compress(torch.from_numpy(xs).to(dev), 1e-4).cpu().numpy().tobytes())
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ C4
+def run_c4(args, torch, F, dev):
+    """Batched shots: 32 uneven crops (W in [161, 321]) of a 401x401x201
+    thrust-faulted model at 20 m, SO8, 1500 steps, 40 compressed slots at
+    atol 1e-4; one stencil launch per time step for all shots
+    (fwi_gradient_batch) vs the same shots one at a time (fwi_gradient)."""
+    import synth
+    nt = args.nt or 1500
+    info = synth.config4_shots(nt=nt)
+    t0 = time.time()
+    vt = synth.thrust_3d_torch((401, 401, 201), dev, seed=12626)
+    vs = synth.gauss_smooth_torch(vt, 3.0)
+    shots, m0s, mts = [], [], []
+    for shot, (ox, oy, w) in info:
+        crop = lambda v: v[ox:ox + w, oy:oy + w, :]
+        m0s.append((1.0 / synth.extend_torch(crop(vs), shot.nbl) ** 2).float().contiguous())
+        mts.append((1.0 / synth.extend_torch(crop(vt), shot.nbl) ** 2).float().contiguous())
+        shots.append(shot)
+    del vt, vs
+    npts = sum(int(np.prod(s.comp_shape)) for s in shots)
+    log("32 crops built in %.1f s, %.3g computational points" % (time.time() - t0, npts))
+    q = torch.from_numpy(shots[0].wavelet().astype(np.float32)).to(dev)
+    ctx = F.Context(0, pool_bytes=int(os.environ.get("FWI_POOL_BYTES", 64 << 30)))
+    ctx.set_timing(True)
+    tunes = {}
+    if not args.no_autotune:
+        for s, m in zip(shots, m0s):
+            key = tuple(s.comp_shape)
+            if key not in tunes:
+                tunes[key] = ctx.autotune(s, m, q, steps=2)
+    d_obs = [ctx.forward(s, m, q) for s, m in zip(shots, mts)]
+    torch.cuda.synchronize()
+    nslots = args.slots or 40
+
+    def batched():
+        return ctx.gradient_batch(shots, m0s, q, d_obs, nslots=nslots, compress=True, atol=args.atol)
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for i in range(args.steps):
+        phis, grads = batched()
+        log("batched step %d/%d done" % (i + 1, args.steps))
+    torch.cuda.synchronize()
+    t_b = (time.time() - t0) / args.steps
+    st = ctx.stats()
+    # the same shots one at a time (same schedule and codec settings)
+    t0 = time.time()
+    seq_err = 0.0
+    for s, m, d, g in zip(shots, m0s, d_obs, grads):
+        phi1, g1 = ctx.gradient(s, m, q, d, nslots=nslots, compress=True, atol=args.atol)
+        seq_err = max(seq_err, rel_l2(g1, g))
+    torch.cuda.synchronize()
+    t_s = time.time() - t0
+    # compressed vs exact checkpoints on the first two shots
+    errs = []
+    for s, m, d, g in list(zip(shots, m0s, d_obs, grads))[:2]:
+        _, ge = ctx.gradient(s, m, q, d, nslots=nslots, compress=False)
+        errs.append(rel_l2(g, ge))
+    fwd_ms = st["ms_forward"] / max(st["n_forward"] / len(shots), 1)
+    adj_ms = st["ms_adjoint"] / max(st["n_adjoint"] / len(shots), 1)
+    kinds = {"forward_step_batched": (fwd_ms, 16.0 * npts), "adjoint_imaging_step_batched": (adj_ms, 28.0 * npts)}
+    dom = max(kinds, key=lambda k: kinds[k][0] * (st["n_adjoint"] if "adj" in k else st["n_forward"]))
+    ms, bpl = kinds[dom]
+    achieved = bpl / (ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(t_b / len(shots), 4), "unit": "s/shot", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t_b, 1),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched 3D gradients: 32 shots on uneven crops (W 161-321) of a "
+                               "401x401x201 thrust-faulted model at 20 m (+40 layer), SO8, %d steps, "
+                               "%d compressed slots at atol %g; one stencil launch per step for all "
+                               "shots" % (nt, nslots, args.atol),
+                   "computational_points_total": npts},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_ms": round(ms, 4), "bytes_per_launch": bpl},
+        "s_per_batch": round(t_b, 3),
+        "one_at_a_time_s_per_shot": round(t_s / len(shots), 4),
+        "speedup_batched_vs_one_at_a_time": round(t_s / t_b, 3),
+        "batched_equals_one_at_a_time_rel_l2": seq_err,
+        "grad_rel_l2_compressed_vs_exact_first_shots": [float("%.3e" % e) for e in errs],
+        "kernel_ms": {k: round(st[k], 1) for k in ("ms_forward", "ms_adjoint", "ms_encode", "ms_decode", "ms_total")},
+        "ckpt_compression_factor": round(st["ckpt_raw_bytes"] / max(st["ckpt_bytes"], 1), 2),
+    }
+    print(json.dumps(out), flush=True)
+
+
 # ------------------------------------------------------------------ C5
-def run_c5(args, torch, F, metrics, dev):
+def run_c5(args, torch, F, dev):
     """Differentiable 2D FWI gradient: 16 shots through FwiOperator (autograd),
     1001x401 at 10 m (1081x481 with the layer), SO16, 3000 steps, 40 slots,
     compressed checkpoints vs exact ones."""
@@ -247,7 +444,7 @@ def run_c5(args, torch, F, metrics, dev):
     torch.cuda.synchronize()
     t_c = (time.time() - t0) / args.steps
     st = ctx.stats()            # last call: the backward of the last shot
-    err = metrics.rel_l2(g_c.cpu().numpy(), g_u.cpu().numpy())
+    err = rel_l2(g_c, g_u)
     npts = int(np.prod(shots[0].comp_shape))
     nf, nenc, rr, ra = schedule_counts(F, nt, nslots)
     out = {
@@ -288,7 +485,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5"])
     ap.add_argument("--nt", type=int, default=None)
     ap.add_argument("--atol", type=float, default=1e-4)
     ap.add_argument("--slots", type=int, default=0, help="compressed slots (0: cost model)")
@@ -305,7 +502,6 @@ def main():
 
     import torch
     import paper_2009_12623_amd.fwigrad as F
-    from oracle import metrics
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
@@ -330,7 +526,13 @@ def main():
         print(json.dumps(res))
         return
     if args.workload == "c5":
-        run_c5(args, torch, F, metrics, dev)
+        run_c5(args, torch, F, dev)
+        return
+    if args.workload == "c2":
+        run_c2(args, torch, F, dev)
+        return
+    if args.workload == "c4":
+        run_c4(args, torch, F, dev)
         return
     wl = workload_c3 if args.workload == "c3" else workload_c1
     nt = args.nt or (2000 if args.workload == "c3" else 500)
@@ -367,7 +569,7 @@ def main():
     torch.cuda.synchronize()
     t_pilot = time.time() - t0
     st_p = ctx.stats()
-    err_p = metrics.rel_l2(g_p.cpu().numpy(), g_u.cpu().numpy())
+    err_p = rel_l2(g_p, g_u)
     log("pilot compressed s=%d: %.2f s, rel err %.2e, %d B/field" %
         (s_unc, t_pilot, err_p, st_p["ckpt_bytes"] // max(st_p["n_encode"], 1)))
     if args.slots:
@@ -402,7 +604,7 @@ def main():
     t1 = time.time()
     st = ctx.stats()
     s_per_shot = (t1 - t0) / args.steps
-    err = metrics.rel_l2(g_c.cpu().numpy(), g_u.cpu().numpy())
+    err = rel_l2(g_c, g_u)
 
     # roofline of the dominant kernel (time-weighted), from HIP events on the
     # stream the kernels run on

@@ -126,6 +126,15 @@ int fwi_ctx_destroy(fwi_ctx *ctx);
 /* Collect per-kernel HIP-event timings in later calls (small overhead). */
 int fwi_ctx_set_timing(fwi_ctx *ctx, int on);
 int fwi_ctx_stats(const fwi_ctx *ctx, fwi_stats *out);
+/* Captured schedules: with on != 0, fwi_gradient and fwi_gradient_batch
+ * record the whole checkpoint schedule of a call (every step, codec and
+ * receiver launch) into a hipGraph the first time a call signature (grid,
+ * shot, pointers, checkpoint config, launch shapes) is seen, and replay it on
+ * later calls with the same signature; a graph is re-captured after any of
+ * the library's buffers is reallocated.  Results are identical to direct
+ * launches.  Per-kernel timings are not collected during replays; launch
+ * counts are.  Off by default; off drops every graph. */
+int fwi_ctx_set_graphs(fwi_ctx *ctx, int on);
 /* Message of the last failure on this thread (static storage). */
 const char *fwi_last_error(void);
 
@@ -133,6 +142,13 @@ const char *fwi_last_error(void);
  * squared slowness s^2/m^2]. */
 int fwi_forward(fwi_ctx *ctx, const fwi_grid *g, const float *m,
                 const fwi_shot *shot, float *d_sim, hipStream_t stream);
+
+/* fwi_forward that also returns the last two levels u^nt and u^{nt-1}
+ * [device, computational grid, either may be NULL]: wavefield snapshots
+ * for codec studies (Sec. 3 "Evolution of compressibility"). */
+int fwi_forward_state(fwi_ctx *ctx, const fwi_grid *g, const float *m,
+                      const fwi_shot *shot, float *d_sim, float *u_last,
+                      float *u_prev, hipStream_t stream);
 
 /* Eqs. (3)-(4): Phi [host] and grad [device, computational grid,
  * overwritten] for observed data d_obs [device, nt x nrec], with the
@@ -143,6 +159,21 @@ int fwi_gradient(fwi_ctx *ctx, const fwi_grid *g, const float *m,
                  const fwi_shot *shot, const float *d_obs,
                  const fwi_ckpt_cfg *cfg, float *grad, double *phi,
                  hipStream_t stream);
+
+/* Eqs. (3)-(4) for nshots shots at once: shots that share ndim, space
+ * order, nt and dt (grid dims, nbl, h, vmax, source and receivers may
+ * differ, e.g. uneven apertures of one survey).  All shots follow one
+ * checkpoint schedule; every time step is a single stencil launch over all
+ * shots; checkpoints are taken per shot.  Arrays of nshots entries [host]:
+ * grids, models[i] [device, shot i's computational grid], shots, d_obs[i]
+ * [device, nt x nrec_i], grads[i] [device, overwritten], phis[i] [host].
+ * cfg is shared; cfg.pool_bytes (0 = the context's pool size) is the total
+ * for all shots, split in proportion to their field sizes.  Each shot's
+ * results equal fwi_gradient's for that shot bit for bit. */
+int fwi_gradient_batch(fwi_ctx *ctx, int nshots, const fwi_grid *grids,
+                       const float *const *models, const fwi_shot *shots,
+                       const float *const *d_obs, const fwi_ckpt_cfg *cfg,
+                       float *const *grads, double *phis, hipStream_t stream);
 
 /* Split form for automatic differentiation: the forward sweep writes d_sim
  * and keeps its checkpoints in a new tape (owns device memory until

@@ -61,6 +61,20 @@ struct StepParams {
 void launch_step(const StepParams &p, int ndim, int radius, bool adjoint,
                  hipStream_t st);
 
+// One shot's part of a batched step launch.
+struct BatchEntry {
+    StepParams p;
+    int first;                       // first workgroup of this shot in the launch
+    int ntz, nty, nwg, launched;     // tile counts (3D: launched = nwg rounded to 8)
+};
+// tile counts of e.p (3D uses e.p.rpl); returns the workgroups the shot
+// needs, receiver-sampling workgroups included
+int step_geometry(BatchEntry &e, int ndim, bool adjoint);
+// tab: device array of nshot entries with increasing `first`; total = the
+// last entry's first + its workgroups.  3D batches use 2 rows per lane.
+void launch_step_batch(const BatchEntry *tab, int nshot, int total, int ndim, int radius,
+                       bool adjoint, hipStream_t st);
+
 // unpadded computational grid <-> padded layout
 struct PadMap {
     long nx, ny, nz;        // computational dims (ny = 1 in 2D)
@@ -69,6 +83,8 @@ struct PadMap {
 };
 void launch_coef(const float *m, float *b_padded, const PadMap &pm, double dt, hipStream_t st);
 void launch_unpad(const float *acc_padded, float *g, const PadMap &pm, hipStream_t st);
+void launch_fill_zero(float *p, size_t n, hipStream_t st);
+void launch_copy(float *dst, const float *src, size_t n, hipStream_t st);
 void launch_probe(const float *a, const float *b, const float *c, float *d, size_t n, int nsrc,
                   hipStream_t st);
 void launch_gather(const float *field_origin, const int *rec_off, int nrec,

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -49,6 +50,10 @@ struct Error {
             throw Error{FWI_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)};         \
     } while (0)
 
+// bumped whenever any library buffer is (re)allocated: captured schedules
+// embed buffer addresses and are valid only for the generation they saw
+unsigned long long g_alloc_gen = 0;
+
 template <class T>
 struct DevBuf {
     T *p = nullptr;
@@ -66,6 +71,7 @@ struct DevBuf {
                                         " bytes failed"};
         }
         n = want;
+        ++g_alloc_gen;
         if (zero) HIPCHK(hipMemset(p, 0, want * sizeof(T)));
     }
     void release()
@@ -88,6 +94,63 @@ struct FieldPtr {
 constexpr size_t ARENA_ALIGN = size_t(2) << 20;
 constexpr size_t ARENA_STAGGER = size_t(12) << 10;
 
+// Device state of one shot's gradient: the six padded arrays (one arena),
+// receiver tables, recorded data, residual, reduction buffers and the
+// counters of its checkpoint stream stack.  A context holds one for the
+// single-shot calls and one per shot for batched calls.
+struct ShotBufs {
+    DevBuf<char> arena;
+    size_t arena_stride = 0;
+    size_t padded_elems = 0;
+    FieldPtr fa, fb, la, lb, coef, gacc;
+    DevBuf<int> rec_off, node_pad;
+    DevBuf<int> node_xyz, rec_ptr, rec_idx;
+    DevBuf<float> dsim, res;
+    DevBuf<double> partials, phi;
+    DevBuf<unsigned long long> misc;     // stream bytes, pool high-water, total bytes
+    DevBuf<StreamSlot> slots;
+    void release()
+    {
+        FieldPtr *arr[6] = {&fa, &fb, &la, &lb, &coef, &gacc};
+        for (FieldPtr *a : arr) a->release();
+        arena.release();
+        padded_elems = 0;
+        rec_off.release(); node_pad.release(); node_xyz.release(); rec_ptr.release();
+        rec_idx.release(); dsim.release(); res.release(); partials.release(); phi.release();
+        misc.release(); slots.release();
+    }
+};
+
+// Launch tables of batched steps: one BatchEntry per shot per launch, staged
+// in pinned host memory and copied to the device just before the launch.
+// Every launch of a call has its own slot, and a call ends with a stream
+// synchronisation, so no copy overwrites a table a queued launch reads.
+struct BatchTables {
+    BatchEntry *host = nullptr;
+    DevBuf<BatchEntry> dev;
+    size_t cap = 0, used = 0;
+    void ensure(size_t n)
+    {
+        used = 0;
+        if (n <= cap) return;
+        release();
+        if (hipHostMalloc((void **)&host, n * sizeof(BatchEntry), hipHostMallocDefault) != hipSuccess) {
+            host = nullptr;
+            (void)hipGetLastError();
+            throw Error{FWI_ENOMEM, "pinned allocation of launch tables failed"};
+        }
+        dev.ensure(n);
+        cap = n;
+    }
+    void release()
+    {
+        if (host) (void)hipHostFree(host);
+        host = nullptr;
+        dev.release();
+        cap = used = 0;
+    }
+};
+
 enum Kind { K_FWD = 0, K_ADJ = 1, K_ENC = 2, K_DEC = 3, K_NKIND = 4 };
 
 }  // namespace
@@ -96,24 +159,41 @@ struct fwi_ctx {
     int device = 0;
     size_t pool_default = 0;
     DevBuf<unsigned char> pool;
-    // working fields, coefficient b = dt^2/m and gradient accumulator, all
-    // in the padded layout
-    // the six padded arrays a time step touches, carved from one arena
-    DevBuf<char> arena;
-    size_t arena_stride = 0;
-    FieldPtr fa, fb, la, lb, coef, gacc;
-    size_t padded_elems = 0;
+    // single-shot device state (fields, receivers, data, reductions)
+    ShotBufs sb;
+    // per-shot device state of batched calls
+    std::vector<std::unique_ptr<ShotBufs>> batch;
+    BatchTables btab;
     // codec scratch
     DevBuf<unsigned long long> scratch, chunk_bits, chunk_off, misc;
     DevBuf<StreamSlot> slots;
     DevBuf<unsigned int> flags;
-    DevBuf<double> partials, phi;
-    // receivers
-    DevBuf<int> rec_off, node_pad;
-    DevBuf<int> node_xyz, rec_ptr, rec_idx;
-    DevBuf<float> dsim, res;
     // timing
     bool timing = false;
+    // captured schedules: one hipGraph per call signature, replayed while
+    // no library buffer has been reallocated since the capture
+    bool graphs = false;
+    bool capturing = false;
+    struct GraphEntry {
+        hipGraphExec_t exec = nullptr;
+        unsigned long long gen = 0;
+        long long n_forward = 0, n_adjoint = 0, n_encode = 0, n_decode = 0;
+        long long ckpt_raw_bytes = 0, ckpt_bytes_host = 0;
+        BatchEntry *tables = nullptr;      // batched launch tables of this graph
+    };
+    std::map<std::string, GraphEntry> gcache;
+    // the legacy null stream cannot be captured: schedules of calls made on
+    // it run on this stream, ordered with events
+    hipStream_t gstream = nullptr;
+    hipEvent_t gfence[2] = {nullptr, nullptr};
+    void drop_graphs()
+    {
+        for (auto &kv : gcache) {
+            if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+            if (kv.second.tables) (void)hipFree(kv.second.tables);
+        }
+        gcache.clear();
+    }
     // stencil launch shape; overridden per grid by fwi_autotune
     int xchunk3 = 0;           // 3D x planes per workgroup (0: default)
     int rpl3 = 2;              // 3D rows per lane
@@ -302,23 +382,23 @@ void upload(DevBuf<T> &b, const std::vector<T> &v, hipStream_t st)
 }
 
 // point the six arrays into the arena
-void carve_fields(fwi_ctx *c)
+void carve_fields(ShotBufs *b)
 {
-    FieldPtr *arr[6] = {&c->fa, &c->fb, &c->la, &c->lb, &c->coef, &c->gacc};
+    FieldPtr *arr[6] = {&b->fa, &b->fb, &b->la, &b->lb, &b->coef, &b->gacc};
     for (int i = 0; i < 6; ++i)
-        arr[i]->p = (float *)(c->arena.p + (size_t)i * (c->arena_stride + ARENA_STAGGER));
+        arr[i]->p = (float *)(b->arena.p + (size_t)i * (b->arena_stride + ARENA_STAGGER));
 }
 
-void ensure_fields(fwi_ctx *c, const Setup &s)
+void ensure_fields(ShotBufs *b, const Setup &s)
 {
     const size_t pe = s.pad.elems();
-    if (pe != c->padded_elems) {
-        c->arena.release();
-        c->padded_elems = 0;
-        c->arena_stride = (pe * sizeof(float) + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
-        c->arena.ensure(6 * (c->arena_stride + ARENA_STAGGER), true);
-        c->padded_elems = pe;
-        carve_fields(c);
+    if (pe != b->padded_elems) {
+        b->arena.release();
+        b->padded_elems = 0;
+        b->arena_stride = (pe * sizeof(float) + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN;
+        b->arena.ensure(6 * (b->arena_stride + ARENA_STAGGER), true);
+        b->padded_elems = pe;
+        carve_fields(b);
     }
 }
 
@@ -342,7 +422,7 @@ void ensure_codec(fwi_ctx *c, const FieldView &f, int nslot_entries)
     c->chunk_off.ensure((size_t)((g.nchunks + 1023) / 1024) + 2);
     c->misc.ensure(4);
     c->flags.ensure(1);
-    c->slots.ensure((size_t)std::max(nslot_entries, 1));
+    c->sb.slots.ensure((size_t)std::max(nslot_entries, 1));
 }
 
 // ---------------------------------------------------------------- timing
@@ -353,7 +433,7 @@ struct Timer {
     int kind;
     Timer(fwi_ctx *c_, hipStream_t st_, int k) : c(c_), st(st_), kind(k)
     {
-        if (c->timing) {
+        if (c->timing && !c->capturing) {
             a = c->ev();
             HIPCHK(hipEventRecord(a, st));
         }
@@ -410,6 +490,8 @@ struct Exec {
     hipStream_t st;
     const float *m;
     const fwi_shot *shot;
+    ShotBufs *B = &c->sb;
+    unsigned long long *misc = nullptr;  // counters of the stream stack (set with the pool)
     float *cur = nullptr, *prev = nullptr;
     bool prev_valid = true;
     int work = 0;
@@ -431,8 +513,8 @@ struct Exec {
 
     // cur/prev/l1/l2 are allocation bases of padded arrays
     float *at_origin(float *base) const { return base + S.pad.origin; }
-    float *W0() const { return c->fa.p; }
-    float *W1() const { return c->fb.p; }
+    float *W0() const { return B->fa.p; }
+    float *W1() const { return B->fb.p; }
     bool in_w(const float *p) const { return p == W0() || p == W1(); }
 
     PadMap padmap() const
@@ -449,26 +531,26 @@ struct Exec {
 
     void init_fields()
     {
-        launch_coef(m, c->coef.p, padmap(), S.dt, st);
-        HIPCHK(hipMemsetAsync(c->fa.p, 0, c->padded_elems * sizeof(float), st));
-        HIPCHK(hipMemsetAsync(c->fb.p, 0, c->padded_elems * sizeof(float), st));
+        launch_coef(m, B->coef.p, padmap(), S.dt, st);
+        HIPCHK(hipMemsetAsync(B->fa.p, 0, B->padded_elems * sizeof(float), st));
+        HIPCHK(hipMemsetAsync(B->fb.p, 0, B->padded_elems * sizeof(float), st));
         cur = W0();
         prev = W1();
         work = 0;
-        upload(c->rec_off, S.rec_pad, st);
+        upload(B->rec_off, S.rec_pad, st);
     }
 
     void init_adjoint()
     {
-        HIPCHK(hipMemsetAsync(c->la.p, 0, c->padded_elems * sizeof(float), st));
-        HIPCHK(hipMemsetAsync(c->lb.p, 0, c->padded_elems * sizeof(float), st));
-        l1 = c->la.p;
-        l2 = c->lb.p;
-        HIPCHK(hipMemsetAsync(c->gacc.p, 0, c->padded_elems * sizeof(float), st));
-        upload(c->node_pad, S.node_pad, st);
-        upload(c->node_xyz, S.node_xyz, st);
-        upload(c->rec_ptr, S.rec_ptr, st);
-        upload(c->rec_idx, S.rec_idx, st);
+        HIPCHK(hipMemsetAsync(B->la.p, 0, B->padded_elems * sizeof(float), st));
+        HIPCHK(hipMemsetAsync(B->lb.p, 0, B->padded_elems * sizeof(float), st));
+        l1 = B->la.p;
+        l2 = B->lb.p;
+        HIPCHK(hipMemsetAsync(B->gacc.p, 0, B->padded_elems * sizeof(float), st));
+        upload(B->node_pad, S.node_pad, st);
+        upload(B->node_xyz, S.node_xyz, st);
+        upload(B->rec_ptr, S.rec_ptr, st);
+        upload(B->rec_idx, S.rec_idx, st);
     }
 
     std::vector<int> grid_key() const
@@ -489,7 +571,7 @@ struct Exec {
     StepParams params() const
     {
         StepParams p{};
-        p.b = c->coef.p;
+        p.b = B->coef.p;
         p.psx = S.pad.sx;
         p.psy = S.ndim == 3 ? S.pad.sy : 0;
         p.origin = S.pad.origin;
@@ -509,32 +591,49 @@ struct Exec {
         return p;
     }
 
-    void advance(int a, int b, bool record)
+    // parameters of the forward step that produces level k (out chosen so
+    // the two working buffers alternate and checkpoint memory is never written)
+    StepParams fwd_params(int k, bool record)
     {
-        if (work != a) throw Error{FWI_EINVAL, "internal: advance from a state not held"};
-        if (!prev_valid) throw Error{FWI_EINVAL, "internal: advance without the older level"};
-        Timer tm(c, st, K_FWD);
         StepParams p = params();
         apply_shape(p, false);
         p.src = S.src_pad;
         p.wav = shot->wavelet;
-        p.rec_off = c->rec_off.p;
+        p.rec_off = B->rec_off.p;
         p.nrec = S.nrec;
+        p.u1 = cur;
+        p.u2 = prev;
+        p.out = in_w(prev) ? prev : (cur == W0() ? W1() : W0());
+        p.step = k - 1;
+        // the launch samples the level it reads, u^{k-1}, on first visit
+        p.grow = nullptr;
+        if (record && k - 1 >= 1 && k - 1 > reached) {
+            p.grow = dsim + (size_t)(k - 2) * S.nrec;
+            reached = k - 1;
+        }
+        return p;
+    }
+
+    void fwd_commit(const StepParams &p)
+    {
+        prev = cur;
+        cur = p.out;
+    }
+
+    void check_advance(int a) const
+    {
+        if (work != a) throw Error{FWI_EINVAL, "internal: advance from a state not held"};
+        if (!prev_valid) throw Error{FWI_EINVAL, "internal: advance without the older level"};
+    }
+
+    void advance(int a, int b, bool record)
+    {
+        check_advance(a);
+        Timer tm(c, st, K_FWD);
         for (int k = a + 1; k <= b; ++k) {
-            float *out = in_w(prev) ? prev : (cur == W0() ? W1() : W0());
-            p.u1 = cur;
-            p.u2 = prev;
-            p.out = out;
-            p.step = k - 1;
-            // the launch samples the level it reads, u^{k-1}, on first visit
-            p.grow = nullptr;
-            if (record && k - 1 >= 1 && k - 1 > reached) {
-                p.grow = dsim + (size_t)(k - 2) * S.nrec;
-                reached = k - 1;
-            }
+            const StepParams p = fwd_params(k, record);
             launch_step(p, S.ndim, S.R, false, st);
-            prev = cur;
-            cur = out;
+            fwd_commit(p);
         }
         c->stats.n_forward += b - a;
         work = b;
@@ -544,7 +643,7 @@ struct Exec {
     void flush_record()
     {
         if (dsim && work >= 1 && work > reached) {
-            launch_gather(cur, c->rec_off.p, S.nrec, dsim + (size_t)(work - 1) * S.nrec, st);
+            launch_gather(cur, B->rec_off.p, S.nrec, dsim + (size_t)(work - 1) * S.nrec, st);
             reached = work;
         }
     }
@@ -559,9 +658,8 @@ struct Exec {
         c->stats.ckpt_raw_bytes += (long long)levels * (long long)S.ncomp * 4;
         if (!compress) {
             const size_t off = (size_t)(2 * slot) * raw_bytes;
-            HIPCHK(hipMemcpyAsync(pool + off, cur, raw_bytes, hipMemcpyDeviceToDevice, st));
-            if (both)
-                HIPCHK(hipMemcpyAsync(pool + off + raw_bytes, prev, raw_bytes, hipMemcpyDeviceToDevice, st));
+            launch_copy((float *)(pool + off), cur, raw_bytes / sizeof(float), st);
+            if (both) launch_copy((float *)(pool + off + raw_bytes), prev, raw_bytes / sizeof(float), st);
             c->stats.ckpt_bytes += (long long)levels * (long long)raw_bytes;
             c->stats.pool_high = std::max<long long>(c->stats.pool_high,
                                                      (long long)(off + (size_t)levels * raw_bytes));
@@ -584,9 +682,9 @@ struct Exec {
             // streams are stacked: this one starts after the last stream of
             // the slot below (or after level 0 of this slot)
             e.prev_index = lev == 1 ? 2 * slot : (slot == 0 ? -1 : 2 * (slot - 1) + (slot_both[slot - 1] ? 1 : 0));
-            e.out_bytes = c->misc.p + 0;
-            e.pool_high = c->misc.p + 1;
-            e.total_bytes = c->misc.p + 2;
+            e.out_bytes = misc + 0;
+            e.pool_high = misc + 1;
+            e.total_bytes = misc + 2;
             e.flags = c->flags.p;
             codec_encode(e, st);
             c->stats.n_encode += 1;
@@ -596,8 +694,8 @@ struct Exec {
     void restore(int slot, int k, bool only_cur)
     {
         if (slot < 0) {
-            HIPCHK(hipMemsetAsync(c->fa.p, 0, c->padded_elems * sizeof(float), st));
-            HIPCHK(hipMemsetAsync(c->fb.p, 0, c->padded_elems * sizeof(float), st));
+            launch_fill_zero(B->fa.p, B->padded_elems, st);
+            launch_fill_zero(B->fb.p, B->padded_elems, st);
             cur = W0();
             prev = W1();
             prev_valid = true;
@@ -627,34 +725,43 @@ struct Exec {
         work = k;
     }
 
-    void reverse(int k)
+    // residual and Phi before the first adjoint step
+    void pre_reverse(int k)
     {
         if (work != k) throw Error{FWI_EINVAL, "internal: reverse without its state"};
         if (!adj_src) {
             flush_record();
             const size_t n = (size_t)S.nt * S.nrec;
-            launch_residual(dsim, d_obs, c->res.p, n, c->partials.p, (int)c->partials.n, c->phi.p, st);
-            adj_src = c->res.p;
+            launch_residual(dsim, d_obs, B->res.p, n, B->partials.p, (int)B->partials.n, B->phi.p, st);
+            adj_src = B->res.p;
         }
-        Timer tm(c, st, K_ADJ);
+    }
+
+    StepParams adj_params()
+    {
         StepParams p = params();
         apply_shape(p, true);
         p.u1 = l1;
         p.u2 = l2;
         p.out = l2;
         p.uk = cur;
-        p.g = c->gacc.p;
-        launch_step(p, S.ndim, S.R, true, st);
+        p.g = B->gacc.p;
+        return p;
+    }
+
+    // receiver residuals into the new adjoint level (and their imaging term)
+    void post_reverse(int k)
+    {
         InjectParams ip{};
         ip.lam = l2;
-        ip.g = c->gacc.p;
+        ip.g = B->gacc.p;
         ip.uk = cur;
-        ip.b = c->coef.p;
+        ip.b = B->coef.p;
         ip.res_row = adj_src + (size_t)(k - 1) * S.nrec;
-        ip.node_pad = c->node_pad.p;
-        ip.node_xyz = c->node_xyz.p;
-        ip.rec_ptr = c->rec_ptr.p;
-        ip.rec_idx = c->rec_idx.p;
+        ip.node_pad = B->node_pad.p;
+        ip.node_xyz = B->node_xyz.p;
+        ip.rec_ptr = B->rec_ptr.p;
+        ip.rec_idx = B->rec_idx.p;
         ip.nnode = (int)S.node_pad.size();
         ip.nx = S.pad.nx;
         ip.ny = S.pad.ny;
@@ -666,6 +773,16 @@ struct Exec {
         launch_inject(ip, st);
         std::swap(l1, l2);
         c->stats.n_adjoint += 1;
+    }
+
+    void reverse(int k)
+    {
+        pre_reverse(k);
+        {
+            Timer tm(c, st, K_ADJ);
+            launch_step(adj_params(), S.ndim, S.R, true, st);
+        }
+        post_reverse(k);
     }
 
     // run acts[from, to); stops before the first REVERSE if stop_at_reverse
@@ -752,7 +869,8 @@ void setup_ckpt(Exec &ex, const fwi_ckpt_cfg *cfg, unsigned char *pool, size_t c
     ex.pool = pool;
     ex.pool_cap = cap;
     ex.slots = slots;
-    ex.raw_bytes = ex.c->padded_elems * sizeof(float);
+    ex.raw_bytes = ex.B->padded_elems * sizeof(float);
+    if (!ex.misc) ex.misc = ex.c->misc.p;
     if (!ex.compress && (size_t)nslots_used * 2 * ex.raw_bytes > cap)
         throw Error{FWI_ECAPACITY, "pool of " + std::to_string(cap) + " bytes cannot hold " +
                                        std::to_string(nslots_used) + " exact checkpoints"};
@@ -798,6 +916,207 @@ int guarded(F &&f)
     }
 }
 
+// ------------------------------------------------------------ batched shots
+// Walks one action list for several shots in lock step.  Every time step is
+// one launch of the batched stencil over all shots; checkpoint and
+// receiver work stays per shot (each shot has its own stream stack).
+struct BatchExec {
+    fwi_ctx *c;
+    hipStream_t st;
+    std::vector<Exec> &ex;
+    int ndim, R;
+    BatchEntry *dev_base;      // device tables the launches read
+    bool upload;               // copy each table before its launch (eager runs)
+    std::vector<StepParams> ps;
+
+    void launch(bool adj)
+    {
+        const int n = (int)ex.size();
+        BatchTables &t = c->btab;
+        if (t.used + (size_t)n > t.cap) throw Error{FWI_EINVAL, "internal: launch tables exhausted"};
+        BatchEntry *h = t.host + t.used;
+        int first = 0;
+        for (int i = 0; i < n; ++i) {
+            h[i] = BatchEntry{};
+            h[i].p = ps[i];
+            h[i].p.rpl = 2;             // the batched 3D kernel uses 2 rows per lane
+            h[i].first = first;
+            first += step_geometry(h[i], ndim, adj);
+        }
+        BatchEntry *d = dev_base + t.used;
+        if (upload) HIPCHK(hipMemcpyAsync(d, h, (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice, st));
+        launch_step_batch(d, n, first, ndim, R, adj, st);
+        t.used += n;
+    }
+
+    void advance(int a, int b)
+    {
+        for (auto &e : ex) e.check_advance(a);
+        Timer tm(c, st, K_FWD);
+        ps.resize(ex.size());
+        for (int k = a + 1; k <= b; ++k) {
+            for (size_t i = 0; i < ex.size(); ++i) ps[i] = ex[i].fwd_params(k, true);
+            launch(false);
+            for (size_t i = 0; i < ex.size(); ++i) ex[i].fwd_commit(ps[i]);
+        }
+        for (auto &e : ex) e.work = b;
+        c->stats.n_forward += (long long)(b - a) * (long long)ex.size();
+    }
+
+    void reverse(int k)
+    {
+        for (auto &e : ex) e.pre_reverse(k);
+        ps.resize(ex.size());
+        {
+            Timer tm(c, st, K_ADJ);
+            for (size_t i = 0; i < ex.size(); ++i) ps[i] = ex[i].adj_params();
+            launch(true);
+        }
+        for (auto &e : ex) e.post_reverse(k);
+    }
+
+    void run(const std::vector<fwi_action> &acts, const std::vector<char> &both)
+    {
+        for (size_t i = 0; i < acts.size(); ++i) {
+            const fwi_action &a = acts[i];
+            switch (a.op) {
+            case FWI_ADVANCE: advance(a.a, a.b); break;
+            case FWI_TAKESHOT:
+                for (auto &e : ex) e.takeshot(a.a, a.b, both[i] != 0);
+                break;
+            case FWI_RESTORE: {
+                const bool only = ex[0].compress && i + 1 < acts.size() && acts[i + 1].op == FWI_REVERSE;
+                for (auto &e : ex) e.restore(a.a, a.b, only);
+                break;
+            }
+            case FWI_REVERSE: reverse(a.a); break;
+            case FWI_FREE: break;
+            default: throw Error{FWI_EINVAL, "internal: bad action"};
+            }
+        }
+    }
+};
+
+// batched launches one action list needs (one per forward step, one per reverse step)
+size_t launches_of(const std::vector<fwi_action> &acts)
+{
+    size_t n = 0;
+    for (auto &a : acts) {
+        if (a.op == FWI_ADVANCE) n += (size_t)(a.b - a.a);
+        else if (a.op == FWI_REVERSE) n += 1;
+    }
+    return n;
+}
+
+// ------------------------------------------------------- captured schedules
+struct KeyBuilder {
+    std::string s;
+    template <class T>
+    KeyBuilder &add(const T &v)
+    {
+        s.append((const char *)&v, sizeof(T));
+        return *this;
+    }
+    KeyBuilder &bytes(const void *p, size_t n)
+    {
+        unsigned long long h = 1469598103934665603ull;     // FNV-1a
+        for (size_t i = 0; i < n; ++i) h = (h ^ ((const unsigned char *)p)[i]) * 1099511628211ull;
+        return add(h).add(n);
+    }
+};
+
+void key_shot(KeyBuilder &k, fwi_ctx *c, const fwi_grid *g, const fwi_shot *sh, const Setup &S)
+{
+    k.add(g->ndim).add(g->n).add(g->h).add(g->space_order).add(g->nbl).add(g->nt).add(g->dt).add(g->vmax);
+    k.add(sh->src).add(sh->wavelet).add(sh->nrec);
+    k.bytes(sh->rec, sizeof(int32_t) * (size_t)sh->nrec * (size_t)g->ndim);
+    auto it = c->tuned.find({S.ndim, S.pad.nx, S.pad.ny, S.pad.nz, S.R});
+    if (it != c->tuned.end()) k.add(it->second.first).add(it->second.second);
+    k.add(c->xchunk3).add(c->rpl3).add(c->remap3);
+}
+
+// Enqueue a schedule: directly, or (graphs on) by replaying the graph
+// captured for `key`, capturing it first if needed.  `issue(tables)` enqueues
+// every launch of the schedule; batched runs get a device table buffer owned
+// by the graph (filled once after the capture) in place of per-launch copies.
+template <class Issue>
+void run_schedule(fwi_ctx *c, hipStream_t caller, const std::string &key, size_t table_entries, Issue &&issue)
+{
+    if (!c->graphs) {
+        issue((BatchEntry *)nullptr, caller);
+        return;
+    }
+    hipStream_t st = caller;
+    if (!caller) {
+        if (!c->gstream) {
+            HIPCHK(hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&c->gfence[0], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&c->gfence[1], hipEventDisableTiming));
+        }
+        st = c->gstream;
+        HIPCHK(hipEventRecord(c->gfence[0], caller));
+        HIPCHK(hipStreamWaitEvent(st, c->gfence[0], 0));
+    }
+    auto it = c->gcache.find(key);
+    if (it != c->gcache.end() && it->second.gen != g_alloc_gen) {
+        if (it->second.exec) (void)hipGraphExecDestroy(it->second.exec);
+        if (it->second.tables) (void)hipFree(it->second.tables);
+        c->gcache.erase(it);
+        it = c->gcache.end();
+    }
+    if (it == c->gcache.end()) {
+        fwi_ctx::GraphEntry ge;
+        if (table_entries && hipMalloc((void **)&ge.tables, table_entries * sizeof(BatchEntry)) != hipSuccess) {
+            (void)hipGetLastError();
+            throw Error{FWI_ENOMEM, "allocation of captured launch tables failed"};
+        }
+        const fwi_stats before = c->stats;
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        c->capturing = true;
+        try {
+            issue(ge.tables, st);
+        } catch (...) {
+            c->capturing = false;
+            (void)hipStreamEndCapture(st, &g);
+            if (g) (void)hipGraphDestroy(g);
+            if (ge.tables) (void)hipFree(ge.tables);
+            throw;
+        }
+        c->capturing = false;
+        HIPCHK(hipStreamEndCapture(st, &g));
+        const hipError_t e = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) {
+            if (ge.tables) (void)hipFree(ge.tables);
+            throw Error{FWI_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e)};
+        }
+        if (table_entries)
+            HIPCHK(hipMemcpy(ge.tables, c->btab.host, table_entries * sizeof(BatchEntry), hipMemcpyHostToDevice));
+        ge.gen = g_alloc_gen;
+        ge.n_forward = c->stats.n_forward - before.n_forward;
+        ge.n_adjoint = c->stats.n_adjoint - before.n_adjoint;
+        ge.n_encode = c->stats.n_encode - before.n_encode;
+        ge.n_decode = c->stats.n_decode - before.n_decode;
+        ge.ckpt_raw_bytes = c->stats.ckpt_raw_bytes - before.ckpt_raw_bytes;
+        ge.ckpt_bytes_host = c->stats.ckpt_bytes - before.ckpt_bytes;
+        it = c->gcache.emplace(key, ge).first;
+    } else {
+        const fwi_ctx::GraphEntry &ge = it->second;
+        c->stats.n_forward += ge.n_forward;
+        c->stats.n_adjoint += ge.n_adjoint;
+        c->stats.n_encode += ge.n_encode;
+        c->stats.n_decode += ge.n_decode;
+        c->stats.ckpt_raw_bytes += ge.ckpt_raw_bytes;
+        c->stats.ckpt_bytes += ge.ckpt_bytes_host;
+    }
+    HIPCHK(hipGraphLaunch(it->second.exec, st));
+    if (!caller) {
+        HIPCHK(hipEventRecord(c->gfence[1], st));
+        HIPCHK(hipStreamWaitEvent(caller, c->gfence[1], 0));
+    }
+}
+
 }  // namespace
 
 // ================================================================== C ABI
@@ -831,13 +1150,27 @@ int fwi_ctx_destroy(fwi_ctx *c)
         for (auto e : c->evpool) (void)hipEventDestroy(e);
         if (c->t0) (void)hipEventDestroy(c->t0);
         if (c->t1) (void)hipEventDestroy(c->t1);
-        c->pool.release(); c->arena.release(); c->fa.release(); c->fb.release(); c->la.release(); c->lb.release();
-        c->coef.release(); c->scratch.release(); c->chunk_bits.release(); c->chunk_off.release();
-        c->misc.release(); c->slots.release(); c->flags.release(); c->partials.release();
-        c->phi.release(); c->rec_off.release(); c->node_pad.release(); c->gacc.release();
-        c->node_xyz.release(); c->rec_ptr.release(); c->rec_idx.release(); c->dsim.release();
-        c->res.release();
+        c->drop_graphs();
+        if (c->gstream) (void)hipStreamDestroy(c->gstream);
+        for (auto e : c->gfence)
+            if (e) (void)hipEventDestroy(e);
+        c->pool.release(); c->sb.release();
+        for (auto &b : c->batch) b->release();
+        c->batch.clear();
+        c->btab.release();
+        c->scratch.release(); c->chunk_bits.release(); c->chunk_off.release();
+        c->misc.release(); c->flags.release();
         delete c;
+    });
+}
+
+int fwi_ctx_set_graphs(fwi_ctx *c, int on)
+{
+    return guarded([&] {
+        if (!c) throw Error{FWI_EINVAL, "ctx is null"};
+        HIPCHK(hipSetDevice(c->device));
+        c->graphs = on != 0;
+        if (!c->graphs) c->drop_graphs();
     });
 }
 
@@ -864,11 +1197,30 @@ int fwi_forward(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *s
         if (!c || !m || (!d_sim && shot && shot->nrec > 0)) throw Error{FWI_EINVAL, "null argument"};
         begin_call(c, st);
         Exec ex{c, make_setup(g, shot, true), st, m, shot};
-        ensure_fields(c, ex.S);
+        ensure_fields(&c->sb, ex.S);
         ex.dsim = d_sim;
         ex.init_fields();
         ex.advance(0, ex.S.nt, true);
         ex.flush_record();
+        HIPCHK(hipGetLastError());
+        end_call(c, st);
+    });
+}
+
+int fwi_forward_state(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot,
+                      float *d_sim, float *u_last, float *u_prev, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !m || (!d_sim && shot && shot->nrec > 0)) throw Error{FWI_EINVAL, "null argument"};
+        begin_call(c, st);
+        Exec ex{c, make_setup(g, shot, true), st, m, shot};
+        ensure_fields(&c->sb, ex.S);
+        ex.dsim = d_sim;
+        ex.init_fields();
+        ex.advance(0, ex.S.nt, true);
+        ex.flush_record();
+        if (u_last) launch_unpad(ex.cur, u_last, ex.padmap(), st);
+        if (u_prev) launch_unpad(ex.prev, u_prev, ex.padmap(), st);
         HIPCHK(hipGetLastError());
         end_call(c, st);
     });
@@ -884,7 +1236,7 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         check_cfg(cfg);
         begin_call(c, st);
         Exec ex{c, make_setup(g, shot, true), st, m, shot};
-        ensure_fields(c, ex.S);
+        ensure_fields(&c->sb, ex.S);
         const auto &acts = plan_for(c, ex.S.nt, cfg->nslots);
         const int used = max_slot_used(acts);
         FieldView fv = padded_view(ex.S);
@@ -892,23 +1244,133 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         if (c->pool.n < c->pool_default) c->pool.ensure(c->pool_default);
         const size_t cap = cfg->pool_bytes ? std::min(cfg->pool_bytes, c->pool_default) : c->pool_default;
         reset_status(c, st);
-        setup_ckpt(ex, cfg, c->pool.p, cap, c->slots.p, used);
+        setup_ckpt(ex, cfg, c->pool.p, cap, c->sb.slots.p, used);
         const size_t nd = (size_t)ex.S.nt * ex.S.nrec;
-        c->dsim.ensure(std::max<size_t>(nd, 1));
-        c->res.ensure(std::max<size_t>(nd, 1));
-        c->partials.ensure(256);
-        c->phi.ensure(1);
-        HIPCHK(hipMemsetAsync(c->phi.p, 0, sizeof(double), st));
-        ex.dsim = c->dsim.p;
+        c->sb.dsim.ensure(std::max<size_t>(nd, 1));
+        c->sb.res.ensure(std::max<size_t>(nd, 1));
+        c->sb.partials.ensure(256);
+        c->sb.phi.ensure(1);
+        HIPCHK(hipMemsetAsync(c->sb.phi.p, 0, sizeof(double), st));
+        ex.dsim = c->sb.dsim.p;
         ex.d_obs = d_obs;
         ex.grad = grad;
         ex.init_fields();
         ex.init_adjoint();
-        ex.run(acts, restart_flags(acts), 0, false);
-        launch_unpad(c->gacc.p, grad, ex.padmap(), st);
+        KeyBuilder key;
+        key.add('G');
+        key_shot(key, c, g, shot, ex.S);
+        key.add(m).add(d_obs).add(grad).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
+        run_schedule(c, st, key.s, 0, [&](BatchEntry *, hipStream_t rs) {
+            ex.st = rs;
+            ex.run(acts, restart_flags(acts), 0, false);
+            launch_unpad(c->sb.gacc.p, grad, ex.padmap(), rs);
+            ex.st = st;
+        });
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(phi, c->phi.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(phi, c->sb.phi.p, sizeof(double), hipMemcpyDeviceToHost, st));
         finish_status(c, st);
+        end_call(c, st);
+    });
+}
+
+int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const float *const *models,
+                       const fwi_shot *shots, const float *const *d_obs, const fwi_ckpt_cfg *cfg,
+                       float *const *grads, double *phis, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || nshots < 1 || !grids || !models || !shots || !grads || !phis || !d_obs)
+            throw Error{FWI_EINVAL, "null argument or nshots < 1"};
+        check_cfg(cfg);
+        for (int i = 0; i < nshots; ++i) {
+            if (!models[i] || !grads[i] || (!d_obs[i] && shots[i].nrec > 0))
+                throw Error{FWI_EINVAL, "null model, gradient or data of shot " + std::to_string(i)};
+            const fwi_grid &a = grids[0], &b = grids[i];
+            if (b.ndim != a.ndim || b.space_order != a.space_order || b.nt != a.nt || b.dt != a.dt)
+                throw Error{FWI_EINVAL, "batched shots must share ndim, space order, nt and dt"};
+        }
+        begin_call(c, st);
+        std::vector<Setup> setups;
+        setups.reserve(nshots);
+        for (int i = 0; i < nshots; ++i) setups.push_back(make_setup(&grids[i], &shots[i], true));
+        while ((int)c->batch.size() < nshots) c->batch.push_back(std::make_unique<ShotBufs>());
+        const int nt = setups[0].nt;
+        const auto &acts = plan_for(c, nt, cfg->nslots);
+        const int used = max_slot_used(acts);
+        const std::vector<char> both = restart_flags(acts);
+        if (c->pool.n < c->pool_default) c->pool.ensure(c->pool_default);
+        const size_t cap = cfg->pool_bytes ? std::min(cfg->pool_bytes, c->pool_default) : c->pool_default;
+        // pool regions in proportion to each shot's padded field size
+        std::vector<size_t> off(nshots + 1, 0);
+        double wsum = 0;
+        for (auto &S : setups) wsum += (double)S.pad.elems();
+        double acc = 0;
+        for (int i = 0; i < nshots; ++i) {
+            acc += (double)setups[i].pad.elems();
+            off[i + 1] = i + 1 == nshots ? cap : ((size_t)((double)cap * (acc / wsum)) & ~(size_t)255);
+        }
+        if (cfg->compress)
+            for (auto &S : setups) ensure_codec(c, padded_view(S), 1);
+        reset_status(c, st);
+        std::vector<Exec> ex;
+        ex.reserve(nshots);
+        for (int i = 0; i < nshots; ++i) {
+            ShotBufs *b = c->batch[i].get();
+            ensure_fields(b, setups[i]);
+            b->slots.ensure((size_t)std::max(2 * used, 1));
+            b->misc.ensure(4);
+            HIPCHK(hipMemsetAsync(b->misc.p, 0, 4 * sizeof(unsigned long long), st));
+            Exec e{c, setups[i], st, models[i], &shots[i], b};
+            e.misc = b->misc.p;
+            setup_ckpt(e, cfg, c->pool.p + off[i], off[i + 1] - off[i], b->slots.p, used);
+            const size_t nd = (size_t)nt * e.S.nrec;
+            b->dsim.ensure(std::max<size_t>(nd, 1));
+            b->res.ensure(std::max<size_t>(nd, 1));
+            b->partials.ensure(256);
+            b->phi.ensure(1);
+            HIPCHK(hipMemsetAsync(b->phi.p, 0, sizeof(double), st));
+            e.dsim = b->dsim.p;
+            e.d_obs = d_obs[i];
+            e.grad = grads[i];
+            e.init_fields();
+            e.init_adjoint();
+            ex.push_back(std::move(e));
+        }
+        const size_t nent = launches_of(acts) * (size_t)nshots;
+        c->btab.ensure(nent);
+        KeyBuilder key;
+        key.add('B').add(nshots).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
+        for (int i = 0; i < nshots; ++i) {
+            key_shot(key, c, &grids[i], &shots[i], setups[i]);
+            key.add(models[i]).add(d_obs[i]).add(grads[i]);
+        }
+        run_schedule(c, st, key.s, nent, [&](BatchEntry *gtab, hipStream_t rs) {
+            for (auto &e : ex) e.st = rs;
+            BatchExec bx{c, rs, ex, setups[0].ndim, setups[0].R, gtab ? gtab : c->btab.dev.p, gtab == nullptr, {}};
+            bx.run(acts, both);
+            for (int i = 0; i < nshots; ++i)
+                launch_unpad(c->batch[i]->gacc.p, grads[i], ex[i].padmap(), rs);
+            for (auto &e : ex) e.st = st;
+        });
+        std::vector<double> ph(nshots, 0.0);
+        std::vector<unsigned long long> mc(4 * (size_t)nshots, 0);
+        for (int i = 0; i < nshots; ++i) {
+            ShotBufs *b = c->batch[i].get();
+            HIPCHK(hipMemcpyAsync(&ph[i], b->phi.p, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(&mc[4 * i], b->misc.p, 4 * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, st));
+        }
+        HIPCHK(hipGetLastError());
+        finish_status(c, st);
+        long long high = 0, bytes = 0;
+        for (int i = 0; i < nshots; ++i) {
+            phis[i] = ph[i];
+            high += (long long)mc[4 * i + 1];
+            bytes += (long long)mc[4 * i + 2];
+        }
+        if (cfg->compress) {
+            c->stats.pool_high = high;
+            c->stats.ckpt_bytes = bytes;
+        }
         end_call(c, st);
     });
 }
@@ -930,7 +1392,7 @@ int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_sh
             Exec ex{c, make_setup(g, shot, true), st, m, shot};
             t->rec.assign(shot->rec, shot->rec + (size_t)shot->nrec * g->ndim);
             t->shot.rec = t->rec.data();
-            ensure_fields(c, ex.S);
+            ensure_fields(&c->sb, ex.S);
             t->acts = plan_for(c, ex.S.nt, cfg->nslots);
             const int used = max_slot_used(t->acts);
             FieldView fv = padded_view(ex.S);
@@ -945,11 +1407,11 @@ int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_sh
             t->both = restart_flags(t->acts);
             t->next = ex.run(t->acts, t->both, 0, true);
             t->slot_both = ex.slot_both;
-            t->xcur.ensure(c->padded_elems);
-            t->xprev.ensure(c->padded_elems);
-            HIPCHK(hipMemcpyAsync(t->xcur.p, ex.cur, c->padded_elems * sizeof(float),
+            t->xcur.ensure(c->sb.padded_elems);
+            t->xprev.ensure(c->sb.padded_elems);
+            HIPCHK(hipMemcpyAsync(t->xcur.p, ex.cur, c->sb.padded_elems * sizeof(float),
                                   hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(t->xprev.p, ex.prev, c->padded_elems * sizeof(float),
+            HIPCHK(hipMemcpyAsync(t->xprev.p, ex.prev, c->sb.padded_elems * sizeof(float),
                                   hipMemcpyDeviceToDevice, st));
             HIPCHK(hipGetLastError());
             finish_status(c, st);
@@ -970,7 +1432,7 @@ int fwi_backward(fwi_ctx *c, fwi_tape *t, const float *dd, float *grad, hipStrea
         if (t->used) throw Error{FWI_EINVAL, "tape already back-propagated"};
         begin_call(c, st);
         Exec ex{c, make_setup(&t->grid, &t->shot, true), st, t->m, &t->shot};
-        ensure_fields(c, ex.S);
+        ensure_fields(&c->sb, ex.S);
         const int used = max_slot_used(t->acts);
         FieldView fv = padded_view(ex.S);
         if (t->cfg.compress) ensure_codec(c, fv, 1);
@@ -987,7 +1449,7 @@ int fwi_backward(fwi_ctx *c, fwi_tape *t, const float *dd, float *grad, hipStrea
         ex.reached = t->grid.nt;
         ex.slot_both = t->slot_both;
         ex.run(t->acts, t->both, t->next, false);
-        launch_unpad(c->gacc.p, grad, ex.padmap(), st);
+        launch_unpad(c->sb.gacc.p, grad, ex.padmap(), st);
         HIPCHK(hipGetLastError());
         finish_status(c, st);
         t->used = true;
@@ -1149,8 +1611,8 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         if (steps < 1) throw Error{FWI_EINVAL, "steps must be >= 1"};
         HIPCHK(hipSetDevice(c->device));
         Exec ex{c, make_setup(g, shot, true), st, m, shot};
-        ensure_fields(c, ex.S);
-        const size_t arena_bytes = c->arena.n;
+        ensure_fields(&c->sb, ex.S);
+        const size_t arena_bytes = c->sb.arena.n;
         std::vector<fwi_ctx::Shape> cands;
         const int xcs3[] = {8, 16, 32, 64};
         const int xcs2[] = {4, 8, 16, 32, 64};
@@ -1171,10 +1633,10 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
             p.rpl = sh.rpl;
             p.remap = sh.remap;
             auto one = [&](int i) {
-                float *a = (i & 1) ? c->fb.p : c->fa.p, *b = (i & 1) ? c->fa.p : c->fb.p;
+                float *a = (i & 1) ? c->sb.fb.p : c->sb.fa.p, *b = (i & 1) ? c->sb.fa.p : c->sb.fb.p;
                 if (adj) {
-                    float *l1 = (i & 1) ? c->lb.p : c->la.p, *l2 = (i & 1) ? c->la.p : c->lb.p;
-                    p.u1 = l1; p.u2 = l2; p.out = l2; p.uk = a; p.g = c->gacc.p;
+                    float *l1 = (i & 1) ? c->sb.lb.p : c->sb.la.p, *l2 = (i & 1) ? c->sb.la.p : c->sb.lb.p;
+                    p.u1 = l1; p.u2 = l2; p.out = l2; p.uk = a; p.g = c->sb.gacc.p;
                 } else {
                     p.u1 = a; p.u2 = b; p.out = b; p.wav = shot->wavelet; p.step = 0;
                 }
@@ -1190,7 +1652,7 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
             return (double)ms / steps;
         };
         auto reset = [&] {
-            HIPCHK(hipMemsetAsync(c->arena.p, 0, arena_bytes, st));
+            HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, arena_bytes, st));
             ex.init_fields();
         };
         reset();
@@ -1204,12 +1666,13 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         c->tuned[ex.grid_key()] = {sf, sa};
+        c->drop_graphs();
         out->ncand = (int)cands.size();
         out->fwd_xchunk = sf.xchunk; out->fwd_rows_per_lane = sf.rpl; out->fwd_xcd_order = sf.remap;
         out->adj_xchunk = sa.xchunk; out->adj_rows_per_lane = sa.rpl; out->adj_xcd_order = sa.remap;
         out->fwd_ms = bf;
         out->adj_ms = ba;
-        HIPCHK(hipMemsetAsync(c->arena.p, 0, arena_bytes, st));
+        HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, arena_bytes, st));
         HIPCHK(hipStreamSynchronize(st));
     });
 }

@@ -97,12 +97,11 @@ __device__ __forceinline__ void tile_coords(int hw, int nwg, int ntz, int nty, b
 }
 
 template <int R, bool ADJ, int RPL>
-__global__ __launch_bounds__(TILE_Z * 8)
-void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
+__device__ __forceinline__ void step3d_body(const StepParams &p, int hw, int ntz, int nty, int nwg,
+                                            int launched)
 {
     constexpr int ROWS = 8 * RPL;
     __shared__ float tile[2][ROWS + 2 * R][TILE_Z + 2 * R];
-    const int hw = blockIdx.x;
     if (hw >= launched) {                          // receiver sampling blocks
         gather_block(p, hw - launched);
         return;
@@ -249,15 +248,20 @@ void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
     }
 }
 
+template <int R, bool ADJ, int RPL>
+__global__ __launch_bounds__(TILE_Z * 8)
+void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
+{
+    step3d_body<R, ADJ, RPL>(p, blockIdx.x, ntz, nty, nwg, launched);
+}
+
 // ------------------------------------------------------------------- 2D
 // Workgroup = 256 lanes along z, one row each, streaming x with the same
 // pipelining; the z neighbours come from a double-buffered LDS row.
 template <int R, bool ADJ>
-__global__ __launch_bounds__(TILE_Z2)
-void step2d_kernel(StepParams p, int ntz, int nwg)
+__device__ __forceinline__ void step2d_body(const StepParams &p, int hw, int ntz, int nwg)
 {
     __shared__ float row[2][TILE_Z2 + 2 * R];
-    const int hw = blockIdx.x;
     if (hw >= nwg) {
         gather_block(p, hw - nwg);
         return;
@@ -325,29 +329,70 @@ void step2d_kernel(StepParams p, int ntz, int nwg)
 }
 
 template <int R, bool ADJ>
+__global__ __launch_bounds__(TILE_Z2)
+void step2d_kernel(StepParams p, int ntz, int nwg)
+{
+    step2d_body<R, ADJ>(p, blockIdx.x, ntz, nwg);
+}
+
+// ---------------------------------------------------------------- batched
+// One launch covers several shots: entry s owns workgroups
+// [first_s, first_{s+1}); a workgroup finds its entry by binary search and
+// runs the same body as the single-shot kernel on that entry's parameters.
+__device__ __forceinline__ int batch_entry(const BatchEntry *__restrict__ tab, int nshot, int wg)
+{
+    int lo = 0, hi = nshot - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].first <= wg) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int R, bool ADJ>
+__global__ __launch_bounds__(TILE_Z * 8)
+void step3d_batch_kernel(const BatchEntry *__restrict__ tab, int nshot)
+{
+    const int s = batch_entry(tab, nshot, blockIdx.x);
+    const BatchEntry &e = tab[s];
+    step3d_body<R, ADJ, 2>(e.p, blockIdx.x - e.first, e.ntz, e.nty, e.nwg, e.launched);
+}
+
+template <int R, bool ADJ>
+__global__ __launch_bounds__(TILE_Z2)
+void step2d_batch_kernel(const BatchEntry *__restrict__ tab, int nshot)
+{
+    const int s = batch_entry(tab, nshot, blockIdx.x);
+    const BatchEntry &e = tab[s];
+    step2d_body<R, ADJ>(e.p, blockIdx.x - e.first, e.ntz, e.nwg);
+}
+
+template <int R, bool ADJ>
 void launch_r(const StepParams &p, int ndim, hipStream_t st)
 {
-    const int nchunk = (p.nx + p.xchunk - 1) / p.xchunk;
-    const bool gather = !ADJ && p.grow && p.nrec > 0;
+    BatchEntry e{};
+    e.p = p;
+    const int total = step_geometry(e, ndim, ADJ);
     if (ndim == 3) {
-        const int rows = 8 * p.rpl;
-        const int ntz = (p.nz + TILE_Z - 1) / TILE_Z;
-        const int nty = (p.ny + rows - 1) / rows;
-        const int nwg = ntz * nty * nchunk;
-        const int launched = ((nwg + 7) / 8) * 8;
-        const int ng = gather ? (p.nrec + 511) / 512 : 0;
         if (p.rpl == 4)
-            hipLaunchKernelGGL((step3d_kernel<R, ADJ, 4>), dim3(launched + ng), dim3(TILE_Z, 8, 1), 0, st,
-                               p, ntz, nty, nwg, launched);
+            hipLaunchKernelGGL((step3d_kernel<R, ADJ, 4>), dim3(total), dim3(TILE_Z, 8, 1), 0, st,
+                               p, e.ntz, e.nty, e.nwg, e.launched);
         else
-            hipLaunchKernelGGL((step3d_kernel<R, ADJ, 2>), dim3(launched + ng), dim3(TILE_Z, 8, 1), 0, st,
-                               p, ntz, nty, nwg, launched);
+            hipLaunchKernelGGL((step3d_kernel<R, ADJ, 2>), dim3(total), dim3(TILE_Z, 8, 1), 0, st,
+                               p, e.ntz, e.nty, e.nwg, e.launched);
     } else {
-        const int ntz = (p.nz + TILE_Z2 - 1) / TILE_Z2;
-        const int nwg = ntz * nchunk;
-        const int ng = gather ? (p.nrec + TILE_Z2 - 1) / TILE_Z2 : 0;
-        hipLaunchKernelGGL((step2d_kernel<R, ADJ>), dim3(nwg + ng), dim3(TILE_Z2), 0, st, p, ntz, nwg);
+        hipLaunchKernelGGL((step2d_kernel<R, ADJ>), dim3(total), dim3(TILE_Z2), 0, st, p, e.ntz, e.nwg);
     }
+}
+
+template <int R, bool ADJ>
+void launch_batch_r(const BatchEntry *tab, int nshot, int total, int ndim, hipStream_t st)
+{
+    if (ndim == 3)
+        hipLaunchKernelGGL((step3d_batch_kernel<R, ADJ>), dim3(total), dim3(TILE_Z, 8, 1), 0, st, tab, nshot);
+    else
+        hipLaunchKernelGGL((step2d_batch_kernel<R, ADJ>), dim3(total), dim3(TILE_Z2), 0, st, tab, nshot);
 }
 
 // ------------------------------------------------------------- small kernels
@@ -363,6 +408,20 @@ __global__ __launch_bounds__(256) void probe_kernel(const float *__restrict__ a,
         for (; i < n; i += step) d[i] = a[i];
     else
         for (; i < n; i += step) d[i] = a[i] + b[i] + c[i];
+}
+
+// p[0..n) = 0 and dst = src (n floats): kernels rather than memset/memcpy
+// nodes, so a captured schedule holds kernel nodes only
+__global__ void fill_zero_kernel(float *p, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+__global__ void copy_kernel(float *__restrict__ dst, const float *__restrict__ src, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
 }
 
 // b = dt^2/m from the unpadded model into the padded layout
@@ -451,6 +510,42 @@ __global__ void inject_kernel(InjectParams p)
 
 }  // namespace
 
+int step_geometry(BatchEntry &e, int ndim, bool adjoint)
+{
+    const StepParams &p = e.p;
+    const int nchunk = (p.nx + p.xchunk - 1) / p.xchunk;
+    const bool gather = !adjoint && p.grow && p.nrec > 0;
+    if (ndim == 3) {
+        const int rows = 8 * p.rpl;
+        e.ntz = (p.nz + TILE_Z - 1) / TILE_Z;
+        e.nty = (p.ny + rows - 1) / rows;
+        e.nwg = e.ntz * e.nty * nchunk;
+        e.launched = ((e.nwg + 7) / 8) * 8;
+        const int ng = gather ? (p.nrec + 511) / 512 : 0;
+        return e.launched + ng;
+    }
+    e.ntz = (p.nz + TILE_Z2 - 1) / TILE_Z2;
+    e.nty = 1;
+    e.nwg = e.ntz * nchunk;
+    e.launched = e.nwg;
+    const int ng = gather ? (p.nrec + TILE_Z2 - 1) / TILE_Z2 : 0;
+    return e.nwg + ng;
+}
+
+void launch_step_batch(const BatchEntry *tab, int nshot, int total, int ndim, int radius, bool adjoint,
+                       hipStream_t st)
+{
+    switch (radius * 2 + (adjoint ? 1 : 0)) {
+    case 4: launch_batch_r<2, false>(tab, nshot, total, ndim, st); break;
+    case 5: launch_batch_r<2, true>(tab, nshot, total, ndim, st); break;
+    case 8: launch_batch_r<4, false>(tab, nshot, total, ndim, st); break;
+    case 9: launch_batch_r<4, true>(tab, nshot, total, ndim, st); break;
+    case 16: launch_batch_r<8, false>(tab, nshot, total, ndim, st); break;
+    case 17: launch_batch_r<8, true>(tab, nshot, total, ndim, st); break;
+    default: break;
+    }
+}
+
 void launch_step(const StepParams &p, int ndim, int radius, bool adjoint, hipStream_t st)
 {
     switch (radius * 2 + (adjoint ? 1 : 0)) {
@@ -474,6 +569,16 @@ void launch_probe(const float *a, const float *b, const float *c, float *d, size
                   hipStream_t st)
 {
     hipLaunchKernelGGL(probe_kernel, dim3(256 * 32), dim3(256), 0, st, a, b, c, d, n, nsrc);
+}
+
+void launch_fill_zero(float *p, size_t n, hipStream_t st)
+{
+    if (n) hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(n)), dim3(256), 0, st, p, n);
+}
+
+void launch_copy(float *dst, const float *src, size_t n, hipStream_t st)
+{
+    if (n) hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, st, dst, src, n);
 }
 
 void launch_coef(const float *m, float *b, const PadMap &pm, double dt, hipStream_t st)

@@ -70,7 +70,7 @@ _lib = None
 EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_stats",
            "fwi_last_error", "fwi_forward", "fwi_gradient", "fwi_forward_ckpt",
            "fwi_backward", "fwi_tape_free", "ckpt_bound", "ckpt_compress",
-           "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune", "fwi_ckpt_pool_bytes"]
+           "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune", "fwi_ckpt_pool_bytes", "fwi_forward_state", "fwi_gradient_batch", "fwi_ctx_set_graphs"]
 
 
 def lib():
@@ -87,6 +87,7 @@ def lib():
     L.fwi_ctx_create.argtypes = [ctypes.POINTER(P), I, ctypes.c_size_t]
     L.fwi_ctx_destroy.argtypes = [P]
     L.fwi_ctx_set_timing.argtypes = [P, I]
+    L.fwi_ctx_set_graphs.argtypes = [P, I]
     L.fwi_ctx_stats.argtypes = [P, ctypes.POINTER(fwi_stats)]
     L.fwi_last_error.restype = ctypes.c_char_p
     L.fwi_forward.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), P, P]
@@ -103,6 +104,12 @@ def lib():
     L.fwi_revolve_plan.argtypes = [I, I, ctypes.POINTER(fwi_action), I, ctypes.POINTER(I),
                                    ctypes.POINTER(ctypes.c_longlong)]
     L.fwi_bandwidth_probe.argtypes = [P, P, P, P, ctypes.c_size_t, I, P]
+    L.fwi_forward_state.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), P, P,
+                                    P, P]
+    L.fwi_gradient_batch.argtypes = [P, I, ctypes.POINTER(fwi_grid), ctypes.POINTER(P),
+                                     ctypes.POINTER(fwi_shot), ctypes.POINTER(P),
+                                     ctypes.POINTER(fwi_ckpt_cfg), ctypes.POINTER(P),
+                                     ctypes.POINTER(ctypes.c_double), P]
     L.fwi_ckpt_pool_bytes.argtypes = [ctypes.POINTER(fwi_grid), ctypes.POINTER(fwi_ckpt_cfg),
                                       ctypes.POINTER(ctypes.c_size_t)]
     L.fwi_autotune.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), I,
@@ -233,6 +240,9 @@ class Context:
         except Exception:
             pass
 
+    def set_graphs(self, on: bool):
+        check(lib().fwi_ctx_set_graphs(self.h, int(bool(on))))
+
     def set_timing(self, on: bool):
         check(lib().fwi_ctx_set_timing(self.h, int(bool(on))))
 
@@ -258,6 +268,16 @@ class Context:
                                 _stream()))
         return d
 
+    def forward_state(self, shot, m, wavelet):
+        """(d_sim, u^nt, u^{nt-1}) on the computational grid"""
+        sa = ShotArgs(shot, wavelet)
+        g = grid_of(shot)
+        d = torch.empty((shot.nt, sa.nrec), dtype=torch.float32, device=m.device)
+        u1, u0 = torch.empty_like(m), torch.empty_like(m)
+        check(lib().fwi_forward_state(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), _ptr(d),
+                                      _ptr(u1), _ptr(u0), _stream()))
+        return d, u1, u0
+
     # Eqs. (3)-(4)
     def gradient(self, shot, m, wavelet, d_obs, nslots=10, compress=False, atol=1e-4,
                  grad=None, pool_bytes=0):
@@ -269,6 +289,26 @@ class Context:
         check(lib().fwi_gradient(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), _ptr(d_obs),
                                  ctypes.byref(cfg), _ptr(out), ctypes.byref(phi), _stream()))
         return phi.value, out
+
+    def gradient_batch(self, shots, models, wavelets, d_obs, nslots=10, compress=False, atol=1e-4,
+                       pool_bytes=0, grads=None):
+        """fwi_gradient_batch: lists of shots, models, wavelets (or one
+        wavelet for all) and observed data; returns (phis, grads)."""
+        n = len(shots)
+        if not isinstance(wavelets, (list, tuple)):
+            wavelets = [wavelets] * n
+        sas = [ShotArgs(s, w) for s, w in zip(shots, wavelets)]
+        grids = (fwi_grid * n)(*[grid_of(s) for s in shots])
+        cshots = (fwi_shot * n)(*[sa.c for sa in sas])
+        ms = (ctypes.c_void_p * n)(*[_ptr(m) for m in models])
+        ds = (ctypes.c_void_p * n)(*[_ptr(d) for d in d_obs])
+        outs = [torch.empty_like(m) for m in models] if grads is None else grads
+        gs = (ctypes.c_void_p * n)(*[_ptr(g) for g in outs])
+        phis = (ctypes.c_double * n)()
+        cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), float(atol), int(pool_bytes))
+        check(lib().fwi_gradient_batch(self.h, n, grids, ms, cshots, ds, ctypes.byref(cfg), gs, phis,
+                                       _stream()))
+        return list(phis), outs
 
     def forward_ckpt(self, shot, m, wavelet, nslots=10, compress=False, atol=1e-4, pool_bytes=0):
         sa = ShotArgs(shot, wavelet)

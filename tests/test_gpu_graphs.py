@@ -1,0 +1,102 @@
+"""Captured schedules (fwi_ctx_set_graphs): the first call with a signature
+captures the whole checkpoint schedule into a hipGraph, later calls replay
+it.  Every replay must equal the direct-launch result bit for bit, with
+unrelated eager work and synchronisations between the replays, and a graph
+must be re-captured after the library reallocates a buffer it refers to.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+F = pytest.importorskip("paper_2009_12623_amd.fwigrad")
+
+DEV = "cuda:0"
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def problem(ndim, n, so, nt, seed=3):
+    shot = synth.tiny_shot(ndim, n=n, so=so, nbl=5, nt=nt)
+    v0, vt = synth.tiny_models(shot.shape, seed=seed)
+    m0 = dev(synth.slowness2(synth.extend(v0, shot.nbl)).astype(np.float32))
+    mt = dev(synth.slowness2(synth.extend(vt, shot.nbl)).astype(np.float32))
+    return shot, m0, mt, dev(shot.wavelet().astype(np.float32))
+
+
+@pytest.mark.parametrize("ndim,n,so,compress", [(2, 50, 16, True), (2, 50, 8, False),
+                                                (3, 18, 8, True), (3, 18, 4, False)])
+def test_graph_replays_equal_direct(ndim, n, so, compress):
+    c = F.Context(0, pool_bytes=1 << 28)
+    shot, m0, mt, q = problem(ndim, n, so, nt=45)
+    other, om, _, oq = problem(ndim, n + 3, so, nt=20, seed=5)
+    d = c.forward(shot, mt, q)
+    phi0, g0 = c.gradient(shot, m0, q, d, nslots=4, compress=compress, atol=1e-4)
+    n0 = c.stats()["n_forward"]
+    c.set_graphs(True)
+    g = torch.empty_like(m0)
+    for i in range(4):
+        g.fill_(float("nan"))
+        phi, _ = c.gradient(shot, m0, q, d, nslots=4, compress=compress, atol=1e-4, grad=g)
+        assert torch.equal(g, g0), i
+        assert phi == phi0
+        assert c.stats()["n_forward"] == n0
+        # unrelated eager work between replays (library and torch)
+        x = (m0 * 2.0).sum()
+        c.forward(shot, m0, q)
+        torch.cuda.synchronize()
+        assert torch.isfinite(x)
+    # a call on another grid reallocates the fields: the next call re-captures
+    c.forward(other, om, oq)
+    phi, _ = c.gradient(shot, m0, q, d, nslots=4, compress=compress, atol=1e-4, grad=g)
+    assert torch.equal(g, g0) and phi == phi0
+    c.set_graphs(False)
+    phi, g2 = c.gradient(shot, m0, q, d, nslots=4, compress=compress, atol=1e-4)
+    assert torch.equal(g2, g0)
+    c.close()
+
+
+@pytest.mark.parametrize("compress", [True, False])
+def test_graph_replays_equal_direct_batched(compress):
+    c = F.Context(0, pool_bytes=1 << 28)
+    probs = [problem(3, n, 8, nt=40, seed=s) for n, s in ((16, 1), (21, 2), (18, 3))]
+    shots = [p[0] for p in probs]
+    m0s = [p[1] for p in probs]
+    q = probs[0][3]
+    dobs = [c.forward(s, mt, q) for s, _, mt, _ in probs]
+    phis0, g0 = c.gradient_batch(shots, m0s, q, dobs, nslots=3, compress=compress, atol=1e-4)
+    c.set_graphs(True)
+    gs = [torch.empty_like(m) for m in m0s]
+    for i in range(3):
+        for g in gs:
+            g.fill_(float("nan"))
+        phis, _ = c.gradient_batch(shots, m0s, q, dobs, nslots=3, compress=compress, atol=1e-4,
+                                   grads=gs)
+        for a, b in zip(gs, g0):
+            assert torch.equal(a, b), i
+        assert phis == phis0
+        c.gradient(shots[0], m0s[0], q, dobs[0], nslots=2)
+        torch.cuda.synchronize()
+    c.close()
+
+
+def test_graph_on_a_user_stream():
+    c = F.Context(0, pool_bytes=1 << 27)
+    shot, m0, mt, q = problem(2, 40, 8, nt=40)
+    d = c.forward(shot, mt, q)
+    phi0, g0 = c.gradient(shot, m0, q, d, nslots=3, compress=True, atol=1e-4)
+    c.set_graphs(True)
+    s = torch.cuda.Stream()
+    g = torch.empty_like(m0)
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            phi, _ = c.gradient(shot, m0, q, d, nslots=3, compress=True, atol=1e-4, grad=g)
+    s.synchronize()
+    assert torch.equal(g, g0) and phi == phi0
+    c.close()

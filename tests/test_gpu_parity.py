@@ -82,6 +82,18 @@ def test_gradient_matches_oracle(ctx, ndim, n, so, nbl, nt):
     assert abs(phi - phi_ref) <= 1e-4 * phi_ref
 
 
+@pytest.mark.parametrize("ndim,n,so", [(2, 60, 16), (3, 22, 8)])
+def test_forward_state_matches_oracle(ctx, ndim, n, so):
+    """the last two levels returned by fwi_forward_state"""
+    shot = synth.tiny_shot(ndim, n=n, so=so, nbl=5, nt=50)
+    m0, _, q = inputs(shot)
+    d, u1, u0 = ctx.forward_state(shot, dev(m0), dev(q))
+    dref, states = solver.forward(oracle_problem(shot, m0, q), keep_states=True)
+    assert metrics.rel_l2(d.cpu().numpy(), dref) <= 1e-4
+    assert metrics.rel_l2(u1.cpu().numpy(), states[shot.nt]) <= 1e-4
+    assert metrics.rel_l2(u0.cpu().numpy(), states[shot.nt - 1]) <= 1e-4
+
+
 @pytest.mark.parametrize("xchunk,rpl,remap", [(3, 2, 0), (7, 4, 1), (64, 2, 1), (16, 4, 0)])
 @pytest.mark.parametrize("so", [4, 8, 16])
 def test_3d_stencil_launch_shapes_match_oracle(xchunk, rpl, remap, so, monkeypatch):
