@@ -403,7 +403,7 @@ long or_compress(const float *x, int ndim, const long *n, double atol,
     wr32(out + 12, (uint32_t)g.ud[1]);
     wr32(out + 16, (uint32_t)g.ud[2]);
     out[20] = (uint8_t)g.guard;
-    out[21] = (uint8_t)(ndim == 3 ? 4 : 6);
+    out[21] = (uint8_t)floor_log2((uint64_t)g.kblk);    /* log2 of blocks per chunk */
     out[22] = (uint8_t)g.tp;
     out[23] = 0;
     uint64_t ab;
@@ -496,7 +496,8 @@ int or_decompress(const uint8_t *s, long nbytes, float *x, int ndim,
     if (geom_init(&g, ndim, n)) return OR_EINVAL;
     if (nbytes < 64 || memcmp(s, "FWZ1", 4) != 0 || s[4] != 1 || s[5] != 0)
         return OR_ECORRUPT;
-    if (s[6] != ndim || s[7] != QBITS || s[20] != g.guard || s[22] != g.tp)
+    if (s[6] != ndim || s[7] != QBITS || s[20] != g.guard || s[22] != g.tp ||
+        s[21] != floor_log2((uint64_t)g.kblk))
         return OR_ECORRUPT;
     for (int d = 0; d < 3; ++d)
         if ((long)rd32(s + 8 + 4 * d) != g.ud[d]) return OR_ECORRUPT;

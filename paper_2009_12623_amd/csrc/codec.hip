@@ -259,7 +259,7 @@ template <int D>
 __global__ __launch_bounds__(64)
 void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, long nblocks,
                    long nchunks, int kblk, int minexp, unsigned long long *scratch, long chunk_words,
-                   unsigned long long *chunk_bits, unsigned int *flags)
+                   unsigned long long *chunk_bits, unsigned int *flags, int vec)
 {
     using GC = GeomC<D>;
     constexpr int SZ = GC::SZ;
@@ -275,16 +275,34 @@ void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, 
         long bx, by, bz;
         block_coords(b, nb, bx, by, bz);
         uint32_t w[SZ];
+        const bool inner = vec && 4 * bx + 3 < f.n[0] && (D == 2 || 4 * by + 3 < f.n[1]) && 4 * bz + 3 < f.n[2];
+        if (inner) {
+            // whole block inside: one 16-byte load per (x, y) row
 #pragma unroll
-        for (int li = 0; li < SZ; ++li) {
-            const int ix = D == 3 ? (li >> 4) : (li >> 2);
-            const int iy = D == 3 ? ((li >> 2) & 3) : 0;
-            const int iz = li & 3;
-            long x = 4 * bx + ix, y = 4 * by + iy, z = 4 * bz + iz;
-            x = x < f.n[0] ? x : f.n[0] - 1;
-            y = y < f.n[1] ? y : f.n[1] - 1;
-            z = z < f.n[2] ? z : f.n[2] - 1;
-            w[li] = __float_as_uint(src[x * f.sx + y * f.sy + z]);
+            for (int r = 0; r < SZ / 4; ++r) {
+                const int ix = D == 3 ? (r >> 2) : r;
+                const int iy = D == 3 ? (r & 3) : 0;
+                typedef float f4v __attribute__((ext_vector_type(4)));
+                const f4v v = __builtin_nontemporal_load(
+                    (const f4v *)(src + (4 * bx + ix) * f.sx + (4 * by + iy) * f.sy + 4 * bz));
+                w[4 * r + 0] = __float_as_uint(v.x);
+                w[4 * r + 1] = __float_as_uint(v.y);
+                w[4 * r + 2] = __float_as_uint(v.z);
+                w[4 * r + 3] = __float_as_uint(v.w);
+            }
+        } else {
+            // partial block: repeat the last valid sample along each axis
+#pragma unroll
+            for (int li = 0; li < SZ; ++li) {
+                const int ix = D == 3 ? (li >> 4) : (li >> 2);
+                const int iy = D == 3 ? ((li >> 2) & 3) : 0;
+                const int iz = li & 3;
+                long x = 4 * bx + ix, y = 4 * by + iy, z = 4 * bz + iz;
+                x = x < f.n[0] ? x : f.n[0] - 1;
+                y = y < f.n[1] ? y : f.n[1] - 1;
+                z = z < f.n[2] ? z : f.n[2] - 1;
+                w[li] = __float_as_uint(src[x * f.sx + y * f.sy + z]);
+            }
         }
         int Emax = 0;
 #pragma unroll
@@ -508,28 +526,41 @@ void pack_kernel(PackArgs a)
         sc[threadIdx.x] += add;
         __syncthreads();
     }
-    if (c >= a.nchunks) return;
-    const unsigned long long off = a.tile_prefix[blockIdx.x] + sc[threadIdx.x] - len;
-    // tables: super-chunk base (the first chunk of each super-chunk) and
-    // relative chunk offsets (a super-chunk of 256 lies inside one tile)
-    unsigned char *tab = dst + 64;
-    const long sup0 = (c / 256) * 256 - (long)blockIdx.x * TILE;   // in-tile index of the super-chunk head
-    const unsigned long long head = a.tile_prefix[blockIdx.x] + (sup0 > 0 ? sc[sup0 - 1] : 0ull);
-    if ((c & 255) == 0) st64(tab + 8 * (c / 256), off);
-    st32(tab + 8 * a.nsuper + 4 * c, (unsigned int)(off - head));
-    // payload words whose first bit lies in this chunk
+    if (c < a.nchunks) {
+        const unsigned long long off = a.tile_prefix[blockIdx.x] + sc[threadIdx.x] - len;
+        // tables: super-chunk base (the first chunk of each super-chunk) and
+        // relative chunk offsets (a super-chunk of 256 lies inside one tile)
+        unsigned char *tab = dst + 64;
+        const long sup0 = (c / 256) * 256 - (long)blockIdx.x * TILE;   // in-tile index of the super-chunk head
+        const unsigned long long head = a.tile_prefix[blockIdx.x] + (sup0 > 0 ? sc[sup0 - 1] : 0ull);
+        if ((c & 255) == 0) st64(tab + 8 * (c / 256), off);
+        st32(tab + 8 * a.nsuper + 4 * c, (unsigned int)(off - head));
+    }
+    // payload: the block writes every word whose first bit lies in this
+    // tile; consecutive threads take consecutive words (coalesced reads of
+    // the chunk scratch and coalesced writes), finding the chunk that holds
+    // the word's first bit by binary search over the tile's prefix sums
+    __syncthreads();
     unsigned long long *out = (unsigned long long *)(dst + 64 + a.table_bytes);
-    if (len == 0) return;
-    const unsigned long long end = off + len;
-    for (unsigned long long wb = (off + 63ull) & ~63ull; wb < end; wb += 64ull) {
+    const unsigned long long base = a.tile_prefix[blockIdx.x];
+    const unsigned long long tile_end = base + sc[TILE - 1];
+    const long c0 = (long)blockIdx.x * TILE;
+    for (unsigned long long w = ((base + 63ull) >> 6) + threadIdx.x; (w << 6) < tile_end; w += TILE) {
+        unsigned long long pos = w << 6;
+        int lo = 0, hi = TILE - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (base + sc[mid] > pos) hi = mid;
+            else lo = mid + 1;
+        }
+        long cc = c0 + lo;
+        unsigned long long cstart = base + (lo ? sc[lo - 1] : 0ull);
+        unsigned long long clen = sc[lo] - (lo ? sc[lo - 1] : 0ull);
         unsigned long long word = 0ull;
         int got = 0;
-        long cc = c;
-        unsigned long long cstart = off, clen = len;
-        unsigned long long pos = wb;
         while (got < 64) {
             if (pos >= cstart + clen) {
-                // next non-empty chunk
+                // next chunk (possibly in the next tile)
                 ++cc;
                 if (cc >= a.nchunks) break;
                 cstart += clen;
@@ -538,18 +569,17 @@ void pack_kernel(PackArgs a)
             }
             const unsigned long long lb = pos - cstart;       // local bit in chunk cc
             const unsigned long long *src = a.scratch + cc * a.chunk_words;
-            const long wi = (long)(lb >> 6);
             const int sh = (int)(lb & 63);
-            unsigned long long v = src[wi] >> sh;
+            unsigned long long v = src[lb >> 6] >> sh;
             int avail = 64 - sh;
             if ((unsigned long long)avail > clen - lb) avail = (int)(clen - lb);
-            int take = avail < 64 - got ? avail : 64 - got;
+            const int take = avail < 64 - got ? avail : 64 - got;
             v &= lowmask64(take);
             word |= v << got;
             got += take;
             pos += (unsigned long long)take;
         }
-        out[wb >> 6] = word;
+        out[w] = word;
     }
 }
 
@@ -559,7 +589,7 @@ __global__ __launch_bounds__(64)
 void decode_kernel(FieldView f, float *dst, const unsigned char *stream, const unsigned char *pool,
                    const StreamSlot *slots, int slot_index, long nb0, long nb1, long nb2,
                    long nblocks, long nchunks, int kblk, long nsuper, long table_bytes,
-                   unsigned int *flags)
+                   unsigned int *flags, int vec)
 {
     using GC = GeomC<D>;
     constexpr int SZ = GC::SZ;
@@ -645,13 +675,24 @@ void decode_kernel(FieldView f, float *dst, const unsigned char *stream, const u
         }
         long bx, by, bz;
         block_coords(b, nb, bx, by, bz);
+        if (vec && 4 * bx + 3 < f.n[0] && (D == 2 || 4 * by + 3 < f.n[1]) && 4 * bz + 3 < f.n[2]) {
+            // whole block inside: one 16-byte store per (x, y) row
 #pragma unroll
-        for (int li = 0; li < SZ; ++li) {
-            const int ix = D == 3 ? (li >> 4) : (li >> 2);
-            const int iy = D == 3 ? ((li >> 2) & 3) : 0;
-            const int iz = li & 3;
-            const long x = 4 * bx + ix, y = 4 * by + iy, z = 4 * bz + iz;
-            if (x < f.n[0] && y < f.n[1] && z < f.n[2]) dst[x * f.sx + y * f.sy + z] = vals[li];
+            for (int r = 0; r < SZ / 4; ++r) {
+                const int ix = D == 3 ? (r >> 2) : r;
+                const int iy = D == 3 ? (r & 3) : 0;
+                *(float4 *)(dst + (4 * bx + ix) * f.sx + (4 * by + iy) * f.sy + 4 * bz) =
+                    make_float4(vals[4 * r], vals[4 * r + 1], vals[4 * r + 2], vals[4 * r + 3]);
+            }
+        } else {
+#pragma unroll
+            for (int li = 0; li < SZ; ++li) {
+                const int ix = D == 3 ? (li >> 4) : (li >> 2);
+                const int iy = D == 3 ? ((li >> 2) & 3) : 0;
+                const int iz = li & 3;
+                const long x = 4 * bx + ix, y = 4 * by + iy, z = 4 * bz + iz;
+                if (x < f.n[0] && y < f.n[1] && z < f.n[2]) dst[x * f.sx + y * f.sy + z] = vals[li];
+            }
         }
     }
 }
@@ -701,6 +742,12 @@ long codec_bound(const CodecGeom &g)
 // Encode pipeline: encode (lane per chunk) -> tile sums -> plan (placement,
 // header) -> pack (tables + payload).  Scratch layout: scratch words
 // (nchunks * max_chunk_words), chunk_bits (nchunks), tile sums.
+// 16-byte row accesses are valid when every block row starts 16-byte aligned
+static int rows_vectorizable(const FieldView &f, const float *p)
+{
+    return ((uintptr_t)p % 16 == 0) && f.sx % 4 == 0 && (f.ndim == 2 || f.sy % 4 == 0);
+}
+
 void codec_encode(const EncodeArgs &e, hipStream_t st)
 {
     CodecGeom g = codec_geom(e.f.ndim, e.f.n);
@@ -709,11 +756,11 @@ void codec_encode(const EncodeArgs &e, hipStream_t st)
     if (e.f.ndim == 3)
         hipLaunchKernelGGL(encode_kernel<3>, dim3(nwaves), dim3(64), 0, st, e.f, e.src, g.nb[0], g.nb[1],
                            g.nb[2], g.nblocks, g.nchunks, g.kblk, minexp, e.scratch, g.max_chunk_words,
-                           e.chunk_bits, e.flags);
+                           e.chunk_bits, e.flags, rows_vectorizable(e.f, e.src));
     else
         hipLaunchKernelGGL(encode_kernel<2>, dim3(nwaves), dim3(64), 0, st, e.f, e.src, g.nb[0], g.nb[1],
                            g.nb[2], g.nblocks, g.nchunks, g.kblk, minexp, e.scratch, g.max_chunk_words,
-                           e.chunk_bits, e.flags);
+                           e.chunk_bits, e.flags, rows_vectorizable(e.f, e.src));
     const int ntiles = (int)((g.nchunks + TILE - 1) / TILE);
     unsigned long long *tile = e.chunk_off;   // ntiles entries
     hipLaunchKernelGGL(tile_sum_kernel, dim3(ntiles), dim3(TILE), 0, st, e.chunk_bits, g.nchunks, tile);
@@ -728,7 +775,7 @@ void codec_encode(const EncodeArgs &e, hipStream_t st)
     pa.minexp = minexp;
     pa.guard = g.guard;
     pa.tp = g.tp;
-    pa.log2k = e.f.ndim == 3 ? 4 : 6;
+    pa.log2k = __builtin_ctz((unsigned)g.kblk);    // blocks per chunk
     pa.nblocks = g.nblocks;
     pa.nchunks = g.nchunks;
     pa.nsuper = g.nsuper;
@@ -770,11 +817,11 @@ void codec_decode(const DecodeArgs &d, hipStream_t st)
     if (d.f.ndim == 3)
         hipLaunchKernelGGL(decode_kernel<3>, dim3(nwaves), dim3(64), 0, st, d.f, d.dst, d.stream, d.pool,
                            d.slots, d.slot_index, g.nb[0], g.nb[1], g.nb[2], g.nblocks, g.nchunks,
-                           g.kblk, g.nsuper, g.table_bytes, d.flags);
+                           g.kblk, g.nsuper, g.table_bytes, d.flags, rows_vectorizable(d.f, d.dst));
     else
         hipLaunchKernelGGL(decode_kernel<2>, dim3(nwaves), dim3(64), 0, st, d.f, d.dst, d.stream, d.pool,
                            d.slots, d.slot_index, g.nb[0], g.nb[1], g.nb[2], g.nblocks, g.nchunks,
-                           g.kblk, g.nsuper, g.table_bytes, d.flags);
+                           g.kblk, g.nsuper, g.table_bytes, d.flags, rows_vectorizable(d.f, d.dst));
 }
 
 }  // namespace fwi

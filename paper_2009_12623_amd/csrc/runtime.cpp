@@ -1577,7 +1577,8 @@ int ckpt_decompress(fwi_ctx *c, const void *stream, size_t nbytes, float *field,
         const unsigned want[3] = {(unsigned)n[0], (unsigned)(ndim == 3 ? n[1] : n[1]),
                                   (unsigned)(ndim == 3 ? n[2] : 1)};
         if (memcmp(h, "FWZ1", 4) != 0 || h[4] != 1 || h[5] != 0) throw Error{FWI_ECORRUPT, "bad magic or version"};
-        if (h[6] != ndim || h[7] != 24 || h[20] != g.guard || h[22] != g.tp || h[21] != (ndim == 3 ? 4 : 6))
+        if (h[6] != ndim || h[7] != 24 || h[20] != g.guard || h[22] != g.tp ||
+            h[21] != (unsigned char)__builtin_ctz((unsigned)g.kblk))
             throw Error{FWI_ECORRUPT, "stream parameters do not match"};
         if (u32(8) != want[0] || u32(12) != want[1] || u32(16) != want[2])
             throw Error{FWI_ECORRUPT, "stream dims do not match"};

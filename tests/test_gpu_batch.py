@@ -29,13 +29,15 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
 
 
-def cropped_shots(ndim, widths, depth, so, nbl=5, nt=50, seed=4):
+def cropped_shots(ndim, widths, depth, so, nbl=5, nt=50, seed=4, amp=1.0):
     """Shots on crops of one model: crop i has width widths[i] in x (and y
     in 3D) at a seeded origin, the source at its centre at depth 2 and
-    receivers on every 2nd surface node at depth 2."""
+    receivers on every 2nd surface node at depth 2.  ``amp`` scales the true
+    model's perturbation."""
     rng = np.random.default_rng(seed)
     full = (max(widths) + 12,) * (ndim - 1) + (depth,)
     v0, vt = synth.tiny_models(full, seed=seed)
+    vt = v0 * (1.0 + amp * (vt / v0 - 1.0))
     ref = synth.tiny_shot(ndim, n=depth, so=so, nbl=nbl, nt=nt)
     out = []
     for w in widths:
@@ -75,7 +77,7 @@ def test_batch_equals_single_shots(ctx, ndim, widths, depth, so, compress):
 
 
 def test_batch_matches_oracle(ctx):
-    shots, q32 = cropped_shots(2, (40, 71, 55), 48, 16, nt=80, seed=9)
+    shots, q32 = cropped_shots(2, (40, 71, 55), 48, 16, nt=80, seed=9, amp=3.0)
     q = dev(q32)
     models, dobs, refs = [], [], []
     for s, m0, mt in shots:

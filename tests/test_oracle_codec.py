@@ -247,3 +247,20 @@ def test_nonfinite_and_bad_atol_rejected():
         codec.compress(x, 1e-3)
     with pytest.raises(codec.CodecError):
         codec.compress(np.zeros((4, 4), np.float32), 0.0)
+
+
+@pytest.mark.parametrize("shape,log2k", [((5, 6, 7), 0), ((1081, 481), 1), ((200, 200, 200), 2),
+                                         ((4100, 4100), 6)])
+def test_header_records_chunk_length(shape, log2k):
+    """blocks per chunk shrink with the field so that small fields still
+    split into at least 16384 chunks; the header records log2 of it and the
+    chunk count matches"""
+    x = synth.wavefield_like(shape, seed=3) if np.prod(shape) < 3e7 else np.zeros(shape, np.float32)
+    h = codec.header(codec.compress(x, 1e-3))
+    nblocks = int(np.prod([(n + 3) // 4 for n in shape]))
+    k = 1 << log2k
+    assert h["log2k"] == log2k
+    assert h["nchunks"] == 64 * -(-nblocks // (64 * k))
+    kmax = 16 if len(shape) == 3 else 64
+    assert k == 1 or -(-nblocks // k) >= 16384               # enough chunks
+    assert k == kmax or -(-nblocks // (2 * k)) < 16384        # and no more halving than needed
