@@ -208,6 +208,22 @@ int ckpt_compress(fwi_ctx *ctx, const float *field, int ndim, const int n[3],
 int ckpt_decompress(fwi_ctx *ctx, const void *stream_bytes, size_t nbytes,
                     float *field, int ndim, const int n[3], hipStream_t stream);
 
+/* The codec on a field inside a larger array [device]: element (x, y, z)
+ * at origin[x*sx + y*sy + z] (2D: origin[x*sx + z]; sy ignored).  The
+ * stream is the same as ckpt_compress of the dense field.  padded != 0
+ * declares the array layout used for checkpoints: rows start 16-byte
+ * aligned and at least 3 zero-valued points follow the field along every
+ * axis inside the array; the codec then reads and writes whole 4^d blocks
+ * (decompression keeps those points zero).  FWI_EINVAL for strides that
+ * overlap rows or leave no room for the declared padding, or a padded view
+ * with misaligned rows. */
+int ckpt_compress_view(fwi_ctx *ctx, const float *origin, int ndim, const int n[3],
+                       long sx, long sy, int padded, double atol, void *out,
+                       size_t cap, size_t *nbytes, hipStream_t stream);
+int ckpt_decompress_view(fwi_ctx *ctx, const void *stream_bytes, size_t nbytes,
+                         float *origin, int ndim, const int n[3], long sx, long sy,
+                         int padded, hipStream_t stream);
+
 /* Host-only binomial checkpoint schedule reversing states N..1 with nslots
  * slots (minimal forward steps; largest optimal split).  out [host] holds up
  * to cap actions; *nactions receives the full count (FWI_ECAPACITY if it

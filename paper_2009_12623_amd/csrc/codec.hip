@@ -5,7 +5,8 @@
 //   64-byte header | u64 bit offset per super-chunk of 256 chunks |
 //   u32 bit offset per chunk, relative to its super-chunk | pad to 8 bytes |
 //   payload: block bit strings, LSB first in u64 words.
-// A chunk holds K blocks (16 in 3D, 64 in 2D); chunk c = 64 g + l owns the
+// A chunk holds K blocks (16 in 3D, 64 in 2D, halved while the field would
+// have fewer than 16384 chunks, down to 1); chunk c = 64 g + l owns the
 // blocks g*64K + j*64 + l, j = 0..K-1, so that the 64 lanes of a wave, one
 // chunk each, touch 64 neighbouring blocks at every step j.
 //
@@ -20,9 +21,11 @@
 // the whole block in registers.  The 64-coefficient x 32-plane bit matrix is
 // turned into plane masks with an in-register 32x32 bit transpose, so every
 // per-plane step is a handful of vector instructions and no lane ever waits
-// on another.  Encoding writes each chunk to a private scratch slot; a tile
-// scan places the chunks and a pack kernel concatenates them at bit
-// granularity (each output word is assembled by exactly one lane).
+// on another.  Encoding writes each chunk to scratch interleaved by lane; a
+// tile scan places the chunks and a pack kernel concatenates them at bit
+// granularity (each output word is assembled by exactly one thread, and
+// consecutive threads assemble consecutive words).  Interior blocks of
+// 16-byte-aligned fields are read and written one 16-byte row at a time.
 #include <cstring>
 
 #include "internal.hpp"
@@ -161,10 +164,18 @@ __device__ __forceinline__ unsigned long long lowmask64(int n)
     return n >= 64 ? ~0ull : ((1ull << n) - 1ull);
 }
 
+// Chunk scratch is interleaved by lane: word w of chunk c lives at
+// scratch[(c / 64) * 64 * chunk_words + w * 64 + c % 64], so the 64 lanes of a
+// wave writing their w-th words touch one 512-byte span.
+__host__ __device__ __forceinline__ long scratch_word(long c, long w, long chunk_words)
+{
+    return (c >> 6) * 64 * chunk_words + w * 64 + (c & 63);
+}
+
 struct BitWriter {
     unsigned long long acc;
     int fill;
-    unsigned long long *out;
+    unsigned long long *out;        // word 0 of this lane; word w at out[64 w]
     long w;
     __device__ __forceinline__ void put(uint32_t v, int n)    // v < 2^n, n <= 32
     {
@@ -172,7 +183,7 @@ struct BitWriter {
         acc |= (unsigned long long)v << fill;
         fill += n;
         if (fill >= 64) {
-            out[w++] = acc;
+            out[64 * w++] = acc;
             fill -= 64;
             acc = fill ? ((unsigned long long)v >> (n - fill)) : 0ull;
         }
@@ -267,7 +278,7 @@ void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, 
     const long c = (long)blockIdx.x * 64 + threadIdx.x;
     if (c >= nchunks) return;
     const long nb[3] = {nb0, nb1, nb2};
-    BitWriter bw{0ull, 0, scratch + c * chunk_words, 0};
+    BitWriter bw{0ull, 0, scratch + scratch_word(c, 0, chunk_words), 0};
     bool nonfinite = false;
     for (int j = 0; j < kblk; ++j) {
         const long b = chunk_block(c, j, kblk, nblocks);
@@ -276,7 +287,29 @@ void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, 
         block_coords(b, nb, bx, by, bz);
         uint32_t w[SZ];
         const bool inner = vec && 4 * bx + 3 < f.n[0] && (D == 2 || 4 * by + 3 < f.n[1]) && 4 * bz + 3 < f.n[2];
-        if (inner) {
+        if (vec == 2) {
+            // padded field: one 16-byte load per row for every block; rows
+            // past the end repeat the last row, and the z tail repeats the
+            // last valid sample (the extra values read are padding)
+            typedef float f4v __attribute__((ext_vector_type(4)));
+            const long zl = f.n[2] - 1 - 4 * bz;             // last valid z in the block (>= 0)
+#pragma unroll
+            for (int r = 0; r < SZ / 4; ++r) {
+                const int ix = D == 3 ? (r >> 2) : r;
+                const int iy = D == 3 ? (r & 3) : 0;
+                long x = 4 * bx + ix, y = 4 * by + iy;
+                x = x < f.n[0] ? x : f.n[0] - 1;
+                y = y < f.n[1] ? y : f.n[1] - 1;
+                const f4v v = __builtin_nontemporal_load((const f4v *)(src + x * f.sx + y * f.sy + 4 * bz));
+                const float e1 = zl >= 1 ? v.y : v.x;
+                const float e2 = zl >= 2 ? v.z : e1;
+                const float e3 = zl >= 3 ? v.w : e2;
+                w[4 * r + 0] = __float_as_uint(v.x);
+                w[4 * r + 1] = __float_as_uint(e1);
+                w[4 * r + 2] = __float_as_uint(e2);
+                w[4 * r + 3] = __float_as_uint(e3);
+            }
+        } else if (inner) {
             // whole block inside: one 16-byte load per (x, y) row
 #pragma unroll
             for (int r = 0; r < SZ / 4; ++r) {
@@ -369,7 +402,7 @@ void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, 
             }
         }
     }
-    if (bw.fill) bw.out[bw.w] = bw.acc;
+    if (bw.fill) bw.out[64 * bw.w] = bw.acc;
     chunk_bits[c] = (unsigned long long)bw.w * 64ull + (unsigned long long)bw.fill;
     if (nonfinite) atomicOr(flags, 1u);
 }
@@ -568,9 +601,8 @@ void pack_kernel(PackArgs a)
                 continue;
             }
             const unsigned long long lb = pos - cstart;       // local bit in chunk cc
-            const unsigned long long *src = a.scratch + cc * a.chunk_words;
             const int sh = (int)(lb & 63);
-            unsigned long long v = src[lb >> 6] >> sh;
+            unsigned long long v = a.scratch[scratch_word(cc, (long)(lb >> 6), a.chunk_words)] >> sh;
             int avail = 64 - sh;
             if ((unsigned long long)avail > clen - lb) avail = (int)(clen - lb);
             const int take = avail < 64 - got ? avail : 64 - got;
@@ -584,6 +616,16 @@ void pack_kernel(PackArgs a)
 }
 
 // ------------------------------------------------------------------ decode
+// absolute payload bit where chunk c starts (super-chunk base + relative offset)
+__device__ __forceinline__ unsigned long long chunk_start(const unsigned char *s, long nsuper, long c)
+{
+    unsigned long long sup = 0;
+    unsigned int rel = 0;
+    for (int i = 0; i < 8; ++i) sup |= (unsigned long long)s[64 + 8 * (c / 256) + i] << (8 * i);
+    for (int i = 0; i < 4; ++i) rel |= (unsigned int)s[64 + 8 * nsuper + 4 * c + i] << (8 * i);
+    return sup + rel;
+}
+
 template <int D>
 __global__ __launch_bounds__(64)
 void decode_kernel(FieldView f, float *dst, const unsigned char *stream, const unsigned char *pool,
@@ -603,17 +645,15 @@ void decode_kernel(FieldView f, float *dst, const unsigned char *stream, const u
         s = pool + sl.offset;
     }
     const long nb[3] = {nb0, nb1, nb2};
-    unsigned long long pbits = 0, sup = 0;
-    unsigned int rel = 0;
+    unsigned long long pbits = 0;
     for (int i = 0; i < 8; ++i) pbits |= (unsigned long long)s[48 + i] << (8 * i);
-    for (int i = 0; i < 8; ++i) sup |= (unsigned long long)s[64 + 8 * (c / 256) + i] << (8 * i);
-    for (int i = 0; i < 4; ++i) rel |= (unsigned int)s[64 + 8 * nsuper + 4 * c + i] << (8 * i);
+    const unsigned long long start = chunk_start(s, nsuper, c);
     const int minexp = (int)((unsigned int)s[32] | ((unsigned int)s[33] << 8) |
                              ((unsigned int)s[34] << 16) | ((unsigned int)s[35] << 24));
     BitReader br;
     br.w = (const unsigned long long *)(s + 64 + table_bytes);
     br.nw = (long)((pbits + 63) / 64);
-    br.seek(sup + rel);
+    br.seek(start);
     for (int j = 0; j < kblk; ++j) {
         const long b = chunk_block(c, j, kblk, nblocks);
         if (b < 0) break;
@@ -675,7 +715,21 @@ void decode_kernel(FieldView f, float *dst, const unsigned char *stream, const u
         }
         long bx, by, bz;
         block_coords(b, nb, bx, by, bz);
-        if (vec && 4 * bx + 3 < f.n[0] && (D == 2 || 4 * by + 3 < f.n[1]) && 4 * bz + 3 < f.n[2]) {
+        if (vec == 2) {
+            // padded field: whole-block row stores; entries past the field's
+            // end are written as zero (they are padding, which stays zero)
+            const long zl = f.n[2] - 1 - 4 * bz;
+#pragma unroll
+            for (int r = 0; r < SZ / 4; ++r) {
+                const int ix = D == 3 ? (r >> 2) : r;
+                const int iy = D == 3 ? (r & 3) : 0;
+                const long x = 4 * bx + ix, y = 4 * by + iy;
+                const bool row = x < f.n[0] && y < f.n[1];
+                *(float4 *)(dst + x * f.sx + y * f.sy + 4 * bz) =
+                    make_float4(row ? vals[4 * r] : 0.0f, row && zl >= 1 ? vals[4 * r + 1] : 0.0f,
+                                row && zl >= 2 ? vals[4 * r + 2] : 0.0f, row && zl >= 3 ? vals[4 * r + 3] : 0.0f);
+            }
+        } else if (vec && 4 * bx + 3 < f.n[0] && (D == 2 || 4 * by + 3 < f.n[1]) && 4 * bz + 3 < f.n[2]) {
             // whole block inside: one 16-byte store per (x, y) row
 #pragma unroll
             for (int r = 0; r < SZ / 4; ++r) {
@@ -742,10 +796,13 @@ long codec_bound(const CodecGeom &g)
 // Encode pipeline: encode (lane per chunk) -> tile sums -> plan (placement,
 // header) -> pack (tables + payload).  Scratch layout: scratch words
 // (nchunks * max_chunk_words), chunk_bits (nchunks), tile sums.
-// 16-byte row accesses are valid when every block row starts 16-byte aligned
+// 16-byte row accesses are valid when every block row starts 16-byte
+// aligned (1); whole blocks may be read and written when the field also
+// sits in the zero-padded layout (2)
 static int rows_vectorizable(const FieldView &f, const float *p)
 {
-    return ((uintptr_t)p % 16 == 0) && f.sx % 4 == 0 && (f.ndim == 2 || f.sy % 4 == 0);
+    const bool aligned = ((uintptr_t)p % 16 == 0) && f.sx % 4 == 0 && (f.ndim == 2 || f.sy % 4 == 0);
+    return aligned ? (f.padded ? 2 : 1) : 0;
 }
 
 void codec_encode(const EncodeArgs &e, hipStream_t st)

@@ -116,6 +116,11 @@ struct FieldView {
     int ndim;
     long n[3];          // (x, y, z); 2D fields are (nx, 1, nz)
     long sx, sy;        // element strides of x and y (z contiguous)
+    // the field lives in the padded layout: rows start 16-byte aligned and
+    // at least 3 zero-valued points follow the field on every axis, so the
+    // codec may read and write whole 4^d blocks (writing zeros past the
+    // field's end keeps those pads zero)
+    int padded = 0;
 };
 
 struct CodecGeom {

@@ -411,6 +411,7 @@ FieldView padded_view(const Setup &s)
     f.n[2] = s.pad.nz;
     f.sx = s.pad.sx;
     f.sy = s.ndim == 3 ? s.pad.sy : 0;
+    f.padded = 1;
     return f;
 }
 
@@ -1513,7 +1514,105 @@ static FieldView dense_view(int ndim, const int n[3])
     f.n[2] = ndim == 3 ? n[2] : n[1];
     f.sx = f.n[1] * f.n[2];
     f.sy = ndim == 3 ? f.n[2] : 0;
+    f.padded = 0;
     return f;
+}
+
+// a field inside a larger array: element (x, y, z) at origin + x sx + y sy + z
+static FieldView checked_view(int ndim, const int n[3], long sx, long sy, int padded, const float *origin)
+{
+    if (ndim != 2 && ndim != 3) throw Error{FWI_EINVAL, "ndim must be 2 or 3"};
+    for (int d = 0; d < ndim; ++d)
+        if (n[d] < 1) throw Error{FWI_EINVAL, "dims must be >= 1"};
+    FieldView f;
+    f.ndim = ndim;
+    f.n[0] = n[0];
+    f.n[1] = ndim == 3 ? n[1] : 1;
+    f.n[2] = ndim == 3 ? n[2] : n[1];
+    f.sx = sx;
+    f.sy = ndim == 3 ? sy : 0;
+    f.padded = padded != 0;
+    const long slack = padded ? 3 : 0;
+    if (ndim == 3 ? (sy < f.n[2] + slack || sx < (f.n[1] + slack) * sy) : (sx < f.n[2] + slack))
+        throw Error{FWI_EINVAL, "strides overlap rows (or leave no room for the padding declared)"};
+    if (padded && ((uintptr_t)origin % 16 != 0 || sx % 4 != 0 || (ndim == 3 && sy % 4 != 0)))
+        throw Error{FWI_EINVAL, "a padded view needs 16-byte aligned rows"};
+    return f;
+}
+
+static void compress_view(fwi_ctx *c, const FieldView &f, const float *field, double atol, void *out,
+                          size_t cap, size_t *nbytes, hipStream_t st)
+{
+    if (!(atol >= 2.2250738585072014e-308) || !std::isfinite(atol))
+        throw Error{FWI_EINVAL, "atol must be a positive normal number"};
+    begin_call(c, st);
+    ensure_codec(c, f, 1);
+    reset_status(c, st);
+    EncodeArgs e{};
+    e.f = f;
+    e.src = field;
+    e.atol = atol;
+    e.scratch = c->scratch.p;
+    e.chunk_bits = c->chunk_bits.p;
+    e.chunk_off = c->chunk_off.p;
+    e.dst = (unsigned char *)out;
+    e.cap = cap;
+    e.out_bytes = c->misc.p + 0;
+    e.pool_high = c->misc.p + 1;
+    e.total_bytes = c->misc.p + 2;
+    e.flags = c->flags.p;
+    {
+        Timer tm(c, st, K_ENC);
+        codec_encode(e, st);
+    }
+    HIPCHK(hipGetLastError());
+    unsigned long long nb = 0;
+    HIPCHK(hipMemcpyAsync(&nb, c->misc.p, sizeof(nb), hipMemcpyDeviceToHost, st));
+    finish_status(c, st);
+    *nbytes = (size_t)nb;
+    c->stats.n_encode = 1;
+    end_call(c, st);
+}
+
+static void decompress_view(fwi_ctx *c, const FieldView &f, const void *stream, size_t nbytes, float *field,
+                            hipStream_t st)
+{
+    begin_call(c, st);
+    const int ndim = f.ndim;
+    CodecGeom g = codec_geom(ndim, f.n);
+    if (nbytes < 64) throw Error{FWI_ECORRUPT, "stream shorter than its header"};
+    unsigned char h[64];
+    HIPCHK(hipMemcpyAsync(h, stream, 64, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    auto u32 = [&](int o) { unsigned v; memcpy(&v, h + o, 4); return v; };
+    auto u64 = [&](int o) { unsigned long long v; memcpy(&v, h + o, 8); return v; };
+    const unsigned want[3] = {(unsigned)f.n[0], (unsigned)(ndim == 3 ? f.n[1] : f.n[2]),
+                              (unsigned)(ndim == 3 ? f.n[2] : 1)};
+    if (memcmp(h, "FWZ1", 4) != 0 || h[4] != 1 || h[5] != 0) throw Error{FWI_ECORRUPT, "bad magic or version"};
+    if (h[6] != ndim || h[7] != 24 || h[20] != g.guard || h[22] != g.tp ||
+        h[21] != (unsigned char)__builtin_ctz((unsigned)g.kblk))
+        throw Error{FWI_ECORRUPT, "stream parameters do not match"};
+    if (u32(8) != want[0] || u32(12) != want[1] || u32(16) != want[2])
+        throw Error{FWI_ECORRUPT, "stream dims do not match"};
+    if ((long)u32(36) != g.nchunks || (long)u64(40) != g.nblocks) throw Error{FWI_ECORRUPT, "bad tables"};
+    const unsigned long long pbits = u64(48);
+    const unsigned long long total = 64ull + (unsigned long long)g.table_bytes + 8ull * ((pbits + 63) / 64);
+    if (u64(56) != total || nbytes < total) throw Error{FWI_ECORRUPT, "stream length mismatch"};
+    reset_status(c, st);
+    DecodeArgs d{};
+    d.f = f;
+    d.dst = field;
+    d.stream = (const unsigned char *)stream;
+    d.nbytes = nbytes;
+    d.flags = c->flags.p;
+    {
+        Timer tm(c, st, K_DEC);
+        codec_decode(d, st);
+    }
+    HIPCHK(hipGetLastError());
+    finish_status(c, st);
+    c->stats.n_decode = 1;
+    end_call(c, st);
 }
 
 int ckpt_compress(fwi_ctx *c, const float *field, int ndim, const int n[3], double atol, void *out,
@@ -1524,36 +1623,16 @@ int ckpt_compress(fwi_ctx *c, const float *field, int ndim, const int n[3], doub
         if (ndim != 2 && ndim != 3) throw Error{FWI_EINVAL, "ndim must be 2 or 3"};
         for (int d = 0; d < ndim; ++d)
             if (n[d] < 1) throw Error{FWI_EINVAL, "dims must be >= 1"};
-        if (!(atol >= 2.2250738585072014e-308) || !std::isfinite(atol))
-            throw Error{FWI_EINVAL, "atol must be a positive normal number"};
-        begin_call(c, st);
-        FieldView f = dense_view(ndim, n);
-        ensure_codec(c, f, 1);
-        reset_status(c, st);
-        EncodeArgs e{};
-        e.f = f;
-        e.src = field;
-        e.atol = atol;
-        e.scratch = c->scratch.p;
-        e.chunk_bits = c->chunk_bits.p;
-        e.chunk_off = c->chunk_off.p;
-        e.dst = (unsigned char *)out;
-        e.cap = cap;
-        e.out_bytes = c->misc.p + 0;
-        e.pool_high = c->misc.p + 1;
-        e.total_bytes = c->misc.p + 2;
-        e.flags = c->flags.p;
-        {
-            Timer tm(c, st, K_ENC);
-            codec_encode(e, st);
-        }
-        HIPCHK(hipGetLastError());
-        unsigned long long nb = 0;
-        HIPCHK(hipMemcpyAsync(&nb, c->misc.p, sizeof(nb), hipMemcpyDeviceToHost, st));
-        finish_status(c, st);
-        *nbytes = (size_t)nb;
-        c->stats.n_encode = 1;
-        end_call(c, st);
+        compress_view(c, dense_view(ndim, n), field, atol, out, cap, nbytes, st);
+    });
+}
+
+int ckpt_compress_view(fwi_ctx *c, const float *origin, int ndim, const int n[3], long sx, long sy,
+                       int padded, double atol, void *out, size_t cap, size_t *nbytes, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !origin || !out || !nbytes || !n) throw Error{FWI_EINVAL, "null argument"};
+        compress_view(c, checked_view(ndim, n, sx, sy, padded, origin), origin, atol, out, cap, nbytes, st);
     });
 }
 
@@ -1565,42 +1644,16 @@ int ckpt_decompress(fwi_ctx *c, const void *stream, size_t nbytes, float *field,
         if (ndim != 2 && ndim != 3) throw Error{FWI_EINVAL, "ndim must be 2 or 3"};
         for (int d = 0; d < ndim; ++d)
             if (n[d] < 1) throw Error{FWI_EINVAL, "dims must be >= 1"};
-        begin_call(c, st);
-        FieldView f = dense_view(ndim, n);
-        CodecGeom g = codec_geom(ndim, f.n);
-        if (nbytes < 64) throw Error{FWI_ECORRUPT, "stream shorter than its header"};
-        unsigned char h[64];
-        HIPCHK(hipMemcpyAsync(h, stream, 64, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        auto u32 = [&](int o) { unsigned v; memcpy(&v, h + o, 4); return v; };
-        auto u64 = [&](int o) { unsigned long long v; memcpy(&v, h + o, 8); return v; };
-        const unsigned want[3] = {(unsigned)n[0], (unsigned)(ndim == 3 ? n[1] : n[1]),
-                                  (unsigned)(ndim == 3 ? n[2] : 1)};
-        if (memcmp(h, "FWZ1", 4) != 0 || h[4] != 1 || h[5] != 0) throw Error{FWI_ECORRUPT, "bad magic or version"};
-        if (h[6] != ndim || h[7] != 24 || h[20] != g.guard || h[22] != g.tp ||
-            h[21] != (unsigned char)__builtin_ctz((unsigned)g.kblk))
-            throw Error{FWI_ECORRUPT, "stream parameters do not match"};
-        if (u32(8) != want[0] || u32(12) != want[1] || u32(16) != want[2])
-            throw Error{FWI_ECORRUPT, "stream dims do not match"};
-        if ((long)u32(36) != g.nchunks || (long)u64(40) != g.nblocks) throw Error{FWI_ECORRUPT, "bad tables"};
-        const unsigned long long pbits = u64(48);
-        const unsigned long long total = 64ull + (unsigned long long)g.table_bytes + 8ull * ((pbits + 63) / 64);
-        if (u64(56) != total || nbytes < total) throw Error{FWI_ECORRUPT, "stream length mismatch"};
-        reset_status(c, st);
-        DecodeArgs d{};
-        d.f = f;
-        d.dst = field;
-        d.stream = (const unsigned char *)stream;
-        d.nbytes = nbytes;
-        d.flags = c->flags.p;
-        {
-            Timer tm(c, st, K_DEC);
-            codec_decode(d, st);
-        }
-        HIPCHK(hipGetLastError());
-        finish_status(c, st);
-        c->stats.n_decode = 1;
-        end_call(c, st);
+        decompress_view(c, dense_view(ndim, n), stream, nbytes, field, st);
+    });
+}
+
+int ckpt_decompress_view(fwi_ctx *c, const void *stream, size_t nbytes, float *origin, int ndim,
+                         const int n[3], long sx, long sy, int padded, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !stream || !origin || !n) throw Error{FWI_EINVAL, "null argument"};
+        decompress_view(c, checked_view(ndim, n, sx, sy, padded, origin), stream, nbytes, origin, st);
     });
 }
 

@@ -70,7 +70,8 @@ _lib = None
 EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_stats",
            "fwi_last_error", "fwi_forward", "fwi_gradient", "fwi_forward_ckpt",
            "fwi_backward", "fwi_tape_free", "ckpt_bound", "ckpt_compress",
-           "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune", "fwi_ckpt_pool_bytes", "fwi_forward_state", "fwi_gradient_batch", "fwi_ctx_set_graphs"]
+           "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune", "fwi_ckpt_pool_bytes", "fwi_forward_state", "fwi_gradient_batch", "fwi_ctx_set_graphs",
+           "ckpt_compress_view", "ckpt_decompress_view"]
 
 
 def lib():
@@ -88,6 +89,11 @@ def lib():
     L.fwi_ctx_destroy.argtypes = [P]
     L.fwi_ctx_set_timing.argtypes = [P, I]
     L.fwi_ctx_set_graphs.argtypes = [P, I]
+    CL = ctypes.c_long
+    L.ckpt_compress_view.argtypes = [P, P, I, ctypes.POINTER(ctypes.c_int), CL, CL, I, ctypes.c_double, P,
+                                     ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]
+    L.ckpt_decompress_view.argtypes = [P, P, ctypes.c_size_t, P, I, ctypes.POINTER(ctypes.c_int), CL, CL,
+                                       I, P]
     L.fwi_ctx_stats.argtypes = [P, ctypes.POINTER(fwi_stats)]
     L.fwi_last_error.restype = ctypes.c_char_p
     L.fwi_forward.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), P, P]
@@ -333,6 +339,24 @@ class Context:
         check(lib().ckpt_compress(self.h, _ptr(field), field.dim(), _dims3(field.shape), float(atol),
                                   _ptr(out), cap, ctypes.byref(nb), _stream()))
         return out[:nb.value]
+
+    def compress_view(self, array: torch.Tensor, offset: int, shape, sx: int, sy: int, padded: bool,
+                      atol: float) -> torch.Tensor:
+        """compress the field at element `offset` of a contiguous device array"""
+        cap = ckpt_bound(shape)
+        out = torch.empty(cap, dtype=torch.uint8, device=array.device)
+        nb = ctypes.c_size_t()
+        origin = ctypes.c_void_p(_ptr(array).value + 4 * int(offset))
+        check(lib().ckpt_compress_view(self.h, origin, len(shape), _dims3(shape), int(sx), int(sy),
+                                       int(bool(padded)), float(atol), _ptr(out), cap, ctypes.byref(nb),
+                                       _stream()))
+        return out[:nb.value]
+
+    def decompress_view(self, stream: torch.Tensor, array: torch.Tensor, offset: int, shape, sx: int,
+                        sy: int, padded: bool):
+        origin = ctypes.c_void_p(_ptr(array).value + 4 * int(offset))
+        check(lib().ckpt_decompress_view(self.h, _ptr(stream), stream.numel(), origin, len(shape),
+                                         _dims3(shape), int(sx), int(sy), int(bool(padded)), _stream()))
 
     def decompress(self, stream: torch.Tensor, shape) -> torch.Tensor:
         out = torch.empty(tuple(shape), dtype=torch.float32, device=stream.device)

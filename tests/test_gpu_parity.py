@@ -238,6 +238,59 @@ def test_codec_chunk_lengths_bit_exact(ctx, shape, kblk):
     assert np.array_equal(y.view(np.uint32), ocodec.decompress(ref, shape).view(np.uint32))
 
 
+def padded_array(x, pad=8):
+    """x inside a zero array with `pad` points before and after every axis
+    and 16-byte aligned rows: (array, origin offset, sx, sy)"""
+    if x.ndim == 3:
+        n0, n1, n2 = x.shape
+        pz = (2 * pad + n2 + 3) // 4 * 4
+        a = np.zeros((n0 + 2 * pad, n1 + 2 * pad, pz), np.float32)
+        a[pad:pad + n0, pad:pad + n1, pad:pad + n2] = x
+        sy, sx = pz, (n1 + 2 * pad) * pz
+        return a, pad * sx + pad * sy + pad, sx, sy
+    n0, n2 = x.shape
+    pz = (2 * pad + n2 + 3) // 4 * 4
+    a = np.zeros((n0 + 2 * pad, pz), np.float32)
+    a[pad:pad + n0, pad:pad + n2] = x
+    return a, pad * pz + pad, pz, 0
+
+
+@pytest.mark.parametrize("shape", [(37, 29, 45), (70, 66, 367), (130, 97), (181, 181)])
+@pytest.mark.parametrize("atol", [1e-3, 1e-5])
+def test_codec_views_bit_exact(ctx, shape, atol):
+    """the codec on a field inside a larger array (the layout checkpoints
+    use, padded = whole-block access): the same stream as the dense field,
+    and a padded decode writes the values and leaves every pad point zero"""
+    x = synth.wavefield_like(shape, seed=11)
+    ref = ocodec.compress(x, atol)
+    a, off, sx, sy = padded_array(x)
+    A = dev(a)
+    for padded in (True, False):
+        s = ctx.compress_view(A, off, shape, sx, sy, padded, atol).cpu().numpy().tobytes()
+        assert s == ref, padded
+    yref = ocodec.decompress(ref, shape)
+    for padded in (True, False):
+        Q = torch.zeros_like(A)
+        ctx.decompress_view(dev(np.frombuffer(ref, np.uint8).copy()), Q, off, shape, sx, sy, padded)
+        q = Q.cpu().numpy()
+        inner = tuple(slice(8, 8 + n) for n in shape)
+        assert np.array_equal(q[inner].view(np.uint32), yref.view(np.uint32)), padded
+        q[inner] = 0.0
+        assert not q.any(), padded
+
+
+def test_codec_view_rejects_bad_layouts(ctx):
+    x = synth.wavefield_like((20, 20, 20), seed=2)
+    a, off, sx, sy = padded_array(x)
+    A = dev(a)
+    with pytest.raises(F.FwiError):
+        ctx.compress_view(A, off + 1, x.shape, sx, sy, True, 1e-3)      # misaligned rows
+    with pytest.raises(F.FwiError):
+        ctx.compress_view(A, off, x.shape, sx, 19, False, 1e-3)         # rows overlap
+    s = ctx.compress_view(A, off + 1, x.shape, sx, sy, False, 1e-3)     # fine unpadded
+    assert s.numel() > 64
+
+
 def test_codec_on_oracle_wavefields(ctx):
     # float32-rounded states of an oracle FP64 propagation (2D and 3D)
     for ndim, n in ((2, 90), (3, 30)):
