@@ -266,16 +266,46 @@ __device__ __forceinline__ void block_coords(long b, const long *nb, long &bx, l
 }
 
 // ------------------------------------------------------------------ encode
+// arguments of the per-chunk encode and decode (one field)
+struct EncodeK {
+    FieldView f;
+    const float *src;
+    long nb0, nb1, nb2, nblocks, nchunks;
+    int kblk, minexp, vec;
+    unsigned long long *scratch;
+    long chunk_words;
+    unsigned long long *chunk_bits;
+    unsigned int *flags;
+};
+
+struct DecodeK {
+    FieldView f;
+    float *dst;
+    const unsigned char *stream, *pool;
+    const StreamSlot *slots;
+    int slot_index;
+    long nb0, nb1, nb2, nblocks, nchunks;
+    int kblk;
+    long nsuper, table_bytes;
+    unsigned int *flags;
+    int vec;
+};
+
 template <int D>
-__global__ __launch_bounds__(64)
-void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, long nblocks,
-                   long nchunks, int kblk, int minexp, unsigned long long *scratch, long chunk_words,
-                   unsigned long long *chunk_bits, unsigned int *flags, int vec)
+__device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
 {
     using GC = GeomC<D>;
     constexpr int SZ = GC::SZ;
     constexpr Seq<D> seq{};
-    const long c = (long)blockIdx.x * 64 + threadIdx.x;
+    const FieldView &f = k.f;
+    const float *src = k.src;
+    const long nb0 = k.nb0, nb1 = k.nb1, nb2 = k.nb2, nblocks = k.nblocks, nchunks = k.nchunks;
+    const int kblk = k.kblk, minexp = k.minexp, vec = k.vec;
+    unsigned long long *scratch = k.scratch;
+    const long chunk_words = k.chunk_words;
+    unsigned long long *chunk_bits = k.chunk_bits;
+    unsigned int *flags = k.flags;
+    const long c = blk * 64 + threadIdx.x;
     if (c >= nchunks) return;
     const long nb[3] = {nb0, nb1, nb2};
     BitWriter bw{0ull, 0, scratch + scratch_word(c, 0, chunk_words), 0};
@@ -410,18 +440,18 @@ void encode_kernel(FieldView f, const float *src, long nb0, long nb1, long nb2, 
 // --------------------------------------------------------------- placement
 constexpr int TILE = 1024;
 
-__global__ __launch_bounds__(TILE)
-void tile_sum_kernel(const unsigned long long *chunk_bits, long nchunks, unsigned long long *tile_sum)
+__device__ __forceinline__ void tile_sum_body(const unsigned long long *chunk_bits, long nchunks,
+                                              unsigned long long *tile_sum, long blk)
 {
     __shared__ unsigned long long red[TILE];
-    const long c = (long)blockIdx.x * TILE + threadIdx.x;
+    const long c = blk * TILE + threadIdx.x;
     red[threadIdx.x] = c < nchunks ? chunk_bits[c] : 0ull;
     __syncthreads();
     for (int s = TILE / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) tile_sum[blockIdx.x] = red[0];
+    if (threadIdx.x == 0) tile_sum[blk] = red[0];
 }
 
 struct PlanArgs {
@@ -456,8 +486,7 @@ __device__ __forceinline__ void st32(unsigned char *p, unsigned int v)
     for (int i = 0; i < 4; ++i) p[i] = (unsigned char)(v >> (8 * i));
 }
 
-__global__ __launch_bounds__(256)
-void plan_kernel(PlanArgs a)
+__device__ __forceinline__ void plan_body(const PlanArgs &a)
 {
     __shared__ unsigned long long sc[256];
     __shared__ unsigned long long carry;
@@ -543,13 +572,12 @@ struct PackArgs {
     const unsigned int *flags;
 };
 
-__global__ __launch_bounds__(TILE)
-void pack_kernel(PackArgs a)
+__device__ __forceinline__ void pack_body(const PackArgs &a, long blk)
 {
     __shared__ unsigned long long sc[TILE];
     if (*a.flags & 2u) return;
     unsigned char *dst = a.dst ? a.dst : a.pool + *a.dst_offset;
-    const long c = (long)blockIdx.x * TILE + threadIdx.x;
+    const long c = blk * TILE + threadIdx.x;
     const unsigned long long len = c < a.nchunks ? a.chunk_bits[c] : 0ull;
     sc[threadIdx.x] = len;
     __syncthreads();
@@ -560,12 +588,12 @@ void pack_kernel(PackArgs a)
         __syncthreads();
     }
     if (c < a.nchunks) {
-        const unsigned long long off = a.tile_prefix[blockIdx.x] + sc[threadIdx.x] - len;
+        const unsigned long long off = a.tile_prefix[blk] + sc[threadIdx.x] - len;
         // tables: super-chunk base (the first chunk of each super-chunk) and
         // relative chunk offsets (a super-chunk of 256 lies inside one tile)
         unsigned char *tab = dst + 64;
-        const long sup0 = (c / 256) * 256 - (long)blockIdx.x * TILE;   // in-tile index of the super-chunk head
-        const unsigned long long head = a.tile_prefix[blockIdx.x] + (sup0 > 0 ? sc[sup0 - 1] : 0ull);
+        const long sup0 = (c / 256) * 256 - blk * TILE;   // in-tile index of the super-chunk head
+        const unsigned long long head = a.tile_prefix[blk] + (sup0 > 0 ? sc[sup0 - 1] : 0ull);
         if ((c & 255) == 0) st64(tab + 8 * (c / 256), off);
         st32(tab + 8 * a.nsuper + 4 * c, (unsigned int)(off - head));
     }
@@ -575,9 +603,9 @@ void pack_kernel(PackArgs a)
     // the word's first bit by binary search over the tile's prefix sums
     __syncthreads();
     unsigned long long *out = (unsigned long long *)(dst + 64 + a.table_bytes);
-    const unsigned long long base = a.tile_prefix[blockIdx.x];
+    const unsigned long long base = a.tile_prefix[blk];
     const unsigned long long tile_end = base + sc[TILE - 1];
-    const long c0 = (long)blockIdx.x * TILE;
+    const long c0 = blk * TILE;
     for (unsigned long long w = ((base + 63ull) >> 6) + threadIdx.x; (w << 6) < tile_end; w += TILE) {
         unsigned long long pos = w << 6;
         int lo = 0, hi = TILE - 1;
@@ -627,16 +655,22 @@ __device__ __forceinline__ unsigned long long chunk_start(const unsigned char *s
 }
 
 template <int D>
-__global__ __launch_bounds__(64)
-void decode_kernel(FieldView f, float *dst, const unsigned char *stream, const unsigned char *pool,
-                   const StreamSlot *slots, int slot_index, long nb0, long nb1, long nb2,
-                   long nblocks, long nchunks, int kblk, long nsuper, long table_bytes,
-                   unsigned int *flags, int vec)
+__device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
 {
     using GC = GeomC<D>;
     constexpr int SZ = GC::SZ;
     constexpr Seq<D> seq{};
-    const long c = (long)blockIdx.x * 64 + threadIdx.x;
+    const FieldView &f = k.f;
+    float *dst = k.dst;
+    const unsigned char *stream = k.stream, *pool = k.pool;
+    const StreamSlot *slots = k.slots;
+    const int slot_index = k.slot_index;
+    const long nb0 = k.nb0, nb1 = k.nb1, nb2 = k.nb2, nblocks = k.nblocks, nchunks = k.nchunks;
+    const int kblk = k.kblk;
+    const long nsuper = k.nsuper, table_bytes = k.table_bytes;
+    unsigned int *flags = k.flags;
+    const int vec = k.vec;
+    const long c = blk * 64 + threadIdx.x;
     if (c >= nchunks) return;
     const unsigned char *s = stream;
     if (!s) {
@@ -805,23 +839,40 @@ static int rows_vectorizable(const FieldView &f, const float *p)
     return aligned ? (f.padded ? 2 : 1) : 0;
 }
 
-void codec_encode(const EncodeArgs &e, hipStream_t st)
+// one field's encode pipeline: encode -> tile sums -> placement -> pack
+struct EncJob {
+    EncodeK enc;
+    PlanArgs plan;
+    PackArgs pack;
+    int wave0, tile0;          // first encode wave / first tile in a batched launch
+};
+
+struct DecJob {
+    DecodeK dec;
+    int wave0;
+};
+
+static EncJob make_enc_job(const EncodeArgs &e)
 {
-    CodecGeom g = codec_geom(e.f.ndim, e.f.n);
+    const CodecGeom g = codec_geom(e.f.ndim, e.f.n);
     const int minexp = minexp_of(e.atol);
-    const int nwaves = (int)(g.nchunks / 64);
-    if (e.f.ndim == 3)
-        hipLaunchKernelGGL(encode_kernel<3>, dim3(nwaves), dim3(64), 0, st, e.f, e.src, g.nb[0], g.nb[1],
-                           g.nb[2], g.nblocks, g.nchunks, g.kblk, minexp, e.scratch, g.max_chunk_words,
-                           e.chunk_bits, e.flags, rows_vectorizable(e.f, e.src));
-    else
-        hipLaunchKernelGGL(encode_kernel<2>, dim3(nwaves), dim3(64), 0, st, e.f, e.src, g.nb[0], g.nb[1],
-                           g.nb[2], g.nblocks, g.nchunks, g.kblk, minexp, e.scratch, g.max_chunk_words,
-                           e.chunk_bits, e.flags, rows_vectorizable(e.f, e.src));
     const int ntiles = (int)((g.nchunks + TILE - 1) / TILE);
-    unsigned long long *tile = e.chunk_off;   // ntiles entries
-    hipLaunchKernelGGL(tile_sum_kernel, dim3(ntiles), dim3(TILE), 0, st, e.chunk_bits, g.nchunks, tile);
-    PlanArgs pa;
+    EncJob j{};
+    EncodeK &k = j.enc;
+    k.f = e.f;
+    k.src = e.src;
+    k.nb0 = g.nb[0]; k.nb1 = g.nb[1]; k.nb2 = g.nb[2];
+    k.nblocks = g.nblocks;
+    k.nchunks = g.nchunks;
+    k.kblk = g.kblk;
+    k.minexp = minexp;
+    k.vec = rows_vectorizable(e.f, e.src);
+    k.scratch = e.scratch;
+    k.chunk_words = g.max_chunk_words;
+    k.chunk_bits = e.chunk_bits;
+    k.flags = e.flags;
+    unsigned long long *tile = e.chunk_off;   // ntiles sums, then the pool offset
+    PlanArgs &pa = j.plan;
     pa.ndim = e.f.ndim;
     if (e.f.ndim == 3) {
         pa.dims[0] = (unsigned)e.f.n[0]; pa.dims[1] = (unsigned)e.f.n[1]; pa.dims[2] = (unsigned)e.f.n[2];
@@ -851,8 +902,7 @@ void codec_encode(const EncodeArgs &e, hipStream_t st)
     pa.flags = e.flags;
     pa.pool_high = e.pool_high;
     pa.total_bytes = e.total_bytes;
-    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, pa);
-    PackArgs ka;
+    PackArgs &ka = j.pack;
     ka.scratch = e.scratch;
     ka.chunk_words = g.max_chunk_words;
     ka.chunk_bits = e.chunk_bits;
@@ -864,21 +914,154 @@ void codec_encode(const EncodeArgs &e, hipStream_t st)
     ka.pool = e.pool;
     ka.dst_offset = e.chunk_off + ntiles;
     ka.flags = e.flags;
-    hipLaunchKernelGGL(pack_kernel, dim3(ntiles), dim3(TILE), 0, st, ka);
+    j.wave0 = 0;
+    j.tile0 = 0;
+    return j;
+}
+
+static DecJob make_dec_job(const DecodeArgs &d)
+{
+    const CodecGeom g = codec_geom(d.f.ndim, d.f.n);
+    DecJob j{};
+    DecodeK &k = j.dec;
+    k.f = d.f;
+    k.dst = d.dst;
+    k.stream = d.stream;
+    k.pool = d.pool;
+    k.slots = d.slots;
+    k.slot_index = d.slot_index;
+    k.nb0 = g.nb[0]; k.nb1 = g.nb[1]; k.nb2 = g.nb[2];
+    k.nblocks = g.nblocks;
+    k.nchunks = g.nchunks;
+    k.kblk = g.kblk;
+    k.nsuper = g.nsuper;
+    k.table_bytes = g.table_bytes;
+    k.flags = d.flags;
+    k.vec = rows_vectorizable(d.f, d.dst);
+    j.wave0 = 0;
+    return j;
+}
+
+// ---- single-field kernels
+template <int D>
+__global__ __launch_bounds__(64) void encode_kernel(EncodeK k) { encode_body<D>(k, blockIdx.x); }
+
+__global__ __launch_bounds__(TILE) void tile_sum_kernel(const unsigned long long *chunk_bits, long nchunks,
+                                                        unsigned long long *tile_sum)
+{
+    tile_sum_body(chunk_bits, nchunks, tile_sum, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void plan_kernel(PlanArgs a) { plan_body(a); }
+
+__global__ __launch_bounds__(TILE) void pack_kernel(PackArgs a) { pack_body(a, blockIdx.x); }
+
+template <int D>
+__global__ __launch_bounds__(64) void decode_kernel(DecodeK k) { decode_body<D>(k, blockIdx.x); }
+
+// ---- batched kernels: a block finds its field by binary search over the
+// first block of every job
+template <class J>
+__device__ __forceinline__ int job_of(const J *__restrict__ jobs, int n, int blk, int J::*first)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].*first <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void encode_batch_kernel(const EncJob *__restrict__ jobs, int n)
+{
+    const int j = job_of(jobs, n, blockIdx.x, &EncJob::wave0);
+    encode_body<D>(jobs[j].enc, (long)blockIdx.x - jobs[j].wave0);
+}
+
+__global__ __launch_bounds__(TILE) void tile_sum_batch_kernel(const EncJob *__restrict__ jobs, int n)
+{
+    const int j = job_of(jobs, n, blockIdx.x, &EncJob::tile0);
+    tile_sum_body(jobs[j].enc.chunk_bits, jobs[j].enc.nchunks, jobs[j].plan.tile_sum,
+                  (long)blockIdx.x - jobs[j].tile0);
+}
+
+__global__ __launch_bounds__(256) void plan_batch_kernel(const EncJob *__restrict__ jobs)
+{
+    plan_body(jobs[blockIdx.x].plan);
+}
+
+__global__ __launch_bounds__(TILE) void pack_batch_kernel(const EncJob *__restrict__ jobs, int n)
+{
+    const int j = job_of(jobs, n, blockIdx.x, &EncJob::tile0);
+    pack_body(jobs[j].pack, (long)blockIdx.x - jobs[j].tile0);
+}
+
+template <int D>
+__global__ __launch_bounds__(64) void decode_batch_kernel(const DecJob *__restrict__ jobs, int n)
+{
+    const int j = job_of(jobs, n, blockIdx.x, &DecJob::wave0);
+    decode_body<D>(jobs[j].dec, (long)blockIdx.x - jobs[j].wave0);
+}
+
+void codec_encode(const EncodeArgs &e, hipStream_t st)
+{
+    const EncJob j = make_enc_job(e);
+    const int nwaves = (int)(j.enc.nchunks / 64);
+    if (e.f.ndim == 3) hipLaunchKernelGGL(encode_kernel<3>, dim3(nwaves), dim3(64), 0, st, j.enc);
+    else hipLaunchKernelGGL(encode_kernel<2>, dim3(nwaves), dim3(64), 0, st, j.enc);
+    hipLaunchKernelGGL(tile_sum_kernel, dim3(j.plan.ntiles), dim3(TILE), 0, st, j.enc.chunk_bits,
+                       j.enc.nchunks, j.plan.tile_sum);
+    hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, j.plan);
+    hipLaunchKernelGGL(pack_kernel, dim3(j.plan.ntiles), dim3(TILE), 0, st, j.pack);
 }
 
 void codec_decode(const DecodeArgs &d, hipStream_t st)
 {
-    CodecGeom g = codec_geom(d.f.ndim, d.f.n);
-    const int nwaves = (int)(g.nchunks / 64);
-    if (d.f.ndim == 3)
-        hipLaunchKernelGGL(decode_kernel<3>, dim3(nwaves), dim3(64), 0, st, d.f, d.dst, d.stream, d.pool,
-                           d.slots, d.slot_index, g.nb[0], g.nb[1], g.nb[2], g.nblocks, g.nchunks,
-                           g.kblk, g.nsuper, g.table_bytes, d.flags, rows_vectorizable(d.f, d.dst));
-    else
-        hipLaunchKernelGGL(decode_kernel<2>, dim3(nwaves), dim3(64), 0, st, d.f, d.dst, d.stream, d.pool,
-                           d.slots, d.slot_index, g.nb[0], g.nb[1], g.nb[2], g.nblocks, g.nchunks,
-                           g.kblk, g.nsuper, g.table_bytes, d.flags, rows_vectorizable(d.f, d.dst));
+    const DecJob j = make_dec_job(d);
+    const int nwaves = (int)(j.dec.nchunks / 64);
+    if (d.f.ndim == 3) hipLaunchKernelGGL(decode_kernel<3>, dim3(nwaves), dim3(64), 0, st, j.dec);
+    else hipLaunchKernelGGL(decode_kernel<2>, dim3(nwaves), dim3(64), 0, st, j.dec);
+}
+
+size_t codec_job_bytes(bool encode) { return encode ? sizeof(EncJob) : sizeof(DecJob); }
+
+void codec_encode_batch(const EncodeArgs *args, int n, void *host_jobs, void *dev_jobs, bool upload,
+                        hipStream_t st)
+{
+    EncJob *h = (EncJob *)host_jobs;
+    int waves = 0, tiles = 0;
+    for (int i = 0; i < n; ++i) {
+        h[i] = make_enc_job(args[i]);
+        h[i].wave0 = waves;
+        h[i].tile0 = tiles;
+        waves += (int)(h[i].enc.nchunks / 64);
+        tiles += h[i].plan.ntiles;
+    }
+    const EncJob *d = (const EncJob *)dev_jobs;
+    if (upload) (void)hipMemcpyAsync(dev_jobs, host_jobs, (size_t)n * sizeof(EncJob), hipMemcpyHostToDevice, st);
+    if (args[0].f.ndim == 3) hipLaunchKernelGGL(encode_batch_kernel<3>, dim3(waves), dim3(64), 0, st, d, n);
+    else hipLaunchKernelGGL(encode_batch_kernel<2>, dim3(waves), dim3(64), 0, st, d, n);
+    hipLaunchKernelGGL(tile_sum_batch_kernel, dim3(tiles), dim3(TILE), 0, st, d, n);
+    hipLaunchKernelGGL(plan_batch_kernel, dim3(n), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(pack_batch_kernel, dim3(tiles), dim3(TILE), 0, st, d, n);
+}
+
+void codec_decode_batch(const DecodeArgs *args, int n, void *host_jobs, void *dev_jobs, bool upload,
+                        hipStream_t st)
+{
+    DecJob *h = (DecJob *)host_jobs;
+    int waves = 0;
+    for (int i = 0; i < n; ++i) {
+        h[i] = make_dec_job(args[i]);
+        h[i].wave0 = waves;
+        waves += (int)(h[i].dec.nchunks / 64);
+    }
+    const DecJob *d = (const DecJob *)dev_jobs;
+    if (upload) (void)hipMemcpyAsync(dev_jobs, host_jobs, (size_t)n * sizeof(DecJob), hipMemcpyHostToDevice, st);
+    if (args[0].f.ndim == 3) hipLaunchKernelGGL(decode_batch_kernel<3>, dim3(waves), dim3(64), 0, st, d, n);
+    else hipLaunchKernelGGL(decode_batch_kernel<2>, dim3(waves), dim3(64), 0, st, d, n);
 }
 
 }  // namespace fwi

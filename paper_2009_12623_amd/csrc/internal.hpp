@@ -180,4 +180,15 @@ struct DecodeArgs {
 };
 void codec_decode(const DecodeArgs &a, hipStream_t st);
 
+// Several fields in one launch per pipeline stage (fields of one ndim; each
+// with its own scratch, tables and destination).  host_jobs / dev_jobs:
+// n * codec_job_bytes(encode) bytes each; with upload the job table is
+// copied to dev_jobs on the stream before the launches, otherwise dev_jobs
+// must already hold it when the launches run.
+size_t codec_job_bytes(bool encode);
+void codec_encode_batch(const EncodeArgs *args, int n, void *host_jobs, void *dev_jobs, bool upload,
+                        hipStream_t st);
+void codec_decode_batch(const DecodeArgs *args, int n, void *host_jobs, void *dev_jobs, bool upload,
+                        hipStream_t st);
+
 }  // namespace fwi

@@ -121,26 +121,34 @@ struct ShotBufs {
     }
 };
 
-// Launch tables of batched steps: one BatchEntry per shot per launch, staged
-// in pinned host memory and copied to the device just before the launch.
-// Every launch of a call has its own slot, and a call ends with a stream
+// Launch tables of batched calls (step entries, codec jobs), staged in
+// pinned host memory and copied to the device just before their launch.
+// Every launch of a call has its own slice, and a call ends with a stream
 // synchronisation, so no copy overwrites a table a queued launch reads.
 struct BatchTables {
-    BatchEntry *host = nullptr;
-    DevBuf<BatchEntry> dev;
+    char *host = nullptr;
+    DevBuf<char> dev;
     size_t cap = 0, used = 0;
     void ensure(size_t n)
     {
         used = 0;
         if (n <= cap) return;
         release();
-        if (hipHostMalloc((void **)&host, n * sizeof(BatchEntry), hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc((void **)&host, n, hipHostMallocDefault) != hipSuccess) {
             host = nullptr;
             (void)hipGetLastError();
             throw Error{FWI_ENOMEM, "pinned allocation of launch tables failed"};
         }
         dev.ensure(n);
         cap = n;
+    }
+    // byte offset of a new slice of `bytes` (256-byte aligned)
+    size_t take(size_t bytes)
+    {
+        const size_t off = used;
+        used = (used + bytes + 255) & ~(size_t)255;
+        if (used > cap) throw Error{FWI_EINVAL, "internal: launch tables exhausted"};
+        return off;
     }
     void release()
     {
@@ -179,7 +187,7 @@ struct fwi_ctx {
         unsigned long long gen = 0;
         long long n_forward = 0, n_adjoint = 0, n_encode = 0, n_decode = 0;
         long long ckpt_raw_bytes = 0, ckpt_bytes_host = 0;
-        BatchEntry *tables = nullptr;      // batched launch tables of this graph
+        char *tables = nullptr;            // batched launch tables of this graph
     };
     std::map<std::string, GraphEntry> gcache;
     // the legacy null stream cannot be captured: schedules of calls made on
@@ -493,6 +501,8 @@ struct Exec {
     const fwi_shot *shot;
     ShotBufs *B = &c->sb;
     unsigned long long *misc = nullptr;  // counters of the stream stack (set with the pool)
+    // codec scratch of this shot (batched calls); nullptr: the context's
+    unsigned long long *scr = nullptr, *cbits = nullptr, *coff = nullptr;
     float *cur = nullptr, *prev = nullptr;
     bool prev_valid = true;
     int work = 0;
@@ -650,13 +660,42 @@ struct Exec {
     }
 
     // store x_k; the older level only when the schedule will advance from it
-    void takeshot(int slot, int k, bool both)
+    void takeshot_book(int slot, int k, bool both)
     {
         if (work != k) throw Error{FWI_EINVAL, "internal: takeshot of a state not held"};
         if ((int)slot_both.size() <= slot) slot_both.resize(slot + 1, 0);
         slot_both[slot] = both;
+        c->stats.ckpt_raw_bytes += (long long)(both ? 2 : 1) * (long long)S.ncomp * 4;
+    }
+
+    EncodeArgs encode_args(int slot, int lev) const
+    {
+        EncodeArgs e{};
+        e.f = padded_view(S);
+        e.src = at_origin(lev == 0 ? cur : prev);
+        e.atol = atol;
+        e.scratch = scr ? scr : c->scratch.p;
+        e.chunk_bits = cbits ? cbits : c->chunk_bits.p;
+        e.chunk_off = coff ? coff : c->chunk_off.p;
+        e.dst = nullptr;
+        e.pool = pool;
+        e.pool_cap = pool_cap;
+        e.slots = slots;
+        e.slot_index = 2 * slot + lev;
+        // streams are stacked: this one starts after the last stream of
+        // the slot below (or after level 0 of this slot)
+        e.prev_index = lev == 1 ? 2 * slot : (slot == 0 ? -1 : 2 * (slot - 1) + (slot_both[slot - 1] ? 1 : 0));
+        e.out_bytes = misc + 0;
+        e.pool_high = misc + 1;
+        e.total_bytes = misc + 2;
+        e.flags = c->flags.p;
+        return e;
+    }
+
+    void takeshot(int slot, int k, bool both)
+    {
+        takeshot_book(slot, k, both);
         const int levels = both ? 2 : 1;
-        c->stats.ckpt_raw_bytes += (long long)levels * (long long)S.ncomp * 4;
         if (!compress) {
             const size_t off = (size_t)(2 * slot) * raw_bytes;
             launch_copy((float *)(pool + off), cur, raw_bytes / sizeof(float), st);
@@ -668,28 +707,31 @@ struct Exec {
         }
         for (int lev = 0; lev < levels; ++lev) {
             Timer tm(c, st, K_ENC);
-            EncodeArgs e{};
-            e.f = padded_view(S);
-            e.src = at_origin(lev == 0 ? cur : prev);
-            e.atol = atol;
-            e.scratch = c->scratch.p;
-            e.chunk_bits = c->chunk_bits.p;
-            e.chunk_off = c->chunk_off.p;
-            e.dst = nullptr;
-            e.pool = pool;
-            e.pool_cap = pool_cap;
-            e.slots = slots;
-            e.slot_index = 2 * slot + lev;
-            // streams are stacked: this one starts after the last stream of
-            // the slot below (or after level 0 of this slot)
-            e.prev_index = lev == 1 ? 2 * slot : (slot == 0 ? -1 : 2 * (slot - 1) + (slot_both[slot - 1] ? 1 : 0));
-            e.out_bytes = misc + 0;
-            e.pool_high = misc + 1;
-            e.total_bytes = misc + 2;
-            e.flags = c->flags.p;
-            codec_encode(e, st);
+            codec_encode(encode_args(slot, lev), st);
             c->stats.n_encode += 1;
         }
+    }
+
+    DecodeArgs decode_args(int slot, int lev) const
+    {
+        DecodeArgs d{};
+        d.f = padded_view(S);
+        d.dst = at_origin(lev == 0 ? W0() : W1());
+        d.stream = nullptr;
+        d.pool = pool;
+        d.slots = slots;
+        d.slot_index = 2 * slot + lev;
+        d.flags = c->flags.p;
+        return d;
+    }
+
+    // working state after decoding a compressed checkpoint into W0 (and W1)
+    void restore_commit(int k, bool only_cur)
+    {
+        cur = W0();
+        prev = W1();
+        prev_valid = !only_cur;
+        work = k;
     }
 
     void restore(int slot, int k, bool only_cur)
@@ -708,20 +750,10 @@ struct Exec {
         } else {
             for (int lev = 0; lev < (only_cur ? 1 : 2); ++lev) {
                 Timer tm(c, st, K_DEC);
-                DecodeArgs d{};
-                d.f = padded_view(S);
-                d.dst = at_origin(lev == 0 ? W0() : W1());
-                d.stream = nullptr;
-                d.pool = pool;
-                d.slots = slots;
-                d.slot_index = 2 * slot + lev;
-                d.flags = c->flags.p;
-                codec_decode(d, st);
+                codec_decode(decode_args(slot, lev), st);
                 c->stats.n_decode += 1;
             }
-            cur = W0();
-            prev = W1();
-            prev_valid = !only_cur;
+            restore_commit(k, only_cur);
         }
         work = k;
     }
@@ -926,7 +958,7 @@ struct BatchExec {
     hipStream_t st;
     std::vector<Exec> &ex;
     int ndim, R;
-    BatchEntry *dev_base;      // device tables the launches read
+    char *dev_base;            // device tables the launches read
     bool upload;               // copy each table before its launch (eager runs)
     std::vector<StepParams> ps;
 
@@ -934,8 +966,8 @@ struct BatchExec {
     {
         const int n = (int)ex.size();
         BatchTables &t = c->btab;
-        if (t.used + (size_t)n > t.cap) throw Error{FWI_EINVAL, "internal: launch tables exhausted"};
-        BatchEntry *h = t.host + t.used;
+        const size_t off = t.take((size_t)n * sizeof(BatchEntry));
+        BatchEntry *h = (BatchEntry *)(t.host + off);
         int first = 0;
         for (int i = 0; i < n; ++i) {
             h[i] = BatchEntry{};
@@ -944,10 +976,9 @@ struct BatchExec {
             h[i].first = first;
             first += step_geometry(h[i], ndim, adj);
         }
-        BatchEntry *d = dev_base + t.used;
+        BatchEntry *d = (BatchEntry *)(dev_base + off);
         if (upload) HIPCHK(hipMemcpyAsync(d, h, (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice, st));
         launch_step_batch(d, n, first, ndim, R, adj, st);
-        t.used += n;
     }
 
     void advance(int a, int b)
@@ -976,18 +1007,54 @@ struct BatchExec {
         for (auto &e : ex) e.post_reverse(k);
     }
 
+    // compressed checkpoints: one encode pipeline (decode launch) per level
+    // for all shots
+    void takeshot(int slot, int k, bool both)
+    {
+        if (!ex[0].compress) {
+            for (auto &e : ex) e.takeshot(slot, k, both);
+            return;
+        }
+        for (auto &e : ex) e.takeshot_book(slot, k, both);
+        const int n = (int)ex.size();
+        std::vector<EncodeArgs> args(n);
+        for (int lev = 0; lev < (both ? 2 : 1); ++lev) {
+            Timer tm(c, st, K_ENC);
+            for (int i = 0; i < n; ++i) args[i] = ex[i].encode_args(slot, lev);
+            const size_t off = c->btab.take((size_t)n * codec_job_bytes(true));
+            codec_encode_batch(args.data(), n, c->btab.host + off, dev_base + off, upload, st);
+            c->stats.n_encode += n;
+        }
+    }
+
+    void restore(int slot, int k, bool only_cur)
+    {
+        if (slot < 0 || !ex[0].compress) {
+            for (auto &e : ex) e.restore(slot, k, only_cur);
+            return;
+        }
+        const int n = (int)ex.size();
+        std::vector<DecodeArgs> args(n);
+        for (int lev = 0; lev < (only_cur ? 1 : 2); ++lev) {
+            Timer tm(c, st, K_DEC);
+            for (int i = 0; i < n; ++i) args[i] = ex[i].decode_args(slot, lev);
+            const size_t off = c->btab.take((size_t)n * codec_job_bytes(false));
+            codec_decode_batch(args.data(), n, c->btab.host + off, dev_base + off, upload, st);
+            c->stats.n_decode += n;
+        }
+        for (auto &e : ex) e.restore_commit(k, only_cur);
+    }
+
     void run(const std::vector<fwi_action> &acts, const std::vector<char> &both)
     {
         for (size_t i = 0; i < acts.size(); ++i) {
             const fwi_action &a = acts[i];
             switch (a.op) {
             case FWI_ADVANCE: advance(a.a, a.b); break;
-            case FWI_TAKESHOT:
-                for (auto &e : ex) e.takeshot(a.a, a.b, both[i] != 0);
-                break;
+            case FWI_TAKESHOT: takeshot(a.a, a.b, both[i] != 0); break;
             case FWI_RESTORE: {
                 const bool only = ex[0].compress && i + 1 < acts.size() && acts[i + 1].op == FWI_REVERSE;
-                for (auto &e : ex) e.restore(a.a, a.b, only);
+                restore(a.a, a.b, only);
                 break;
             }
             case FWI_REVERSE: reverse(a.a); break;
@@ -998,15 +1065,22 @@ struct BatchExec {
     }
 };
 
-// batched launches one action list needs (one per forward step, one per reverse step)
-size_t launches_of(const std::vector<fwi_action> &acts)
+// table bytes one batched action list needs (an upper bound: every step
+// launch, and two levels per checkpoint taken or restored)
+size_t table_bytes_of(const std::vector<fwi_action> &acts, size_t nshots)
 {
+    auto slice = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t step = slice(nshots * sizeof(BatchEntry));
+    const size_t enc = 2 * slice(nshots * codec_job_bytes(true));
+    const size_t dec = 2 * slice(nshots * codec_job_bytes(false));
     size_t n = 0;
     for (auto &a : acts) {
-        if (a.op == FWI_ADVANCE) n += (size_t)(a.b - a.a);
-        else if (a.op == FWI_REVERSE) n += 1;
+        if (a.op == FWI_ADVANCE) n += (size_t)(a.b - a.a) * step;
+        else if (a.op == FWI_REVERSE) n += step;
+        else if (a.op == FWI_TAKESHOT) n += enc;
+        else if (a.op == FWI_RESTORE) n += dec;
     }
-    return n;
+    return n + 256;
 }
 
 // ------------------------------------------------------- captured schedules
@@ -1041,10 +1115,10 @@ void key_shot(KeyBuilder &k, fwi_ctx *c, const fwi_grid *g, const fwi_shot *sh, 
 // every launch of the schedule; batched runs get a device table buffer owned
 // by the graph (filled once after the capture) in place of per-launch copies.
 template <class Issue>
-void run_schedule(fwi_ctx *c, hipStream_t caller, const std::string &key, size_t table_entries, Issue &&issue)
+void run_schedule(fwi_ctx *c, hipStream_t caller, const std::string &key, size_t table_bytes, Issue &&issue)
 {
     if (!c->graphs) {
-        issue((BatchEntry *)nullptr, caller);
+        issue((char *)nullptr, caller);
         return;
     }
     hipStream_t st = caller;
@@ -1067,7 +1141,7 @@ void run_schedule(fwi_ctx *c, hipStream_t caller, const std::string &key, size_t
     }
     if (it == c->gcache.end()) {
         fwi_ctx::GraphEntry ge;
-        if (table_entries && hipMalloc((void **)&ge.tables, table_entries * sizeof(BatchEntry)) != hipSuccess) {
+        if (table_bytes && hipMalloc((void **)&ge.tables, table_bytes) != hipSuccess) {
             (void)hipGetLastError();
             throw Error{FWI_ENOMEM, "allocation of captured launch tables failed"};
         }
@@ -1092,8 +1166,8 @@ void run_schedule(fwi_ctx *c, hipStream_t caller, const std::string &key, size_t
             if (ge.tables) (void)hipFree(ge.tables);
             throw Error{FWI_EHIP, std::string("graph instantiation failed: ") + hipGetErrorString(e)};
         }
-        if (table_entries)
-            HIPCHK(hipMemcpy(ge.tables, c->btab.host, table_entries * sizeof(BatchEntry), hipMemcpyHostToDevice));
+        if (table_bytes)
+            HIPCHK(hipMemcpy(ge.tables, c->btab.host, c->btab.used, hipMemcpyHostToDevice));
         ge.gen = g_alloc_gen;
         ge.n_forward = c->stats.n_forward - before.n_forward;
         ge.n_adjoint = c->stats.n_adjoint - before.n_adjoint;
@@ -1261,7 +1335,7 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         key.add('G');
         key_shot(key, c, g, shot, ex.S);
         key.add(m).add(d_obs).add(grad).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
-        run_schedule(c, st, key.s, 0, [&](BatchEntry *, hipStream_t rs) {
+        run_schedule(c, st, key.s, 0, [&](char *, hipStream_t rs) {
             ex.st = rs;
             ex.run(acts, restart_flags(acts), 0, false);
             launch_unpad(c->sb.gacc.p, grad, ex.padmap(), rs);
@@ -1309,8 +1383,23 @@ int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const floa
             acc += (double)setups[i].pad.elems();
             off[i + 1] = i + 1 == nshots ? cap : ((size_t)((double)cap * (acc / wsum)) & ~(size_t)255);
         }
-        if (cfg->compress)
-            for (auto &S : setups) ensure_codec(c, padded_view(S), 1);
+        // codec scratch: one region per shot (the shots' fields are encoded
+        // in one launch)
+        std::vector<size_t> scr_off(nshots + 1, 0), cb_off(nshots + 1, 0), co_off(nshots + 1, 0);
+        for (int i = 0; i < nshots; ++i) {
+            const FieldView fv = padded_view(setups[i]);
+            const CodecGeom cg = codec_geom(fv.ndim, fv.n);
+            scr_off[i + 1] = scr_off[i] + (size_t)cg.nchunks * cg.max_chunk_words;
+            cb_off[i + 1] = cb_off[i] + (size_t)cg.nchunks;
+            co_off[i + 1] = co_off[i] + (size_t)((cg.nchunks + 1023) / 1024) + 2;
+        }
+        if (cfg->compress) {
+            c->scratch.ensure(scr_off[nshots]);
+            c->chunk_bits.ensure(cb_off[nshots]);
+            c->chunk_off.ensure(co_off[nshots]);
+        }
+        c->misc.ensure(4);
+        c->flags.ensure(1);
         reset_status(c, st);
         std::vector<Exec> ex;
         ex.reserve(nshots);
@@ -1322,6 +1411,11 @@ int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const floa
             HIPCHK(hipMemsetAsync(b->misc.p, 0, 4 * sizeof(unsigned long long), st));
             Exec e{c, setups[i], st, models[i], &shots[i], b};
             e.misc = b->misc.p;
+            if (cfg->compress) {
+                e.scr = c->scratch.p + scr_off[i];
+                e.cbits = c->chunk_bits.p + cb_off[i];
+                e.coff = c->chunk_off.p + co_off[i];
+            }
             setup_ckpt(e, cfg, c->pool.p + off[i], off[i + 1] - off[i], b->slots.p, used);
             const size_t nd = (size_t)nt * e.S.nrec;
             b->dsim.ensure(std::max<size_t>(nd, 1));
@@ -1336,15 +1430,16 @@ int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const floa
             e.init_adjoint();
             ex.push_back(std::move(e));
         }
-        const size_t nent = launches_of(acts) * (size_t)nshots;
-        c->btab.ensure(nent);
+        const size_t nbytes_tab = table_bytes_of(acts, (size_t)nshots);
         KeyBuilder key;
         key.add('B').add(nshots).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
         for (int i = 0; i < nshots; ++i) {
             key_shot(key, c, &grids[i], &shots[i], setups[i]);
             key.add(models[i]).add(d_obs[i]).add(grads[i]);
         }
-        run_schedule(c, st, key.s, nent, [&](BatchEntry *gtab, hipStream_t rs) {
+        c->btab.ensure(nbytes_tab);     // before any capture: it may allocate
+        run_schedule(c, st, key.s, nbytes_tab, [&](char *gtab, hipStream_t rs) {
+            c->btab.used = 0;
             for (auto &e : ex) e.st = rs;
             BatchExec bx{c, rs, ex, setups[0].ndim, setups[0].R, gtab ? gtab : c->btab.dev.p, gtab == nullptr, {}};
             bx.run(acts, both);
