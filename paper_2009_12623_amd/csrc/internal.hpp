@@ -70,10 +70,11 @@ struct BatchEntry {
 // tile counts of e.p (3D uses e.p.rpl); returns the workgroups the shot
 // needs, receiver-sampling workgroups included
 int step_geometry(BatchEntry &e, int ndim, bool adjoint);
-// tab: device array of nshot entries with increasing `first`; total = the
-// last entry's first + its workgroups.  3D batches use 2 rows per lane.
-void launch_step_batch(const BatchEntry *tab, int nshot, int total, int ndim, int radius,
-                       bool adjoint, hipStream_t st);
+// tab: device array of nshot entries with increasing `first` (host_tab: the
+// same entries on the host); total = the last entry's first + its
+// workgroups.  3D batches use 2 rows per lane.
+void launch_step_batch(const BatchEntry *tab, const BatchEntry *host_tab, int nshot, int total, int ndim,
+                       int radius, bool adjoint, hipStream_t st);
 
 // unpadded computational grid <-> padded layout
 struct PadMap {

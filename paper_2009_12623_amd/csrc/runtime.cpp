@@ -978,7 +978,7 @@ struct BatchExec {
         }
         BatchEntry *d = (BatchEntry *)(dev_base + off);
         if (upload) HIPCHK(hipMemcpyAsync(d, h, (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice, st));
-        launch_step_batch(d, n, first, ndim, R, adj, st);
+        launch_step_batch(d, h, n, first, ndim, R, adj, st);
     }
 
     void advance(int a, int b)

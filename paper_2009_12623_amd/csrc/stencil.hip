@@ -337,11 +337,28 @@ void step2d_kernel(StepParams p, int ntz, int nwg)
 
 // ---------------------------------------------------------------- batched
 // One launch covers several shots: entry s owns workgroups
-// [first_s, first_{s+1}); a workgroup finds its entry by binary search and
-// runs the same body as the single-shot kernel on that entry's parameters.
-__device__ __forceinline__ int batch_entry(const BatchEntry *__restrict__ tab, int nshot, int wg)
+// [first_s, first_{s+1}); a workgroup finds its entry by binary search (over
+// the kernel-argument copy of `first` when the batch has at most
+// BATCH_INDEX shots, else over the table) and runs the same body as the
+// single-shot kernel on that entry's parameters.
+constexpr int BATCH_INDEX = 64;
+struct BatchIndex {
+    int n;                      // entries listed here (0: search the table)
+    int first[BATCH_INDEX];
+};
+
+__device__ __forceinline__ int batch_entry(const BatchEntry *__restrict__ tab, const BatchIndex &ix, int nshot,
+                                           int wg)
 {
     int lo = 0, hi = nshot - 1;
+    if (ix.n) {
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (ix.first[mid] <= wg) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    }
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (tab[mid].first <= wg) lo = mid;
@@ -352,18 +369,18 @@ __device__ __forceinline__ int batch_entry(const BatchEntry *__restrict__ tab, i
 
 template <int R, bool ADJ>
 __global__ __launch_bounds__(TILE_Z * 8)
-void step3d_batch_kernel(const BatchEntry *__restrict__ tab, int nshot)
+void step3d_batch_kernel(const BatchEntry *__restrict__ tab, BatchIndex ix, int nshot)
 {
-    const int s = batch_entry(tab, nshot, blockIdx.x);
+    const int s = batch_entry(tab, ix, nshot, blockIdx.x);
     const BatchEntry &e = tab[s];
     step3d_body<R, ADJ, 2>(e.p, blockIdx.x - e.first, e.ntz, e.nty, e.nwg, e.launched);
 }
 
 template <int R, bool ADJ>
 __global__ __launch_bounds__(TILE_Z2)
-void step2d_batch_kernel(const BatchEntry *__restrict__ tab, int nshot)
+void step2d_batch_kernel(const BatchEntry *__restrict__ tab, BatchIndex ix, int nshot)
 {
-    const int s = batch_entry(tab, nshot, blockIdx.x);
+    const int s = batch_entry(tab, ix, nshot, blockIdx.x);
     const BatchEntry &e = tab[s];
     step2d_body<R, ADJ>(e.p, blockIdx.x - e.first, e.ntz, e.nwg);
 }
@@ -387,12 +404,12 @@ void launch_r(const StepParams &p, int ndim, hipStream_t st)
 }
 
 template <int R, bool ADJ>
-void launch_batch_r(const BatchEntry *tab, int nshot, int total, int ndim, hipStream_t st)
+void launch_batch_r(const BatchEntry *tab, const BatchIndex &ix, int nshot, int total, int ndim, hipStream_t st)
 {
     if (ndim == 3)
-        hipLaunchKernelGGL((step3d_batch_kernel<R, ADJ>), dim3(total), dim3(TILE_Z, 8, 1), 0, st, tab, nshot);
+        hipLaunchKernelGGL((step3d_batch_kernel<R, ADJ>), dim3(total), dim3(TILE_Z, 8, 1), 0, st, tab, ix, nshot);
     else
-        hipLaunchKernelGGL((step2d_batch_kernel<R, ADJ>), dim3(total), dim3(TILE_Z2), 0, st, tab, nshot);
+        hipLaunchKernelGGL((step2d_batch_kernel<R, ADJ>), dim3(total), dim3(TILE_Z2), 0, st, tab, ix, nshot);
 }
 
 // ------------------------------------------------------------- small kernels
@@ -532,16 +549,21 @@ int step_geometry(BatchEntry &e, int ndim, bool adjoint)
     return e.nwg + ng;
 }
 
-void launch_step_batch(const BatchEntry *tab, int nshot, int total, int ndim, int radius, bool adjoint,
-                       hipStream_t st)
+void launch_step_batch(const BatchEntry *tab, const BatchEntry *host_tab, int nshot, int total, int ndim,
+                       int radius, bool adjoint, hipStream_t st)
 {
+    BatchIndex ix{};
+    if (nshot <= BATCH_INDEX) {
+        ix.n = nshot;
+        for (int i = 0; i < nshot; ++i) ix.first[i] = host_tab[i].first;
+    }
     switch (radius * 2 + (adjoint ? 1 : 0)) {
-    case 4: launch_batch_r<2, false>(tab, nshot, total, ndim, st); break;
-    case 5: launch_batch_r<2, true>(tab, nshot, total, ndim, st); break;
-    case 8: launch_batch_r<4, false>(tab, nshot, total, ndim, st); break;
-    case 9: launch_batch_r<4, true>(tab, nshot, total, ndim, st); break;
-    case 16: launch_batch_r<8, false>(tab, nshot, total, ndim, st); break;
-    case 17: launch_batch_r<8, true>(tab, nshot, total, ndim, st); break;
+    case 4: launch_batch_r<2, false>(tab, ix, nshot, total, ndim, st); break;
+    case 5: launch_batch_r<2, true>(tab, ix, nshot, total, ndim, st); break;
+    case 8: launch_batch_r<4, false>(tab, ix, nshot, total, ndim, st); break;
+    case 9: launch_batch_r<4, true>(tab, ix, nshot, total, ndim, st); break;
+    case 16: launch_batch_r<8, false>(tab, ix, nshot, total, ndim, st); break;
+    case 17: launch_batch_r<8, true>(tab, ix, nshot, total, ndim, st); break;
     default: break;
     }
 }
