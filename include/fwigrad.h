@@ -187,6 +187,20 @@ int fwi_forward_ckpt(fwi_ctx *ctx, const fwi_grid *g, const float *m,
 int fwi_backward(fwi_ctx *ctx, fwi_tape *tape, const float *dd, float *grad,
                  hipStream_t stream);
 int fwi_tape_free(fwi_tape *tape);
+/* Split form of fwi_gradient_batch (same shot rules): one tape for all
+ * shots, arrays of nshots entries [host] of device pointers.  cfg.pool_bytes
+ * (0 = the context's pool size) is the total the tape allocates, split in
+ * proportion to the shots' field sizes.  fwi_backward_batch writes
+ * grads[i] = J_i^T dd[i]; fwi_tape_free releases the tape.  A batched tape
+ * goes only to fwi_backward_batch and a single-shot tape only to
+ * fwi_backward (FWI_EINVAL otherwise). */
+int fwi_forward_ckpt_batch(fwi_ctx *ctx, int nshots, const fwi_grid *grids,
+                           const float *const *models, const fwi_shot *shots,
+                           const fwi_ckpt_cfg *cfg, float *const *d_sim,
+                           fwi_tape **tape, hipStream_t stream);
+int fwi_backward_batch(fwi_ctx *ctx, fwi_tape *tape, const float *const *dd,
+                       float *const *grads, hipStream_t stream);
+
 /* Pool bytes [host] that the checkpoints of cfg.nslots slots on grid g can
  * take: exact checkpoints need exactly this much; for compressed ones it is
  * the worst case (every stream at ckpt_bound), so callers usually size a

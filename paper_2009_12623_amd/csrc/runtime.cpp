@@ -246,6 +246,25 @@ struct fwi_tape {
     DevBuf<StreamSlot> slots;
     DevBuf<float> xcur, xprev;
     bool used = false;
+    // batched tapes: one entry per shot (the single-shot members above stay
+    // unused); the schedule position `next` and `acts` are shared
+    struct Shot {
+        fwi_grid grid{};
+        fwi_shot shot{};
+        std::vector<int32_t> rec;
+        const float *m = nullptr;
+        DevBuf<unsigned char> pool;
+        size_t cap = 0;
+        DevBuf<StreamSlot> slots;
+        DevBuf<float> xcur, xprev;
+        DevBuf<unsigned long long> misc;
+        std::vector<char> slot_both;
+        void release()
+        {
+            pool.release(); slots.release(); xcur.release(); xprev.release(); misc.release();
+        }
+    };
+    std::vector<std::unique_ptr<Shot>> shots;
 };
 
 namespace {
@@ -1045,9 +1064,12 @@ struct BatchExec {
         for (auto &e : ex) e.restore_commit(k, only_cur);
     }
 
-    void run(const std::vector<fwi_action> &acts, const std::vector<char> &both)
+    // run acts[from, end); stops before the first REVERSE if stop_at_reverse
+    size_t run(const std::vector<fwi_action> &acts, const std::vector<char> &both, size_t from = 0,
+               bool stop_at_reverse = false)
     {
-        for (size_t i = 0; i < acts.size(); ++i) {
+        size_t i = from;
+        for (; i < acts.size(); ++i) {
             const fwi_action &a = acts[i];
             switch (a.op) {
             case FWI_ADVANCE: advance(a.a, a.b); break;
@@ -1057,11 +1079,18 @@ struct BatchExec {
                 restore(a.a, a.b, only);
                 break;
             }
-            case FWI_REVERSE: reverse(a.a); break;
+            case FWI_REVERSE:
+                if (stop_at_reverse) {
+                    for (auto &e : ex) e.flush_record();
+                    return i;
+                }
+                reverse(a.a);
+                break;
             case FWI_FREE: break;
             default: throw Error{FWI_EINVAL, "internal: bad action"};
             }
         }
+        return i;
     }
 };
 
@@ -1471,6 +1500,179 @@ int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const floa
     });
 }
 
+// per-shot codec scratch regions of a batched call (offsets in words / entries)
+static void batch_codec_scratch(fwi_ctx *c, const std::vector<Setup> &setups, bool compress,
+                                std::vector<size_t> &scr_off, std::vector<size_t> &cb_off,
+                                std::vector<size_t> &co_off)
+{
+    const size_t n = setups.size();
+    scr_off.assign(n + 1, 0);
+    cb_off.assign(n + 1, 0);
+    co_off.assign(n + 1, 0);
+    for (size_t i = 0; i < n; ++i) {
+        const FieldView fv = padded_view(setups[i]);
+        const CodecGeom cg = codec_geom(fv.ndim, fv.n);
+        scr_off[i + 1] = scr_off[i] + (size_t)cg.nchunks * cg.max_chunk_words;
+        cb_off[i + 1] = cb_off[i] + (size_t)cg.nchunks;
+        co_off[i + 1] = co_off[i] + (size_t)((cg.nchunks + 1023) / 1024) + 2;
+    }
+    if (compress) {
+        c->scratch.ensure(scr_off[n]);
+        c->chunk_bits.ensure(cb_off[n]);
+        c->chunk_off.ensure(co_off[n]);
+    }
+    c->misc.ensure(4);
+    c->flags.ensure(1);
+}
+
+static void check_batch_shots(int nshots, const fwi_grid *grids)
+{
+    for (int i = 1; i < nshots; ++i) {
+        const fwi_grid &a = grids[0], &b = grids[i];
+        if (b.ndim != a.ndim || b.space_order != a.space_order || b.nt != a.nt || b.dt != a.dt)
+            throw Error{FWI_EINVAL, "batched shots must share ndim, space order, nt and dt"};
+    }
+}
+
+int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const float *const *models,
+                           const fwi_shot *shots, const fwi_ckpt_cfg *cfg, float *const *d_sim,
+                           fwi_tape **tape, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || nshots < 1 || !grids || !models || !shots || !d_sim || !tape)
+            throw Error{FWI_EINVAL, "null argument or nshots < 1"};
+        check_cfg(cfg);
+        for (int i = 0; i < nshots; ++i)
+            if (!models[i] || (!d_sim[i] && shots[i].nrec > 0))
+                throw Error{FWI_EINVAL, "null model or data of shot " + std::to_string(i)};
+        check_batch_shots(nshots, grids);
+        begin_call(c, st);
+        std::vector<Setup> setups;
+        for (int i = 0; i < nshots; ++i) setups.push_back(make_setup(&grids[i], &shots[i], true));
+        while ((int)c->batch.size() < nshots) c->batch.push_back(std::make_unique<ShotBufs>());
+        std::unique_ptr<fwi_tape> t(new fwi_tape());
+        try {
+            t->ctx = c;
+            t->cfg = *cfg;
+            t->acts = plan_for(c, setups[0].nt, cfg->nslots);
+            t->both = restart_flags(t->acts);
+            const int used = max_slot_used(t->acts);
+            // each shot's pool: the total split in proportion to field sizes
+            const size_t cap = cfg->pool_bytes ? cfg->pool_bytes : c->pool_default;
+            double wsum = 0;
+            for (auto &S : setups) wsum += (double)S.pad.elems();
+            for (int i = 0; i < nshots; ++i) {
+                auto sh = std::make_unique<fwi_tape::Shot>();
+                sh->grid = grids[i];
+                sh->shot = shots[i];
+                sh->rec.assign(shots[i].rec, shots[i].rec + (size_t)shots[i].nrec * grids[i].ndim);
+                sh->shot.rec = sh->rec.data();
+                sh->m = models[i];
+                sh->cap = ((size_t)((double)cap * ((double)setups[i].pad.elems() / wsum))) & ~(size_t)255;
+                sh->pool.ensure(sh->cap + 8);
+                sh->slots.ensure((size_t)std::max(2 * used, 1));
+                sh->misc.ensure(4);
+                t->shots.push_back(std::move(sh));
+            }
+            std::vector<size_t> so, cb, co;
+            batch_codec_scratch(c, setups, cfg->compress != 0, so, cb, co);
+            reset_status(c, st);
+            std::vector<Exec> ex;
+            ex.reserve(nshots);
+            for (int i = 0; i < nshots; ++i) {
+                fwi_tape::Shot &sh = *t->shots[i];
+                ShotBufs *b = c->batch[i].get();
+                ensure_fields(b, setups[i]);
+                HIPCHK(hipMemsetAsync(sh.misc.p, 0, 4 * sizeof(unsigned long long), st));
+                Exec e{c, setups[i], st, models[i], &sh.shot, b};
+                e.misc = sh.misc.p;
+                if (cfg->compress) {
+                    e.scr = c->scratch.p + so[i];
+                    e.cbits = c->chunk_bits.p + cb[i];
+                    e.coff = c->chunk_off.p + co[i];
+                }
+                setup_ckpt(e, cfg, sh.pool.p, sh.cap, sh.slots.p, used);
+                e.dsim = d_sim[i];
+                e.init_fields();
+                ex.push_back(std::move(e));
+            }
+            c->btab.ensure(table_bytes_of(t->acts, (size_t)nshots));
+            BatchExec bx{c, st, ex, setups[0].ndim, setups[0].R, c->btab.dev.p, true, {}};
+            t->next = bx.run(t->acts, t->both, 0, true);
+            for (int i = 0; i < nshots; ++i) {
+                fwi_tape::Shot &sh = *t->shots[i];
+                const size_t pe = c->batch[i]->padded_elems;
+                sh.slot_both = ex[i].slot_both;
+                sh.xcur.ensure(pe);
+                sh.xprev.ensure(pe);
+                launch_copy(sh.xcur.p, ex[i].cur, pe, st);
+                launch_copy(sh.xprev.p, ex[i].prev, pe, st);
+            }
+            HIPCHK(hipGetLastError());
+            finish_status(c, st);
+            end_call(c, st);
+        } catch (...) {
+            for (auto &sh : t->shots) sh->release();
+            throw;
+        }
+        *tape = t.release();
+    });
+}
+
+int fwi_backward_batch(fwi_ctx *c, fwi_tape *t, const float *const *dd, float *const *grads, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !t || !grads || !dd) throw Error{FWI_EINVAL, "null argument"};
+        if (t->shots.empty()) throw Error{FWI_EINVAL, "a single-shot tape needs fwi_backward"};
+        if (t->used) throw Error{FWI_EINVAL, "tape already back-propagated"};
+        const int nshots = (int)t->shots.size();
+        for (int i = 0; i < nshots; ++i)
+            if (!grads[i] || (!dd[i] && t->shots[i]->shot.nrec > 0))
+                throw Error{FWI_EINVAL, "null gradient or adjoint source of shot " + std::to_string(i)};
+        begin_call(c, st);
+        std::vector<Setup> setups;
+        for (auto &sh : t->shots) setups.push_back(make_setup(&sh->grid, &sh->shot, true));
+        while ((int)c->batch.size() < nshots) c->batch.push_back(std::make_unique<ShotBufs>());
+        const int used = max_slot_used(t->acts);
+        std::vector<size_t> so, cb, co;
+        batch_codec_scratch(c, setups, t->cfg.compress != 0, so, cb, co);
+        reset_status(c, st);
+        std::vector<Exec> ex;
+        ex.reserve(nshots);
+        for (int i = 0; i < nshots; ++i) {
+            fwi_tape::Shot &sh = *t->shots[i];
+            ShotBufs *b = c->batch[i].get();
+            ensure_fields(b, setups[i]);
+            Exec e{c, setups[i], st, sh.m, &sh.shot, b};
+            e.misc = sh.misc.p;
+            if (t->cfg.compress) {
+                e.scr = c->scratch.p + so[i];
+                e.cbits = c->chunk_bits.p + cb[i];
+                e.coff = c->chunk_off.p + co[i];
+            }
+            setup_ckpt(e, &t->cfg, sh.pool.p, sh.cap, sh.slots.p, used);
+            e.grad = grads[i];
+            e.adj_src = dd[i];
+            e.init_fields();
+            e.init_adjoint();
+            e.cur = sh.xcur.p;
+            e.prev = sh.xprev.p;
+            e.work = sh.grid.nt;
+            e.reached = sh.grid.nt;
+            e.slot_both = sh.slot_both;
+            ex.push_back(std::move(e));
+        }
+        c->btab.ensure(table_bytes_of(t->acts, (size_t)nshots));
+        BatchExec bx{c, st, ex, setups[0].ndim, setups[0].R, c->btab.dev.p, true, {}};
+        bx.run(t->acts, t->both, t->next, false);
+        for (int i = 0; i < nshots; ++i) launch_unpad(c->batch[i]->gacc.p, grads[i], ex[i].padmap(), st);
+        HIPCHK(hipGetLastError());
+        finish_status(c, st);
+        t->used = true;
+        end_call(c, st);
+    });
+}
+
 int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot,
                      const fwi_ckpt_cfg *cfg, float *d_sim, fwi_tape **tape, hipStream_t st)
 {
@@ -1526,6 +1728,7 @@ int fwi_backward(fwi_ctx *c, fwi_tape *t, const float *dd, float *grad, hipStrea
     return guarded([&] {
         if (!c || !t || !grad || (!dd && t->shot.nrec > 0)) throw Error{FWI_EINVAL, "null argument"};
         if (t->used) throw Error{FWI_EINVAL, "tape already back-propagated"};
+        if (!t->shots.empty()) throw Error{FWI_EINVAL, "a batched tape needs fwi_backward_batch"};
         begin_call(c, st);
         Exec ex{c, make_setup(&t->grid, &t->shot, true), st, t->m, &t->shot};
         ensure_fields(&c->sb, ex.S);
@@ -1558,6 +1761,7 @@ int fwi_tape_free(fwi_tape *t)
     return guarded([&] {
         if (!t) return;
         t->pool.release(); t->slots.release(); t->xcur.release(); t->xprev.release();
+        for (auto &sh : t->shots) sh->release();
         delete t;
     });
 }

@@ -71,7 +71,8 @@ EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_s
            "fwi_last_error", "fwi_forward", "fwi_gradient", "fwi_forward_ckpt",
            "fwi_backward", "fwi_tape_free", "ckpt_bound", "ckpt_compress",
            "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune", "fwi_ckpt_pool_bytes", "fwi_forward_state", "fwi_gradient_batch", "fwi_ctx_set_graphs",
-           "ckpt_compress_view", "ckpt_decompress_view"]
+           "ckpt_compress_view", "ckpt_decompress_view", "fwi_forward_ckpt_batch",
+           "fwi_backward_batch"]
 
 
 def lib():
@@ -116,6 +117,10 @@ def lib():
                                      ctypes.POINTER(fwi_shot), ctypes.POINTER(P),
                                      ctypes.POINTER(fwi_ckpt_cfg), ctypes.POINTER(P),
                                      ctypes.POINTER(ctypes.c_double), P]
+    L.fwi_forward_ckpt_batch.argtypes = [P, I, ctypes.POINTER(fwi_grid), ctypes.POINTER(P),
+                                         ctypes.POINTER(fwi_shot), ctypes.POINTER(fwi_ckpt_cfg),
+                                         ctypes.POINTER(P), ctypes.POINTER(P), P]
+    L.fwi_backward_batch.argtypes = [P, P, ctypes.POINTER(P), ctypes.POINTER(P), P]
     L.fwi_ckpt_pool_bytes.argtypes = [ctypes.POINTER(fwi_grid), ctypes.POINTER(fwi_ckpt_cfg),
                                       ctypes.POINTER(ctypes.c_size_t)]
     L.fwi_autotune.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), I,
@@ -316,6 +321,35 @@ class Context:
                                        _stream()))
         return list(phis), outs
 
+    def forward_ckpt_batch(self, shots, models, wavelets, nslots=10, compress=False, atol=1e-4,
+                           pool_bytes=0):
+        """fwi_forward_ckpt_batch: (list of d_sim, batched Tape)"""
+        n = len(shots)
+        if not isinstance(wavelets, (list, tuple)):
+            wavelets = [wavelets] * n
+        sas = [ShotArgs(s, w) for s, w in zip(shots, wavelets)]
+        grids = (fwi_grid * n)(*[grid_of(s) for s in shots])
+        cshots = (fwi_shot * n)(*[sa.c for sa in sas])
+        ms = (ctypes.c_void_p * n)(*[_ptr(m) for m in models])
+        ds = [torch.empty((s.nt, sa.nrec), dtype=torch.float32, device=models[0].device)
+              for s, sa in zip(shots, sas)]
+        dp = (ctypes.c_void_p * n)(*[_ptr(d) for d in ds])
+        cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), float(atol), int(pool_bytes))
+        t = ctypes.c_void_p()
+        check(lib().fwi_forward_ckpt_batch(self.h, n, grids, ms, cshots, ctypes.byref(cfg), dp,
+                                           ctypes.byref(t), _stream()))
+        return ds, Tape(self, t, sas, list(models))
+
+    def backward_batch(self, tape: Tape, dds, grads=None):
+        n = len(dds)
+        ms = tape.m if isinstance(tape.m, list) else [tape.m] * n
+        outs = [torch.empty_like(m) for m in ms] if grads is None else grads
+        dd = [d.contiguous() for d in dds]
+        dp = (ctypes.c_void_p * n)(*[_ptr(d) for d in dd])
+        gp = (ctypes.c_void_p * n)(*[_ptr(g) for g in outs])
+        check(lib().fwi_backward_batch(self.h, tape.handle, dp, gp, _stream()))
+        return outs
+
     def forward_ckpt(self, shot, m, wavelet, nslots=10, compress=False, atol=1e-4, pool_bytes=0):
         sa = ShotArgs(shot, wavelet)
         g = grid_of(shot)
@@ -327,7 +361,8 @@ class Context:
         return d, Tape(self, t, sa, m)
 
     def backward(self, tape: Tape, dd: torch.Tensor, grad=None) -> torch.Tensor:
-        out = torch.empty_like(tape.m) if grad is None else grad
+        m = tape.m[0] if isinstance(tape.m, list) else tape.m
+        out = torch.empty_like(m) if grad is None else grad
         check(lib().fwi_backward(self.h, tape.handle, _ptr(dd.contiguous()), _ptr(out), _stream()))
         return out
 
@@ -436,3 +471,54 @@ class FwiOperator:
         grown = int(1.25 * used) + (1 << 20) if used else pool
         self._pool[key] = min(worst, max(self._pool.get(key, 0), grown))
         return d
+
+
+class FwiBatchFunction(torch.autograd.Function):
+    """d_sim of several shots of one model m (Eq. 2) as one differentiable
+    op: forward runs fwi_forward_ckpt_batch (one stencil launch per time step
+    for all shots), backward runs fwi_backward_batch and returns the sum over
+    shots of J_i^T dd_i.  Returns one trace tensor per shot."""
+
+    @staticmethod
+    def forward(fctx, m, wavelet, context, shots, nslots, compress, atol, pool_bytes):
+        if fctx.needs_input_grad[1]:
+            raise NotImplementedError("FwiBatchFunction differentiates with respect to m only")
+        md = m.detach().contiguous()
+        ds, tape = context.forward_ckpt_batch(shots, [md] * len(shots), wavelet.detach().contiguous(),
+                                              nslots=nslots, compress=compress, atol=atol,
+                                              pool_bytes=pool_bytes)
+        fctx.context, fctx.tape = context, tape
+        fctx.save_for_backward(m, wavelet)
+        return tuple(ds)
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(fctx, *dds):
+        m, _ = fctx.saved_tensors
+        dds = [torch.zeros_like(d) if d is None else d for d in dds]
+        gs = fctx.context.backward_batch(fctx.tape, dds)
+        fctx.tape.free()
+        fctx.tape = None
+        g = gs[0]
+        for x in gs[1:]:
+            g = g + x
+        return g, None, None, None, None, None, None, None
+
+
+def forward_modelling_batch(context, m, shots, wavelet, nslots=40, compress=True, atol=1e-4,
+                            pool_bytes=0):
+    """Differentiable traces of all shots of model m in one batched sweep."""
+    exact = sum(ckpt_pool_bytes(s, nslots, False) for s in shots)
+    if not compress:
+        return FwiBatchFunction.apply(m, wavelet, context, list(shots), int(nslots), False,
+                                      float(atol), int(pool_bytes or exact))
+    worst = sum(ckpt_pool_bytes(s, nslots, True) for s in shots)
+    pool = int(pool_bytes or min(worst, max(exact // 4, 1 << 24)))
+    while True:
+        try:
+            return FwiBatchFunction.apply(m, wavelet, context, list(shots), int(nslots), True,
+                                          float(atol), pool)
+        except FwiError as e:
+            if e.code != FWI_ECAPACITY or pool >= worst:
+                raise
+            pool = min(worst, 2 * pool)

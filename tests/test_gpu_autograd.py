@@ -173,3 +173,46 @@ def test_wavelet_gradient_not_supported(ctx):
     q = dev(q32).requires_grad_(True)
     with pytest.raises(NotImplementedError):
         F.FwiOperator(ctx, nslots=3, compress=False)(dev(m0).requires_grad_(True), shot, q)
+
+
+@pytest.mark.parametrize("compress", [False, True])
+def test_batched_autograd_equals_batched_gradient(ctx, compress):
+    """forward_modelling_batch (one tape, one launch per step for all shots):
+    the summed gradient equals the sum of fwi_gradient_batch's per-shot
+    gradients bit for bit, and the per-shot autograd path's sum"""
+    base, m0, mt, q32 = problem(2, 60, 16, nt=70)
+    shots = shots_along_x(base, 4)
+    q = dev(q32)
+    dobs = [ctx.forward(s, dev(mt), q) for s in shots]
+    m = dev(m0).requires_grad_(True)
+    ds = F.forward_modelling_batch(ctx, m, shots, q, nslots=5, compress=compress, atol=1e-4)
+    loss = 0.0
+    for d, o in zip(ds, dobs):
+        r = d - o
+        loss = loss + 0.5 * (r * r).sum()
+    loss.backward()
+    phis, gs = ctx.gradient_batch(shots, [dev(m0)] * len(shots), q, dobs, nslots=5,
+                                  compress=compress, atol=1e-4)
+    ref = gs[0]
+    for g in gs[1:]:
+        ref = ref + g
+    assert torch.equal(m.grad, ref)
+    assert abs(float(loss) - sum(phis)) <= 1e-5 * sum(phis)
+    # the per-shot path sums the same shot gradients in autograd's order
+    _, g1 = autograd_gradient(F.FwiOperator(ctx, nslots=5, compress=compress, atol=1e-4),
+                              shots, m0, q, dobs)
+    assert metrics.rel_l2(m.grad.cpu().numpy(), g1.cpu().numpy()) <= 1e-6
+
+
+def test_tape_kinds_are_not_mixed(ctx):
+    base, m0, mt, q32 = problem(2, 40, 8, nt=30)
+    shots = shots_along_x(base, 2)
+    q = dev(q32)
+    ds, tb = ctx.forward_ckpt_batch(shots, [dev(m0)] * 2, q, nslots=3)
+    with pytest.raises(F.FwiError):
+        ctx.backward(tb, ds[0])
+    d1, t1 = ctx.forward_ckpt(shots[0], dev(m0), q, nslots=3, pool_bytes=1 << 26)
+    with pytest.raises(F.FwiError):
+        ctx.backward_batch(t1, [d1, d1])
+    tb.free()
+    t1.free()
