@@ -644,7 +644,8 @@ def main():
     shape = None
     if tune is not None and dom in ("forward_step", "adjoint_imaging_step"):
         pre = "fwd" if dom == "forward_step" else "adj"
-        shape = (tune[pre + "_xchunk"], tune[pre + "_rows_per_lane"], tune[pre + "_xcd_order"])
+        shape = (tune[pre + "_xchunk"], tune[pre + "_rows_per_lane"], tune[pre + "_xcd_order"],
+                 tune[pre + "_deep"])
     traffic = counted_traffic(dom, shape) if args.workload == "c3" else None
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -675,9 +676,9 @@ def main():
             "nslots_uncompressed": s_unc,
             "hbm_budget_gb": round(budget / 1e9, 2),
             "stencil_shape": None if tune is None else {
-                "forward": [tune["fwd_xchunk"], tune["fwd_rows_per_lane"], tune["fwd_xcd_order"]],
-                "adjoint": [tune["adj_xchunk"], tune["adj_rows_per_lane"], tune["adj_xcd_order"]],
-                "fields": ["x_planes_per_workgroup", "rows_per_lane", "xcd_contiguous"]},
+                "forward": [tune["fwd_xchunk"], tune["fwd_rows_per_lane"], tune["fwd_xcd_order"], tune["fwd_deep"]],
+                "adjoint": [tune["adj_xchunk"], tune["adj_rows_per_lane"], tune["adj_xcd_order"], tune["adj_deep"]],
+                "fields": ["x_planes_per_workgroup", "rows_per_lane", "xcd_contiguous", "planes_in_flight_2"]},
         },
         "roofline": roof,
         "stencil_gpts": {"forward": round(npts / (fwd_avg * 1e-3) / 1e9, 2),

@@ -247,9 +247,9 @@ int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
                      int *nactions, long long *nforward);
 
 /* Autotuner: times every candidate launch shape of the stencil kernels on
- * this grid (3D: x planes per workgroup in {8,16,32,64} x rows per lane in
- * {2,4} x tile order round-robin / XCD-contiguous; 2D: x planes in
- * {4..64}), `steps` forward and `steps` adjoint launches each on the model
+ * this grid (3D: x planes per workgroup in {8,16,32,64} x tile order
+ * round-robin / XCD-contiguous x {2 rows per lane, 4 rows per lane, 2 rows
+ * per lane with two planes of loads in flight}; 2D: x planes in {4..64}), `steps` forward and `steps` adjoint launches each on the model
  * m [device], with the buffer roles alternating as in a sweep, and keeps
  * the fastest forward and adjoint shapes for later calls on a grid of the
  * same dims and order.  Results [host].  Synchronises the stream; the context's
@@ -259,6 +259,7 @@ typedef struct {
     int fwd_xchunk, fwd_rows_per_lane, fwd_xcd_order;
     int adj_xchunk, adj_rows_per_lane, adj_xcd_order;
     double fwd_ms, adj_ms;
+    int fwd_deep, adj_deep;       /* two planes of loads in flight */
 } fwi_tune_result;
 int fwi_autotune(fwi_ctx *ctx, const fwi_grid *g, const float *m,
                  const fwi_shot *shot, int steps, fwi_tune_result *out,

@@ -52,6 +52,7 @@ struct StepParams {
     int xchunk;             // x planes per workgroup
     int rpl;                // 3D: rows per lane (tile height 8 rpl), 2 or 4
     int remap;              // 3D: XCD-contiguous tile order
+    int deep;               // 3D: two planes of loads in flight (2 rows per lane)
     // forward only: sample u1 at the receivers into grow (nullptr: skip)
     const int *rec_off;     // padded offsets from the allocation base
     int nrec;

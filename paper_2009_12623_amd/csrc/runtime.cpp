@@ -206,8 +206,9 @@ struct fwi_ctx {
     int xchunk3 = 0;           // 3D x planes per workgroup (0: default)
     int rpl3 = 2;              // 3D rows per lane
     int remap3 = 0;            // 3D XCD-contiguous tile order
+    int deep3 = 0;             // 3D two planes of loads in flight
     struct Shape {
-        int xchunk, rpl, remap;
+        int xchunk, rpl, remap, deep;
     };
     std::map<std::vector<int>, std::pair<Shape, Shape>> tuned;   // grid key -> (forward, adjoint)
     fwi_stats stats{};
@@ -596,6 +597,7 @@ struct Exec {
         p.xchunk = sh.xchunk;
         p.rpl = sh.rpl;
         p.remap = sh.remap;
+        p.deep = sh.deep;
     }
 
     StepParams params() const
@@ -615,6 +617,7 @@ struct Exec {
         p.src = -1;
         p.rpl = c->rpl3;
         p.remap = c->remap3;
+        p.deep = c->deep3;
         // short x chunks: many workgroups in flight; the 2R halo planes
         // re-read per chunk come from L2
         p.xchunk = c->xchunk3 > 0 ? c->xchunk3 : 16;
@@ -1136,7 +1139,7 @@ void key_shot(KeyBuilder &k, fwi_ctx *c, const fwi_grid *g, const fwi_shot *sh, 
     k.bytes(sh->rec, sizeof(int32_t) * (size_t)sh->nrec * (size_t)g->ndim);
     auto it = c->tuned.find({S.ndim, S.pad.nx, S.pad.ny, S.pad.nz, S.R});
     if (it != c->tuned.end()) k.add(it->second.first).add(it->second.second);
-    k.add(c->xchunk3).add(c->rpl3).add(c->remap3);
+    k.add(c->xchunk3).add(c->rpl3).add(c->remap3).add(c->deep3);
 }
 
 // Enqueue a schedule: directly, or (graphs on) by replaying the graph
@@ -1241,6 +1244,7 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         if (const char *e = std::getenv("FWI_XCHUNK")) c->xchunk3 = std::atoi(e);
         if (const char *e = std::getenv("FWI_RPL")) c->rpl3 = std::atoi(e) == 4 ? 4 : 2;
         if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::atoi(e) != 0;
+        if (const char *e = std::getenv("FWI_DEEP")) c->deep3 = std::atoi(e) != 0;
         *ctx = c;
     });
 }
@@ -1971,10 +1975,13 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         const int xcs2[] = {4, 8, 16, 32, 64};
         if (ex.S.ndim == 3) {
             for (int xc : xcs3)
-                for (int rpl : {2, 4})
-                    for (int remap : {0, 1}) cands.push_back({xc, rpl, remap});
+                for (int remap : {0, 1}) {
+                    cands.push_back({xc, 2, remap, 0});
+                    cands.push_back({xc, 4, remap, 0});
+                    cands.push_back({xc, 2, remap, 1});
+                }
         } else {
-            for (int xc : xcs2) cands.push_back({xc, 2, 0});
+            for (int xc : xcs2) cands.push_back({xc, 2, 0, 0});
         }
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
@@ -1985,6 +1992,7 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
             p.xchunk = sh.xchunk;
             p.rpl = sh.rpl;
             p.remap = sh.remap;
+            p.deep = sh.deep;
             auto one = [&](int i) {
                 float *a = (i & 1) ? c->sb.fb.p : c->sb.fa.p, *b = (i & 1) ? c->sb.fa.p : c->sb.fb.p;
                 if (adj) {
@@ -2023,6 +2031,8 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         out->ncand = (int)cands.size();
         out->fwd_xchunk = sf.xchunk; out->fwd_rows_per_lane = sf.rpl; out->fwd_xcd_order = sf.remap;
         out->adj_xchunk = sa.xchunk; out->adj_rows_per_lane = sa.rpl; out->adj_xcd_order = sa.remap;
+        out->fwd_deep = sf.deep;
+        out->adj_deep = sa.deep;
         out->fwd_ms = bf;
         out->adj_ms = ba;
         HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, arena_bytes, st));

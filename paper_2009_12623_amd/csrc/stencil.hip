@@ -248,11 +248,179 @@ __device__ __forceinline__ void step3d_body(const StepParams &p, int hw, int ntz
     }
 }
 
+// Same step with the loads of plane x+2 issued while plane x is computed
+// (two planes in flight per workgroup instead of one).
+template <int R, bool ADJ, int RPL>
+__device__ __forceinline__ void step3d_body_deep(const StepParams &p, int hw, int ntz, int nty, int nwg,
+                                            int launched)
+{
+    constexpr int ROWS = 8 * RPL;
+    __shared__ float tile[2][ROWS + 2 * R][TILE_Z + 2 * R];
+    if (hw >= launched) {                          // receiver sampling blocks
+        gather_block(p, hw - launched);
+        return;
+    }
+    int tzi, tyi, txi;
+    bool valid;
+    tile_coords(hw, nwg, ntz, nty, p.remap != 0, tzi, tyi, txi, valid);
+    if (!valid) return;                            // whole workgroup, before any barrier
+
+    const int tz = threadIdx.x;
+    const int ty = threadIdx.y;
+    const int z0 = tzi * TILE_Z;
+    const int y0 = tyi * ROWS;
+    const int z = z0 + tz;
+    const int xb = txi * p.xchunk;
+    const int xe = min(xb + p.xchunk, p.nx);
+    const bool zin = z < p.nz;
+    // byte strides and offsets (unsigned arithmetic; every result is in range)
+    const unsigned bsx = 4u * (unsigned)p.psx, bsy = 4u * (unsigned)p.psy;
+    const unsigned org = 4u * (unsigned)p.origin;
+    const unsigned srcb = p.src >= 0 ? org + 4u * (unsigned)p.src : 0xFFFFFFFFu;
+    const float *__restrict__ u1 = p.u1;
+    const float *__restrict__ u2 = p.u2;
+    const float *__restrict__ bq = p.b;
+    const bool hy = ty < R;
+    const unsigned hy_top = org + (unsigned)(y0 - R + ty) * bsy + 4u * z;
+    const unsigned hy_bot = org + (unsigned)(y0 + ROWS + ty) * bsy + 4u * z;
+    const bool hzl = tz < R, hzr = tz >= TILE_Z - R;
+    const bool hz = hzl || hzr;
+    const unsigned hz_off = 4u * (unsigned)(hzl ? (z0 - R + tz) : (z + R));
+    const int hcol = hzl ? tz : tz + 2 * R;
+    const unsigned col0 = org + (unsigned)(y0 + ty) * bsy + 4u * z;   // row j at + 8 j bsy
+    const unsigned hz0 = org + (unsigned)(y0 + ty) * bsy + hz_off;
+    const unsigned rstep = 8u * bsy;
+    const int dz = layer_depth(z, p.nz, p.nbl);
+    bool act[RPL];
+    int dyz[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+        const int y = y0 + ty + 8 * j;
+        act[j] = zin && y < p.ny;
+        const int dy = layer_depth(y, p.ny, p.nbl);
+        dyz[j] = dy * dy + dz * dz;
+    }
+
+    float q[RPL][2 * R + 1];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+#pragma unroll
+        for (int i = 0; i <= 2 * R; ++i) q[j][i] = ld(u1, col0 + j * rstep + (unsigned)(xb - R + i) * bsx);
+    {
+        const unsigned pl = (unsigned)xb * bsx;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) tile[0][ty + 8 * j + R][tz + R] = q[j][R];
+        if (hy) {
+            tile[0][ty][tz + R] = ld(u1, pl + hy_top);
+            tile[0][ty + ROWS + R][tz + R] = ld(u1, pl + hy_bot);
+        }
+        if (hz) {
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) tile[0][ty + 8 * j + R][hcol] = ld(u1, pl + hz0 + j * rstep);
+        }
+    }
+    unsigned pa = col0 + (unsigned)xb * bsx;            // row j at + j rstep
+    float u2v[RPL], bv[RPL], ukv[RPL], gv[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+        const unsigned o = pa + j * rstep;
+        u2v[j] = act[j] ? ldnt(u2, o) : 0.f;
+        bv[j] = act[j] ? ldnt(bq, o) : 0.f;
+        ukv[j] = (ADJ && act[j]) ? ldnt(p.uk, o) : 0.f;
+        gv[j] = (ADJ && act[j]) ? ldnt(p.g, o) : 0.f;
+    }
+    // loads of one future plane: queue value (R planes further), halo ring, u2, b (u^k, g)
+    struct Ld {
+        float q[RPL], hz[RPL], u2[RPL], b[RPL], uk[RPL], g[RPL];
+        float ht, hb;
+    };
+    auto issue = [&](Ld &L, int xp) {
+        const unsigned pl = (unsigned)xp * bsx;
+        L.ht = L.hb = 0.f;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) L.q[j] = L.hz[j] = L.u2[j] = L.b[j] = L.uk[j] = L.g[j] = 0.f;
+        if (hy) {
+            L.ht = ld(u1, pl + hy_top);
+            L.hb = ld(u1, pl + hy_bot);
+        }
+        if (hz) {
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) L.hz[j] = ld(u1, pl + hz0 + j * rstep);
+        }
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) L.q[j] = ld(u1, col0 + j * rstep + pl + (unsigned)R * bsx);
+        const unsigned na0 = col0 + pl;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            const unsigned na = na0 + j * rstep;
+            if (act[j]) {
+                L.u2[j] = ldnt(u2, na);
+                L.b[j] = ldnt(bq, na);
+                if (ADJ) { L.uk[j] = ldnt(p.uk, na); L.g[j] = ldnt(p.g, na); }
+            }
+        }
+    };
+    Ld A, B;
+    if (xb + 1 < xe) issue(A, xb + 1);
+    __syncthreads();
+
+    for (int x = xb; x < xe; ++x) {
+        const int cur = (x - xb) & 1;
+        if (x + 2 < xe) issue(B, x + 2);
+        // ---- plane x
+        const int dx = layer_depth(x, p.nx, p.nbl);
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            if (!act[j]) continue;
+            const int r = ty + 8 * j + R;
+            const float c = q[j][R];
+            float lap = 3.0f * p.w[0] * c;
+#pragma unroll
+            for (int k = 1; k <= R; ++k)
+                lap += p.w[k] * ((q[j][R - k] + q[j][R + k]) +
+                                 (tile[cur][r - k][tz + R] + tile[cur][r + k][tz + R]) +
+                                 (tile[cur][r][tz + R - k] + tile[cur][r][tz + R + k]));
+            const unsigned o = pa + j * rstep;
+            const float ov = update<ADJ>(p, dx * dx + dyz[j], o == srcb, c, lap, u2v[j], bv[j]);
+            st(p.out, o, ov);
+            if (ADJ) st(p.g, o, gv[j] - ukv[j] * (ov - 2.0f * c + u2v[j]) * p.inv_dt2);
+        }
+        if (x + 1 >= xe) break;
+        // ---- advance the queues and stage plane x+1 (loads issued one plane ago)
+        const int nb = cur ^ 1;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i) q[j][i] = q[j][i + 1];
+            q[j][2 * R] = A.q[j];
+            tile[nb][ty + 8 * j + R][tz + R] = q[j][R];
+            if (hz) tile[nb][ty + 8 * j + R][hcol] = A.hz[j];
+            u2v[j] = A.u2[j];
+            bv[j] = A.b[j];
+            if (ADJ) { ukv[j] = A.uk[j]; gv[j] = A.g[j]; }
+        }
+        if (hy) {
+            tile[nb][ty][tz + R] = A.ht;
+            tile[nb][ty + ROWS + R][tz + R] = A.hb;
+        }
+        A = B;
+        pa += bsx;
+        __syncthreads();
+    }
+}
+
 template <int R, bool ADJ, int RPL>
 __global__ __launch_bounds__(TILE_Z * 8)
 void step3d_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
 {
     step3d_body<R, ADJ, RPL>(p, blockIdx.x, ntz, nty, nwg, launched);
+}
+
+template <int R, bool ADJ>
+__global__ __launch_bounds__(TILE_Z * 8)
+void step3d_deep_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
+{
+    step3d_body_deep<R, ADJ, 2>(p, blockIdx.x, ntz, nty, nwg, launched);
 }
 
 // ------------------------------------------------------------------- 2D
@@ -392,7 +560,10 @@ void launch_r(const StepParams &p, int ndim, hipStream_t st)
     e.p = p;
     const int total = step_geometry(e, ndim, ADJ);
     if (ndim == 3) {
-        if (p.rpl == 4)
+        if (p.deep)
+            hipLaunchKernelGGL((step3d_deep_kernel<R, ADJ>), dim3(total), dim3(TILE_Z, 8, 1), 0, st,
+                               p, e.ntz, e.nty, e.nwg, e.launched);
+        else if (p.rpl == 4)
             hipLaunchKernelGGL((step3d_kernel<R, ADJ, 4>), dim3(total), dim3(TILE_Z, 8, 1), 0, st,
                                p, e.ntz, e.nty, e.nwg, e.launched);
         else

@@ -58,7 +58,7 @@ class fwi_tune_result(ctypes.Structure):
                 ("fwd_rows_per_lane", ctypes.c_int), ("fwd_xcd_order", ctypes.c_int),
                 ("adj_xchunk", ctypes.c_int), ("adj_rows_per_lane", ctypes.c_int),
                 ("adj_xcd_order", ctypes.c_int), ("fwd_ms", ctypes.c_double),
-                ("adj_ms", ctypes.c_double)]
+                ("adj_ms", ctypes.c_double), ("fwd_deep", ctypes.c_int), ("adj_deep", ctypes.c_int)]
 
 
 class fwi_action(ctypes.Structure):

@@ -94,13 +94,17 @@ def test_forward_state_matches_oracle(ctx, ndim, n, so):
     assert metrics.rel_l2(u0.cpu().numpy(), states[shot.nt - 1]) <= 1e-4
 
 
-@pytest.mark.parametrize("xchunk,rpl,remap", [(3, 2, 0), (7, 4, 1), (64, 2, 1), (16, 4, 0)])
+@pytest.mark.parametrize("xchunk,rpl,remap,deep", [(3, 2, 0, 0), (7, 4, 1, 0), (64, 2, 1, 0), (16, 4, 0, 0),
+                                                   (3, 2, 0, 1), (16, 2, 1, 1), (64, 2, 0, 1), (1, 2, 0, 1),
+                                                   (2, 2, 0, 1)])
 @pytest.mark.parametrize("so", [4, 8, 16])
-def test_3d_stencil_launch_shapes_match_oracle(xchunk, rpl, remap, so, monkeypatch):
-    """every launch shape (x planes per workgroup, rows per lane, tile order)"""
+def test_3d_stencil_launch_shapes_match_oracle(xchunk, rpl, remap, deep, so, monkeypatch):
+    """every launch shape (x planes per workgroup, rows per lane, tile order,
+    loads of one or two planes in flight)"""
     monkeypatch.setenv("FWI_XCHUNK", str(xchunk))
     monkeypatch.setenv("FWI_RPL", str(rpl))
     monkeypatch.setenv("FWI_REMAP", str(remap))
+    monkeypatch.setenv("FWI_DEEP", str(deep))
     c = F.Context(0, pool_bytes=1 << 28)
     shot = synth.tiny_shot(3, n=23, so=so, nbl=5, nt=35)
     m0, mt, q = inputs(shot)
@@ -127,7 +131,7 @@ def test_autotuned_shapes_keep_the_gradient(ndim, n, so):
     _, g_def = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=4)
     r = c.autotune(shot, dev(m0), dev(q), steps=2)
     print("autotune", ndim, r)
-    assert r["ncand"] == (16 if ndim == 3 else 5)
+    assert r["ncand"] == (24 if ndim == 3 else 5)
     assert r["fwd_xchunk"] in (4, 8, 16, 32, 64) and r["adj_xchunk"] in (4, 8, 16, 32, 64)
     assert r["fwd_rows_per_lane"] in (2, 4) and r["fwd_ms"] > 0 and r["adj_ms"] > 0
     _, g = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=4)
