@@ -72,30 +72,46 @@ def workload_c1(torch, dev, nt):
 
 
 # ------------------------------------------------------------ cost model
-def schedule_counts(F, nt, s):
+def schedule_counts(F, nt, s, peak=False):
     """forward steps, fields encoded, restores decoding u^k only, restores
     decoding both levels (a checkpoint keeps u^{k-1} only when the schedule
-    restarts from it)."""
+    restarts from it); with peak, also the largest number of fields stored
+    at once."""
     acts, nf = F.fwi_revolve_plan(nt, s)
-    nenc = rr = ra = 0
-    open_ = {}
+    # which takeshots keep both levels: those later restored and advanced from
+    both = {}
+    taken = {}
     for i, a in enumerate(acts):
         if a[0] == "takeshot":
-            open_[a[1]] = False
+            taken[a[1]] = i
+            both[i] = False
+        elif a[0] == "restore" and a[1] >= 0 and i + 1 < len(acts) and acts[i + 1][0] == "advance":
+            both[taken[a[1]]] = True
+    nenc = rr = ra = 0
+    live = {}
+    fields = high = 0
+    for i, a in enumerate(acts):
+        if a[0] == "takeshot":
+            lv = 2 if both[i] else 1
+            live[a[1]] = lv
+            fields += lv
+            high = max(high, fields)
+            nenc += lv
         elif a[0] == "restore" and a[1] >= 0:
             if i + 1 < len(acts) and acts[i + 1][0] == "reverse":
                 rr += 1
             else:
                 ra += 1
-                open_[a[1]] = True
         elif a[0] == "free":
-            nenc += 2 if open_.pop(a[1]) else 1
-    return nf, nenc, rr, ra
+            fields -= live.pop(a[1])
+    return (nf, nenc, rr, ra, high) if peak else (nf, nenc, rr, ra)
 
 
 def choose_slots(F, nt, st, budget, margin=1.3):
     """Least predicted time over slot counts whose compressed checkpoints fit
-    the budget.  Costs per unit from the pilot run's HIP-event timings."""
+    the budget (the schedule's peak number of stored fields x the pilot's
+    mean field bytes x margin).  Costs per unit from the pilot run's
+    HIP-event timings."""
     tf = st["ms_forward"] / max(st["n_forward"], 1)
     ta = st["ms_adjoint"] / max(st["n_adjoint"], 1)
     te = st["ms_encode"] / max(st["n_encode"], 1)
@@ -106,9 +122,11 @@ def choose_slots(F, nt, st, budget, margin=1.3):
                     1000, 1280, 1600, 2000, 2500, 3000, nt})
     table = []
     for s in cands:
-        if s > nt or 2 * s * per_field * margin > budget:
+        if s > nt:
             continue
-        nf, nenc, rr, ra = schedule_counts(F, nt, s)
+        nf, nenc, rr, ra, high = schedule_counts(F, nt, s, peak=True)
+        if high * per_field * margin > budget:
+            continue
         t = nf * tf + nt * ta + nenc * te + (rr + 2 * ra) * td
         table.append((s, round(t / 1e3, 3)))
         if best is None or t < best[1]:
