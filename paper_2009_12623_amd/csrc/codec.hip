@@ -691,13 +691,16 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
     for (int j = 0; j < kblk; ++j) {
         const long b = chunk_block(c, j, kblk, nblocks);
         if (b < 0) break;
-        float vals[SZ];
+        // integer coefficients of the block (all zero for a skipped block);
+        // the float values are formed as they are stored
+        int ci[SZ];
+        int emax = 0;
         if (br.pos >= pbits) { atomicOr(flags, 4u); return; }
         if (!br.get(1)) {
 #pragma unroll
-            for (int li = 0; li < SZ; ++li) vals[li] = 0.0f;
+            for (int li = 0; li < SZ; ++li) ci[li] = 0;
         } else {
-            const int emax = (int)br.get(8) - 127;
+            emax = (int)br.get(8) - 127;
             const int zs = (int)br.get(3);
             const int S = GC::TP - zs;
             int P = minexp - emax + QB - GC::G;
@@ -728,25 +731,24 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
             if (bad || br.pos > pbits) { atomicOr(flags, 4u); return; }
             transpose32(lo);
             if (D == 3) transpose32(hi);
-            int ci[SZ];
 #pragma unroll
             for (int s2 = 0; s2 < SZ; ++s2) {
                 const uint32_t u = s2 < 32 ? lo[s2] : hi[s2 & 31];
                 ci[seq.perm[s2]] = (int)((u ^ 0xAAAAAAAAu) - 0xAAAAAAAAu);
             }
             block_inv<D>(ci);
-#pragma unroll
-            for (int li = 0; li < SZ; ++li) {
-                const int iv = ci[li];
-                float fv = (float)iv;
-                uint32_t bits = __float_as_uint(fv);
-                const int E = (int)((bits >> 23) & 0xFFu) + emax - QB;
-                if (iv == 0 || E <= 0) bits = 0u;
-                else if (E >= 255) bits = (bits & 0x80000000u) | 0x7F7FFFFFu;
-                else bits = (bits & ~(0xFFu << 23)) | ((uint32_t)E << 23);
-                vals[li] = __uint_as_float(bits);
-            }
         }
+        // int32 -> float32 (round to nearest even), scaled by 2^(emax - Q)
+        // through the exponent field; below 2^-126 -> +0, overflow saturates
+        auto val = [&](int li) {
+            const int iv = ci[li];
+            uint32_t bits = __float_as_uint((float)iv);
+            const int E = (int)((bits >> 23) & 0xFFu) + emax - QB;
+            if (iv == 0 || E <= 0) bits = 0u;
+            else if (E >= 255) bits = (bits & 0x80000000u) | 0x7F7FFFFFu;
+            else bits = (bits & ~(0xFFu << 23)) | ((uint32_t)E << 23);
+            return __uint_as_float(bits);
+        };
         long bx, by, bz;
         block_coords(b, nb, bx, by, bz);
         if (vec == 2) {
@@ -760,8 +762,8 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
                 const long x = 4 * bx + ix, y = 4 * by + iy;
                 const bool row = x < f.n[0] && y < f.n[1];
                 *(float4 *)(dst + x * f.sx + y * f.sy + 4 * bz) =
-                    make_float4(row ? vals[4 * r] : 0.0f, row && zl >= 1 ? vals[4 * r + 1] : 0.0f,
-                                row && zl >= 2 ? vals[4 * r + 2] : 0.0f, row && zl >= 3 ? vals[4 * r + 3] : 0.0f);
+                    make_float4(row ? val(4 * r) : 0.0f, row && zl >= 1 ? val(4 * r + 1) : 0.0f,
+                                row && zl >= 2 ? val(4 * r + 2) : 0.0f, row && zl >= 3 ? val(4 * r + 3) : 0.0f);
             }
         } else if (vec && 4 * bx + 3 < f.n[0] && (D == 2 || 4 * by + 3 < f.n[1]) && 4 * bz + 3 < f.n[2]) {
             // whole block inside: one 16-byte store per (x, y) row
@@ -770,7 +772,7 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
                 const int ix = D == 3 ? (r >> 2) : r;
                 const int iy = D == 3 ? (r & 3) : 0;
                 *(float4 *)(dst + (4 * bx + ix) * f.sx + (4 * by + iy) * f.sy + 4 * bz) =
-                    make_float4(vals[4 * r], vals[4 * r + 1], vals[4 * r + 2], vals[4 * r + 3]);
+                    make_float4(val(4 * r), val(4 * r + 1), val(4 * r + 2), val(4 * r + 3));
             }
         } else {
 #pragma unroll
@@ -779,7 +781,7 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
                 const int iy = D == 3 ? ((li >> 2) & 3) : 0;
                 const int iz = li & 3;
                 const long x = 4 * bx + ix, y = 4 * by + iy, z = 4 * bz + iz;
-                if (x < f.n[0] && y < f.n[1] && z < f.n[2]) dst[x * f.sx + y * f.sy + z] = vals[li];
+                if (x < f.n[0] && y < f.n[1] && z < f.n[2]) dst[x * f.sx + y * f.sy + z] = val(li);
             }
         }
     }
