@@ -72,66 +72,19 @@ def workload_c1(torch, dev, nt):
 
 
 # ------------------------------------------------------------ cost model
-def schedule_counts(F, nt, s, peak=False):
-    """forward steps, fields encoded, restores decoding u^k only, restores
-    decoding both levels (a checkpoint keeps u^{k-1} only when the schedule
-    restarts from it); with peak, also the largest number of fields stored
-    at once."""
-    acts, nf = F.fwi_revolve_plan(nt, s)
-    # which takeshots keep both levels: those later restored and advanced from
-    both = {}
-    taken = {}
-    for i, a in enumerate(acts):
-        if a[0] == "takeshot":
-            taken[a[1]] = i
-            both[i] = False
-        elif a[0] == "restore" and a[1] >= 0 and i + 1 < len(acts) and acts[i + 1][0] == "advance":
-            both[taken[a[1]]] = True
-    nenc = rr = ra = 0
-    live = {}
-    fields = high = 0
-    for i, a in enumerate(acts):
-        if a[0] == "takeshot":
-            lv = 2 if both[i] else 1
-            live[a[1]] = lv
-            fields += lv
-            high = max(high, fields)
-            nenc += lv
-        elif a[0] == "restore" and a[1] >= 0:
-            if i + 1 < len(acts) and acts[i + 1][0] == "reverse":
-                rr += 1
-            else:
-                ra += 1
-        elif a[0] == "free":
-            fields -= live.pop(a[1])
-    return (nf, nenc, rr, ra, high) if peak else (nf, nenc, rr, ra)
+def schedule_counts(F, nt, s):
+    """(forward steps, fields encoded, restores of u^k, restores of both)"""
+    from paper_2009_12623_amd import costmodel
+    c = costmodel.schedule_counts(F.fwi_revolve_plan, nt, s)
+    return c.forward, c.encodes, c.restores_uk, c.restores_both
 
 
 def choose_slots(F, nt, st, budget, margin=1.3):
-    """Least predicted time over slot counts whose compressed checkpoints fit
-    the budget (the schedule's peak number of stored fields x the pilot's
-    mean field bytes x margin).  Costs per unit from the pilot run's
-    HIP-event timings."""
-    tf = st["ms_forward"] / max(st["n_forward"], 1)
-    ta = st["ms_adjoint"] / max(st["n_adjoint"], 1)
-    te = st["ms_encode"] / max(st["n_encode"], 1)
-    td = st["ms_decode"] / max(st["n_decode"], 1)
-    per_field = st["ckpt_bytes"] / max(st["n_encode"], 1)
-    best = None
-    cands = sorted({40, 50, 64, 80, 100, 128, 160, 200, 256, 320, 400, 512, 640, 800,
-                    1000, 1280, 1600, 2000, 2500, 3000, nt})
-    table = []
-    for s in cands:
-        if s > nt:
-            continue
-        nf, nenc, rr, ra, high = schedule_counts(F, nt, s, peak=True)
-        if high * per_field * margin > budget:
-            continue
-        t = nf * tf + nt * ta + nenc * te + (rr + 2 * ra) * td
-        table.append((s, round(t / 1e3, 3)))
-        if best is None or t < best[1]:
-            best = (s, t)
-    return best, table, dict(tf=tf, ta=ta, te=te, td=td, per_field=per_field)
+    from paper_2009_12623_amd import costmodel
+    units = costmodel.UnitCosts.from_stats(st)
+    best, table = costmodel.choose_slots(F.fwi_revolve_plan, nt, units, budget, margin)
+    return best, table, dict(tf=units.t_fwd, ta=units.t_adj, te=units.t_enc, td=units.t_dec,
+                             per_field=units.field_bytes)
 
 
 # ----------------------------------------------------------- CPU oracle
