@@ -237,3 +237,28 @@ def gradient_checkpointed(p: Problem, d_obs: np.ndarray, nslots: int,
         stats["forward_steps"] = revolve.forward_steps(acts)
         stats["d_sim"] = d
     return phi, g
+
+
+# ------------------------------------------------------------- subsampling
+def gradient_subsampled(p: Problem, d_obs: np.ndarray, factor: int, phase: int = 0):
+    """Time-subsampled imaging condition, the comparison baseline of Sec. 1
+    ("Approximate methods") and Sec. 4 ("Subsampling").  The forward and the
+    adjoint sweeps keep every step; the sum of Eq. 4 is taken only over the
+    steps k (1..N) with k = phase (mod factor), each term weighted by factor
+    so that the sum stays an estimate of the full one.  Only those forward
+    states need to be kept.  Returns (phi, g)."""
+    if factor < 1 or not 0 <= phase < factor:
+        raise ValueError("need factor >= 1 and 0 <= phase < factor")
+    d, states = forward(p, keep_states=True)
+    r = d - d_obs
+    phi = 0.5 * float(np.sum(r * r))
+    l1, l2 = p.zeros(), p.zeros()
+    g = p.zeros()
+    for k in range(p.nt, 0, -1):
+        l0 = p.step(l1, l2, p.rec, r[k - 1])
+        if k % factor == phase:
+            term = p.zeros()
+            p.image(term, states[k], l0, l1, l2)
+            g += factor * term
+        l2, l1 = l1, l0
+    return phi, g
