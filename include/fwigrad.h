@@ -160,6 +160,32 @@ int fwi_gradient(fwi_ctx *ctx, const fwi_grid *g, const float *m,
                  const fwi_ckpt_cfg *cfg, float *grad, double *phi,
                  hipStream_t stream);
 
+/* Time-subsampled imaging condition, the comparison baseline of Sec. 1
+ * ("Approximate methods") and Sec. 4 ("Subsampling"): both sweeps keep
+ * every step, but the sum of Eq. (4) runs only over the steps k (1..nt)
+ * with k = phase (mod factor), each term weighted by factor.  Only those
+ * forward states are kept (exact FP32 copies in the context's pool, capped
+ * at pool_bytes when that is nonzero); there is no recomputation.  factor 1
+ * gives fwi_gradient's exact result bit for bit.  Arguments and outputs as
+ * in fwi_gradient.  FWI_EINVAL unless factor >= 1 and 0 <= phase < factor;
+ * FWI_ECAPACITY if the kept states do not fit the pool. */
+int fwi_gradient_subsampled(fwi_ctx *ctx, const fwi_grid *g, const float *m,
+                            const fwi_shot *shot, const float *d_obs,
+                            int factor, int phase, size_t pool_bytes,
+                            float *grad, double *phi, hipStream_t stream);
+
+/* Eq. (1) rows k0+1 .. k1 from a given state: u_cur holds u^k0 and u_prev
+ * u^(k0-1) on entry [device, computational grid, not aliased]; on return
+ * they hold u^k1 and u^(k1-1).  Restarting the forward sweep from a stored
+ * (e.g. decompressed, Sec. 3 "Forward propagation") state.  d_sim [device,
+ * nt x nrec, may be NULL] receives rows k0 .. k1-1 (u^(k0+1) .. u^k1 at the
+ * receivers); other rows are left alone.  Spans chained from zero states
+ * reproduce fwi_forward_state bit for bit.  FWI_EINVAL unless
+ * 0 <= k0 <= k1 <= nt. */
+int fwi_forward_span(fwi_ctx *ctx, const fwi_grid *g, const float *m,
+                     const fwi_shot *shot, int k0, int k1, float *u_cur,
+                     float *u_prev, float *d_sim, hipStream_t stream);
+
 /* Eqs. (3)-(4) for nshots shots at once: shots that share ndim, space
  * order, nt and dt (grid dims, nbl, h, vmax, source and receivers may
  * differ, e.g. uneven apertures of one survey).  All shots follow one

@@ -85,6 +85,7 @@ struct PadMap {
 };
 void launch_coef(const float *m, float *b_padded, const PadMap &pm, double dt, hipStream_t st);
 void launch_unpad(const float *acc_padded, float *g, const PadMap &pm, hipStream_t st);
+void launch_pad(const float *f, float *dst_padded, const PadMap &pm, hipStream_t st);
 void launch_fill_zero(float *p, size_t n, hipStream_t st);
 void launch_copy(float *dst, const float *src, size_t n, hipStream_t st);
 void launch_probe(const float *a, const float *b, const float *c, float *d, size_t n, int nsrc,
@@ -99,7 +100,7 @@ void launch_residual(const float *d_sim, const float *d_obs, float *res,
 // pointers are allocation bases of padded arrays
 struct InjectParams {
     float *lam;             // new adjoint level
-    float *g;               // gradient accumulator
+    float *g;               // gradient accumulator (nullptr: no imaging term)
     const float *uk;        // forward state
     const float *b;
     const float *res_row;   // residual row of this step (nrec)

@@ -804,12 +804,13 @@ struct Exec {
         return p;
     }
 
-    // receiver residuals into the new adjoint level (and their imaging term)
-    void post_reverse(int k)
+    // receiver residuals into the new adjoint level (and their imaging term,
+    // scaled by img; img = 0: the step images nothing)
+    void post_reverse(int k, float img = 1.0f)
     {
         InjectParams ip{};
         ip.lam = l2;
-        ip.g = B->gacc.p;
+        ip.g = img != 0.0f ? B->gacc.p : nullptr;
         ip.uk = cur;
         ip.b = B->coef.p;
         ip.res_row = adj_src + (size_t)(k - 1) * S.nrec;
@@ -824,7 +825,7 @@ struct Exec {
         ip.nbl = S.nbl;
         ip.ndim = S.ndim;
         ip.kappa = S.kappa;
-        ip.inv_dt2 = S.inv_dt2;
+        ip.inv_dt2 = S.inv_dt2 * img;
         launch_inject(ip, st);
         std::swap(l1, l2);
         c->stats.n_adjoint += 1;
@@ -838,6 +839,50 @@ struct Exec {
             launch_step(adj_params(), S.ndim, S.R, true, st);
         }
         post_reverse(k);
+    }
+
+    // Time-subsampled imaging: every forward step, keeping u^k (exact copy,
+    // slot j at store + j raw) at the steps k = phase (mod factor); then
+    // every adjoint step, imaging only at those steps with weight factor.
+    // Adjoint steps that image nothing run the forward stencil without
+    // source (same update, no u^k / g streams).
+    void run_subsampled(int factor, int phase, char *store, size_t raw)
+    {
+        size_t j = 0;
+        for (int k = 1; k <= S.nt; ++k) {
+            {
+                Timer tm(c, st, K_FWD);
+                const StepParams p = fwd_params(k, true);
+                launch_step(p, S.ndim, S.R, false, st);
+                fwd_commit(p);
+            }
+            c->stats.n_forward += 1;
+            work = k;
+            if (k % factor == phase) {
+                launch_copy((float *)(store + j * raw), cur, raw / sizeof(float), st);
+                ++j;
+            }
+        }
+        pre_reverse(S.nt);
+        for (int k = S.nt; k >= 1; --k) {
+            Timer tm(c, st, K_ADJ);
+            if (k % factor == phase) {
+                --j;
+                cur = (float *)(store + j * raw);
+                StepParams p = adj_params();
+                p.inv_dt2 = S.inv_dt2 * (float)factor;
+                launch_step(p, S.ndim, S.R, true, st);
+                post_reverse(k, (float)factor);
+            } else {
+                StepParams p = params();
+                apply_shape(p, false);
+                p.u1 = l1;
+                p.u2 = l2;
+                p.out = l2;
+                launch_step(p, S.ndim, S.R, false, st);
+                post_reverse(k, 0.0f);
+            }
+        }
     }
 
     // run acts[from, to); stops before the first REVERSE if stop_at_reverse
@@ -1377,6 +1422,76 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(phi, c->sb.phi.p, sizeof(double), hipMemcpyDeviceToHost, st));
         finish_status(c, st);
+        end_call(c, st);
+    });
+}
+
+int fwi_gradient_subsampled(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot,
+                            const float *d_obs, int factor, int phase, size_t pool_bytes, float *grad,
+                            double *phi, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !m || !grad || !phi || (!d_obs && shot && shot->nrec > 0))
+            throw Error{FWI_EINVAL, "null argument"};
+        if (factor < 1 || phase < 0 || phase >= factor)
+            throw Error{FWI_EINVAL, "need factor >= 1 and 0 <= phase < factor"};
+        begin_call(c, st);
+        Exec ex{c, make_setup(g, shot, true), st, m, shot};
+        ensure_fields(&c->sb, ex.S);
+        size_t nstore = 0;
+        for (int k = 1; k <= ex.S.nt; ++k) nstore += k % factor == phase;
+        const size_t raw = c->sb.padded_elems * sizeof(float);
+        if (c->pool.n < c->pool_default) c->pool.ensure(c->pool_default);
+        const size_t cap = pool_bytes ? std::min(pool_bytes, c->pool_default) : c->pool_default;
+        if (nstore * raw > cap)
+            throw Error{FWI_ECAPACITY, "subsampled snapshots exceed the pool (" + std::to_string(nstore) +
+                                           " fields): raise the factor or the pool"};
+        const size_t nd = (size_t)ex.S.nt * ex.S.nrec;
+        c->sb.dsim.ensure(std::max<size_t>(nd, 1));
+        c->sb.res.ensure(std::max<size_t>(nd, 1));
+        c->sb.partials.ensure(256);
+        c->sb.phi.ensure(1);
+        HIPCHK(hipMemsetAsync(c->sb.phi.p, 0, sizeof(double), st));
+        ex.dsim = c->sb.dsim.p;
+        ex.d_obs = d_obs;
+        ex.grad = grad;
+        ex.init_fields();
+        ex.init_adjoint();
+        ex.run_subsampled(factor, phase, (char *)c->pool.p, raw);
+        launch_unpad(c->sb.gacc.p, grad, ex.padmap(), st);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(phi, c->sb.phi.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        c->stats.ckpt_raw_bytes = (long long)(nstore * (size_t)ex.S.ncomp * 4);
+        c->stats.ckpt_bytes = (long long)(nstore * raw);
+        c->stats.pool_high = (long long)(nstore * raw);
+        end_call(c, st);
+    });
+}
+
+int fwi_forward_span(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot, int k0, int k1,
+                     float *u_cur, float *u_prev, float *d_sim, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !m || !u_cur || !u_prev || !g) throw Error{FWI_EINVAL, "null argument"};
+        if (u_cur == u_prev || (d_sim && (d_sim == u_cur || d_sim == u_prev)))
+            throw Error{FWI_EINVAL, "u_cur, u_prev and d_sim must be distinct arrays"};
+        if (k0 < 0 || k1 < k0 || k1 > g->nt) throw Error{FWI_EINVAL, "need 0 <= k0 <= k1 <= nt"};
+        begin_call(c, st);
+        Exec ex{c, make_setup(g, shot, true), st, m, shot};
+        ensure_fields(&c->sb, ex.S);
+        const bool record = d_sim != nullptr;
+        ex.dsim = d_sim;
+        ex.init_fields();
+        launch_pad(u_cur, ex.W0(), ex.padmap(), st);
+        launch_pad(u_prev, ex.W1(), ex.padmap(), st);
+        ex.work = k0;
+        ex.reached = k0;
+        if (k1 > k0) ex.advance(k0, k1, record);
+        if (record) ex.flush_record();
+        launch_unpad(ex.cur, u_cur, ex.padmap(), st);
+        launch_unpad(ex.prev, u_prev, ex.padmap(), st);
+        HIPCHK(hipGetLastError());
         end_call(c, st);
     });
 }

@@ -624,6 +624,18 @@ __global__ void coef_kernel(const float *m, float *b, PadMap pm, float dt2)
     }
 }
 
+// padded (interior only; pads untouched) = unpadded field
+__global__ void pad_kernel(const float *f, float *dst, PadMap pm)
+{
+    const size_t n = (size_t)pm.nx * pm.ny * pm.nz;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t z = i % pm.nz, r = i / pm.nz;
+        const size_t y = r % pm.ny, x = r / pm.ny;
+        dst[pm.origin + x * pm.sx + y * pm.sy + z] = f[i];
+    }
+}
+
 // grad (unpadded) = accumulator (padded)
 __global__ void unpad_kernel(const float *acc, float *g, PadMap pm)
 {
@@ -693,7 +705,7 @@ __global__ void inject_kernel(InjectParams p)
     const float e = p.kappa * bb * (float)(dx * dx + dy * dy + dz * dz);
     const float delta = bb * s / (1.0f + e);
     p.lam[pi] += delta;
-    p.g[pi] -= p.uk[pi] * delta * p.inv_dt2;
+    if (p.g) p.g[pi] -= p.uk[pi] * delta * p.inv_dt2;
 }
 
 }  // namespace
@@ -784,6 +796,12 @@ void launch_unpad(const float *acc, float *g, const PadMap &pm, hipStream_t st)
 {
     hipLaunchKernelGGL(unpad_kernel, dim3(grid_for((size_t)pm.nx * pm.ny * pm.nz)), dim3(256), 0, st, acc,
                        g, pm);
+}
+
+void launch_pad(const float *f, float *dst, const PadMap &pm, hipStream_t st)
+{
+    hipLaunchKernelGGL(pad_kernel, dim3(grid_for((size_t)pm.nx * pm.ny * pm.nz)), dim3(256), 0, st, f, dst,
+                       pm);
 }
 
 void launch_gather(const float *field, const int *off, int n, float *out, hipStream_t st)

@@ -72,7 +72,7 @@ EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_s
            "fwi_backward", "fwi_tape_free", "ckpt_bound", "ckpt_compress",
            "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune", "fwi_ckpt_pool_bytes", "fwi_forward_state", "fwi_gradient_batch", "fwi_ctx_set_graphs",
            "ckpt_compress_view", "ckpt_decompress_view", "fwi_forward_ckpt_batch",
-           "fwi_backward_batch"]
+           "fwi_backward_batch", "fwi_gradient_subsampled", "fwi_forward_span"]
 
 
 def lib():
@@ -121,6 +121,10 @@ def lib():
                                          ctypes.POINTER(fwi_shot), ctypes.POINTER(fwi_ckpt_cfg),
                                          ctypes.POINTER(P), ctypes.POINTER(P), P]
     L.fwi_backward_batch.argtypes = [P, P, ctypes.POINTER(P), ctypes.POINTER(P), P]
+    L.fwi_gradient_subsampled.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), P, I, I,
+                                          ctypes.c_size_t, P, ctypes.POINTER(ctypes.c_double), P]
+    L.fwi_forward_span.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), I, I, P, P, P,
+                                   P]
     L.fwi_ckpt_pool_bytes.argtypes = [ctypes.POINTER(fwi_grid), ctypes.POINTER(fwi_ckpt_cfg),
                                       ctypes.POINTER(ctypes.c_size_t)]
     L.fwi_autotune.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), I,
@@ -288,6 +292,30 @@ class Context:
         check(lib().fwi_forward_state(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), _ptr(d),
                                       _ptr(u1), _ptr(u0), _stream()))
         return d, u1, u0
+
+    def forward_span(self, shot, m, wavelet, k0, k1, u_cur, u_prev, d_sim=None):
+        """fwi_forward_span: advances (u_cur, u_prev) = (u^k0, u^{k0-1}) in
+        place to (u^k1, u^{k1-1}); fills rows k0..k1-1 of d_sim if given."""
+        sa = ShotArgs(shot, wavelet)
+        g = grid_of(shot)
+        for t in (u_cur, u_prev):
+            if t.shape != m.shape or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("states must be contiguous float32 arrays of the model's shape")
+        check(lib().fwi_forward_span(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), int(k0), int(k1),
+                                     _ptr(u_cur), _ptr(u_prev), _ptr(d_sim) if d_sim is not None else None,
+                                     _stream()))
+        return u_cur, u_prev
+
+    def gradient_subsampled(self, shot, m, wavelet, d_obs, factor, phase=0, pool_bytes=0, grad=None):
+        """fwi_gradient_subsampled: (phi, grad) with imaging every factor-th step"""
+        sa = ShotArgs(shot, wavelet)
+        g = grid_of(shot)
+        out = torch.empty_like(m) if grad is None else grad
+        phi = ctypes.c_double()
+        check(lib().fwi_gradient_subsampled(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), _ptr(d_obs),
+                                            int(factor), int(phase), int(pool_bytes), _ptr(out),
+                                            ctypes.byref(phi), _stream()))
+        return phi.value, out
 
     # Eqs. (3)-(4)
     def gradient(self, shot, m, wavelet, d_obs, nslots=10, compress=False, atol=1e-4,
