@@ -471,12 +471,81 @@ def run_c5(args, torch, F, dev):
 
 
 # ------------------------------------------------------------------ main
+def run_studies(args, torch, F, dev):
+    """The error and compressibility experiments of Sec. 4 on the GPU path:
+    compressibility over time and lossy restart on the 3D thrust model (961 x
+    961 x 367 computational grid, 2000 steps); gradient error against atol,
+    against the number of checkpoints and against the subsampling factor on
+    the 2D layered shot (181 x 181, 500 steps); stacking error over the 16
+    shots of the 2D smooth model (1081 x 481, 3000 steps, 40 slots)."""
+    from paper_2009_12623_amd import studies
+    import synth
+    t_start = time.time()
+    out = {}
+    ctx = F.Context(0, pool_bytes=24 << 30)
+    # 3D: compressibility and restart
+    shot, m0, mt, name3, _ = workload_c3(torch, dev, args.nt or 2000)
+    q = torch.from_numpy(shot.wavelet().astype(np.float32)).to(dev)
+    del m0
+    t0 = time.time()
+    out["compressibility_over_time"] = {
+        "workload": name3, "atol": 1e-4,
+        "rows": studies.compressibility_over_time(ctx, shot, mt, q, 1e-4, every=max(shot.nt // 20, 1))}
+    log("compressibility over time: %.1f s" % (time.time() - t0))
+    t0 = time.time()
+    out["lossy_restart"] = {
+        "workload": name3, "restart_step": shot.nt // 2,
+        "rows": studies.lossy_restart(ctx, shot, mt, q, shot.nt // 2, [1e-1, 1e-2, 1e-4, 1e-6])}
+    log("lossy restart: %.1f s" % (time.time() - t0))
+    del mt
+    torch.cuda.empty_cache()
+    # 2D single shot: gradient error against atol, slots and subsampling
+    shot, m0, mt, name1, _ = workload_c1(torch, dev, 500)
+    q = torch.from_numpy(shot.wavelet().astype(np.float32)).to(dev)
+    d_obs = ctx.forward(shot, mt, q)
+    t0 = time.time()
+    out["gradient_error_vs_atol"] = {
+        "workload": name1,
+        "rows": studies.gradient_error_vs_atol(ctx, shot, m0, q, d_obs,
+                                               [1.0, 1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6])}
+    out["gradient_error_vs_slots"] = {
+        "workload": name1,
+        "rows": studies.gradient_error_vs_slots(ctx, shot, m0, q, d_obs,
+                                                [5, 8, 15, 25, 44, 76, 132, 227, 391, 500],
+                                                [1e-1, 1e-2, 1e-4, 1e-8])}
+    out["subsampling_error"] = {
+        "workload": name1,
+        "rows": studies.subsampling_error(ctx, shot, m0, q, d_obs, [2, 3, 4, 6, 8, 12, 16, 24, 32])}
+    log("2D gradient studies: %.1f s" % (time.time() - t0))
+    # stacking over the 2D multi-shot survey
+    shots = synth.config5_shots(nt=3000)
+    v0 = synth.smooth_2d()
+    vt = synth.blobs_2d(v0)
+    nbl = shots[0].nbl
+    m0 = torch.from_numpy(synth.slowness2(synth.extend(v0, nbl)).astype(np.float32)).to(dev)
+    mt = torch.from_numpy(synth.slowness2(synth.extend(vt, nbl)).astype(np.float32)).to(dev)
+    q = torch.from_numpy(shots[0].wavelet().astype(np.float32)).to(dev)
+    d5 = [ctx.forward(s, mt, q) for s in shots]
+    t0 = time.time()
+    out["stacking_error"] = {
+        "workload": "2D smooth model 1001x401 at 10 m (1081x481), SO16, 3000 steps, 16 shots, 40 slots",
+        "atol": 1e-4,
+        "rows": studies.stacking_error(ctx, shots, [m0] * len(shots), q, d5, 1e-4, 40)}
+    log("stacking: %.1f s" % (time.time() - t0))
+    ctx.close()
+    total = time.time() - t_start
+    print(json.dumps({"metric": "error and compressibility studies (Sec. 4), wall time", "value": round(total, 1),
+                      "unit": "s", "n_gpus": 1, "higher_is_better": False, "vs_baseline": None,
+                      "dtype": "f32", "data": "synthetic", "config": {"workload": "studies"},
+                      "studies": out}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5", "studies"])
     ap.add_argument("--nt", type=int, default=None)
     ap.add_argument("--atol", type=float, default=1e-4)
     ap.add_argument("--slots", type=int, default=0, help="compressed slots (0: cost model)")
@@ -516,6 +585,8 @@ def main():
                                             "GBs": round(4 * n * (nsrc + 1) / ms / 1e6, 1)}
         print(json.dumps(res))
         return
+    if args.workload == "studies":
+        return run_studies(args, torch, F, dev)
     if args.workload == "c5":
         run_c5(args, torch, F, dev)
         return
