@@ -540,15 +540,65 @@ def run_studies(args, torch, F, dev):
                       "studies": out}), flush=True)
 
 
+def run_fwi_loop(args, torch, F, dev):
+    """2D FWI (Sec. 4 "Convergence") on the 16-shot smooth-model survey
+    (1001x401 at 10 m, 1081x481 with the layer, SO16, 3000 steps, 40 slots):
+    30 gradient-descent iterations through the batched autograd path with
+    exact checkpoints and with compressed ones at several atol; objective
+    trajectories, model error and seconds per iteration."""
+    from paper_2009_12623_amd import fwi
+    import synth
+    iters = args.iterations
+    shots = synth.config5_shots(nt=args.nt or 3000)
+    v0 = synth.smooth_2d()
+    vt = synth.blobs_2d(v0)
+    nbl = shots[0].nbl
+    m0 = torch.from_numpy(synth.slowness2(synth.extend(v0, nbl)).astype(np.float32)).to(dev)
+    mt = torch.from_numpy(synth.slowness2(synth.extend(vt, nbl)).astype(np.float32)).to(dev)
+    q = torch.from_numpy(shots[0].wavelet().astype(np.float32)).to(dev)
+    mask = torch.zeros_like(m0)
+    mask[nbl:-nbl, nbl + 10:-nbl] = 1.0      # layer and the acquisition rows stay fixed
+    ctx = F.Context(0, pool_bytes=8 << 30)
+    if not args.no_autotune:
+        ctx.autotune(shots[0], m0, q, steps=8)
+    d_obs = [ctx.forward(s, mt, q) for s in shots]
+    phys = (slice(nbl, -nbl), slice(nbl, -nbl))
+    err0 = rel_l2(m0[phys], mt[phys])
+    runs = {}
+    for atol in [None, 1e-1, 1e-2, 1e-4]:
+        t0 = time.time()
+        r = fwi.run_fwi(ctx, shots, m0, q, d_obs, iterations=iters, nslots=40, compress=atol is not None,
+                        atol=atol or 1e-4, step=0.05, vmin=1500.0, vmax=4500.0, mask=mask)
+        key = "exact" if atol is None else "atol_%g" % atol
+        runs[key] = {"objective": [float("%.6g" % x) for x in r["objective"]],
+                     "model_rel_l2": round(rel_l2(r["m"][phys], mt[phys]), 6),
+                     "s_per_iteration": round(r["s_per_iteration"], 3)}
+        log("%s: objective %.4e -> %.4e, model error %.4f -> %.4f, %.2f s/iteration (%.1f s)" %
+            (key, r["objective"][0], r["objective"][-1], err0, runs[key]["model_rel_l2"],
+             r["s_per_iteration"], time.time() - t0))
+    ex = runs["exact"]["objective"]
+    for k, v in runs.items():
+        v["max_rel_dev_from_exact"] = float("%.4g" % max(abs(a - b) / b for a, b in zip(v["objective"], ex)))
+    ctx.close()
+    print(json.dumps({"metric": "2D FWI loop, 16 shots per iteration: s/iteration (compressed, atol 1e-4)",
+                      "value": runs["atol_0.0001"]["s_per_iteration"], "unit": "s/iteration", "n_gpus": 1,
+                      "steps": iters, "higher_is_better": False, "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": "2D FWI, 1001x401 smooth model + 3 blobs, 16 shots, SO16, "
+                                             "%d steps, 40 slots, %d iterations" % (shots[0].nt, iters)},
+                      "initial_model_rel_l2": round(err0, 6), "runs": runs}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5", "studies"])
+    ap.add_argument("--workload", default="c3", choices=["c3", "c1", "c2", "c4", "c5", "studies", "fwi"])
     ap.add_argument("--nt", type=int, default=None)
     ap.add_argument("--atol", type=float, default=1e-4)
     ap.add_argument("--slots", type=int, default=0, help="compressed slots (0: cost model)")
+    ap.add_argument("--iterations", type=int, default=30, help="FWI iterations (fwi workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (HBM counter calibration)")
@@ -585,6 +635,8 @@ def main():
                                             "GBs": round(4 * n * (nsrc + 1) / ms / 1e6, 1)}
         print(json.dumps(res))
         return
+    if args.workload == "fwi":
+        return run_fwi_loop(args, torch, F, dev)
     if args.workload == "studies":
         return run_studies(args, torch, F, dev)
     if args.workload == "c5":
