@@ -775,6 +775,13 @@ def main():
                 "fields": ["x_planes_per_workgroup", "rows_per_lane", "xcd_contiguous", "planes_in_flight_2"]},
         },
         "roofline": roof,
+        # the same kernels timed alone (autotune trials, no codec work beside
+        # them); the timed region runs the codec concurrently on a second stream
+        "roofline_isolated": None if tune is None else {
+            "adjoint_imaging_step": {"avg_launch_ms": round(tune["adj_ms"], 4),
+                                     "frac": round(28.0 * npts / (tune["adj_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "forward_step": {"avg_launch_ms": round(tune["fwd_ms"], 4),
+                             "frac": round(16.0 * npts / (tune["fwd_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}},
         "stencil_gpts": {"forward": round(npts / (fwd_avg * 1e-3) / 1e9, 2),
                          "forward_physical": round(nphys / (fwd_avg * 1e-3) / 1e9, 2),
                          "adjoint": round(npts / (st["ms_adjoint"] / max(st["n_adjoint"], 1) * 1e-3) / 1e9, 2)},

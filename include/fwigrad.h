@@ -135,6 +135,14 @@ int fwi_ctx_stats(const fwi_ctx *ctx, fwi_stats *out);
  * launches.  Per-kernel timings are not collected during replays; launch
  * counts are.  Off by default; off drops every graph. */
 int fwi_ctx_set_graphs(fwi_ctx *ctx, int on);
+/* Codec overlap: with on != 0 (the default), fwi_gradient and the
+ * single-shot tapes run the checkpoint codec of compressed schedules on a
+ * second stream of the context (default priority), ordered with events
+ * against the stencil steps that share its working buffers, so encodes and
+ * decodes run beside the forward and adjoint steps.  Results are identical
+ * either way; per-kernel timings then overlap.  Changing it drops captured
+ * schedules. */
+int fwi_ctx_set_overlap(fwi_ctx *ctx, int on);
 /* Message of the last failure on this thread (static storage). */
 const char *fwi_last_error(void);
 

@@ -214,6 +214,26 @@ struct fwi_ctx {
     fwi_stats stats{};
     std::vector<hipEvent_t> evpool;
     size_t evused = 0;
+    // codec work of compressed single-shot schedules runs on its own stream,
+    // overlapped with the stencil; ordering events come from spool
+    int overlap = 1;
+    hipStream_t cstream = nullptr;
+    std::vector<hipEvent_t> spool;
+    size_t sused = 0;
+    hipStream_t codec_stream()
+    {
+        if (!cstream) HIPCHK(hipStreamCreateWithFlags(&cstream, hipStreamNonBlocking));
+        return cstream;
+    }
+    hipEvent_t sev()
+    {
+        if (sused == spool.size()) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            spool.push_back(e);
+        }
+        return spool[sused++];
+    }
     struct Iv {
         int kind;
         hipEvent_t a, b;
@@ -483,6 +503,7 @@ void begin_call(fwi_ctx *c, hipStream_t st)
     c->stats = fwi_stats{};
     c->ivs.clear();
     c->evused = 0;
+    c->sused = 0;
     if (c->timing) {
         if (!c->t0) {
             HIPCHK(hipEventCreate(&c->t0));
@@ -541,12 +562,76 @@ struct Exec {
     StreamSlot *slots = nullptr;
     size_t raw_bytes = 0;            // uncompressed: bytes of one padded level
     std::vector<char> slot_both;     // slot holds both levels
+    // Codec stream (compressed schedules with overlap on; nullptr: all work
+    // on st).  The working buffers W0/W1 are the only memory both streams
+    // touch; for each, the event after its last use on each stream orders
+    // the other stream's next use (encode of u^k runs beside the next
+    // forward step, decode of the next u^k beside the current adjoint step).
+    hipStream_t cs = nullptr;
+    hipEvent_t wmain[2] = {nullptr, nullptr}, wcodec[2] = {nullptr, nullptr};
 
     // cur/prev/l1/l2 are allocation bases of padded arrays
     float *at_origin(float *base) const { return base + S.pad.origin; }
     float *W0() const { return B->fa.p; }
     float *W1() const { return B->fb.p; }
     bool in_w(const float *p) const { return p == W0() || p == W1(); }
+
+    int wslot(const float *p) const { return p == W0() ? 0 : p == W1() ? 1 : -1; }
+    hipStream_t cst() const { return cs ? cs : st; }
+    // main stream: wait for the codec's last use of buffer p
+    void main_wait(const float *p)
+    {
+        const int i = wslot(p);
+        if (cs && i >= 0 && wcodec[i]) {
+            HIPCHK(hipStreamWaitEvent(st, wcodec[i], 0));
+            wcodec[i] = nullptr;
+        }
+    }
+    // main stream has just used the given buffers
+    void main_used(const float *a, const float *b = nullptr, const float *o = nullptr)
+    {
+        if (!cs) return;
+        hipEvent_t e = c->sev();
+        HIPCHK(hipEventRecord(e, st));
+        for (const float *p : {a, b, o}) {
+            const int i = wslot(p);
+            if (i >= 0) wmain[i] = e;
+        }
+    }
+    // codec stream: wait for the main stream's last use of buffer p
+    void codec_wait(const float *p)
+    {
+        const int i = wslot(p);
+        if (cs && i >= 0 && wmain[i]) HIPCHK(hipStreamWaitEvent(cs, wmain[i], 0));
+    }
+    void codec_used(const float *p)
+    {
+        const int i = wslot(p);
+        if (!cs || i < 0) return;
+        hipEvent_t e = c->sev();
+        HIPCHK(hipEventRecord(e, cs));
+        wcodec[i] = e;
+    }
+    // start of a run: the codec stream follows everything issued so far
+    void fork()
+    {
+        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = nullptr;
+        cs = (compress && c->overlap) ? c->codec_stream() : nullptr;
+        if (!cs) return;
+        hipEvent_t e = c->sev();
+        HIPCHK(hipEventRecord(e, st));
+        HIPCHK(hipStreamWaitEvent(cs, e, 0));
+    }
+    // end of a run: the main stream follows all codec work
+    void join()
+    {
+        if (!cs) return;
+        hipEvent_t e = c->sev();
+        HIPCHK(hipEventRecord(e, cs));
+        HIPCHK(hipStreamWaitEvent(st, e, 0));
+        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = nullptr;
+        cs = nullptr;
+    }
 
     PadMap padmap() const
     {
@@ -665,7 +750,11 @@ struct Exec {
         Timer tm(c, st, K_FWD);
         for (int k = a + 1; k <= b; ++k) {
             const StepParams p = fwd_params(k, record);
+            main_wait(p.u1);
+            main_wait(p.u2);
+            main_wait(p.out);
             launch_step(p, S.ndim, S.R, false, st);
+            main_used(p.u1, p.u2, p.out);
             fwd_commit(p);
         }
         c->stats.n_forward += b - a;
@@ -728,17 +817,22 @@ struct Exec {
             return;
         }
         for (int lev = 0; lev < levels; ++lev) {
-            Timer tm(c, st, K_ENC);
-            codec_encode(encode_args(slot, lev), st);
+            const float *src = lev == 0 ? cur : prev;
+            codec_wait(src);
+            {
+                Timer tm(c, cst(), K_ENC);
+                codec_encode(encode_args(slot, lev), cst());
+            }
+            codec_used(src);
             c->stats.n_encode += 1;
         }
     }
 
-    DecodeArgs decode_args(int slot, int lev) const
+    DecodeArgs decode_args(int slot, int lev, float *target = nullptr) const
     {
         DecodeArgs d{};
         d.f = padded_view(S);
-        d.dst = at_origin(lev == 0 ? W0() : W1());
+        d.dst = at_origin(target ? target : (lev == 0 ? W0() : W1()));
         d.stream = nullptr;
         d.pool = pool;
         d.slots = slots;
@@ -747,11 +841,12 @@ struct Exec {
         return d;
     }
 
-    // working state after decoding a compressed checkpoint into W0 (and W1)
-    void restore_commit(int k, bool only_cur)
+    // working state after decoding a compressed checkpoint into t0 (and the
+    // other working buffer)
+    void restore_commit(int k, bool only_cur, float *t0 = nullptr)
     {
-        cur = W0();
-        prev = W1();
+        cur = t0 ? t0 : W0();
+        prev = cur == W0() ? W1() : W0();
         prev_valid = !only_cur;
         work = k;
     }
@@ -759,8 +854,11 @@ struct Exec {
     void restore(int slot, int k, bool only_cur)
     {
         if (slot < 0) {
+            main_wait(W0());
+            main_wait(W1());
             launch_fill_zero(B->fa.p, B->padded_elems, st);
             launch_fill_zero(B->fb.p, B->padded_elems, st);
+            main_used(W0(), W1());
             cur = W0();
             prev = W1();
             prev_valid = true;
@@ -770,12 +868,20 @@ struct Exec {
             prev = (float *)(pool + off + raw_bytes);
             prev_valid = slot < (int)slot_both.size() && slot_both[slot];
         } else {
+            // u^k alone goes to the working buffer the current state is not
+            // in, so the decode can run beside the adjoint step reading it
+            float *t0 = only_cur ? (cur == W0() ? W1() : W0()) : W0();
             for (int lev = 0; lev < (only_cur ? 1 : 2); ++lev) {
-                Timer tm(c, st, K_DEC);
-                codec_decode(decode_args(slot, lev), st);
+                float *t = lev == 0 ? t0 : (t0 == W0() ? W1() : W0());
+                codec_wait(t);
+                {
+                    Timer tm(c, cst(), K_DEC);
+                    codec_decode(decode_args(slot, lev, t), cst());
+                }
+                codec_used(t);
                 c->stats.n_decode += 1;
             }
-            restore_commit(k, only_cur);
+            restore_commit(k, only_cur, t0);
         }
         work = k;
     }
@@ -834,11 +940,13 @@ struct Exec {
     void reverse(int k)
     {
         pre_reverse(k);
+        main_wait(cur);
         {
             Timer tm(c, st, K_ADJ);
             launch_step(adj_params(), S.ndim, S.R, true, st);
         }
         post_reverse(k);
+        main_used(cur);
     }
 
     // Time-subsampled imaging: every forward step, keeping u^k (exact copy,
@@ -889,6 +997,7 @@ struct Exec {
     size_t run(const std::vector<fwi_action> &acts, const std::vector<char> &both, size_t from,
                bool stop_at_reverse)
     {
+        fork();
         size_t i = from;
         for (; i < acts.size(); ++i) {
             const fwi_action &a = acts[i];
@@ -902,6 +1011,7 @@ struct Exec {
             }
             case FWI_REVERSE:
                 if (stop_at_reverse) {
+                    join();
                     flush_record();
                     return i;
                 }
@@ -911,6 +1021,7 @@ struct Exec {
             default: throw Error{FWI_EINVAL, "internal: bad action"};
             }
         }
+        join();
         return i;
     }
 };
@@ -1301,6 +1412,8 @@ int fwi_ctx_destroy(fwi_ctx *c)
         (void)hipSetDevice(c->device);
         (void)hipDeviceSynchronize();
         for (auto e : c->evpool) (void)hipEventDestroy(e);
+        for (auto e : c->spool) (void)hipEventDestroy(e);
+        if (c->cstream) (void)hipStreamDestroy(c->cstream);
         if (c->t0) (void)hipEventDestroy(c->t0);
         if (c->t1) (void)hipEventDestroy(c->t1);
         c->drop_graphs();
@@ -1314,6 +1427,15 @@ int fwi_ctx_destroy(fwi_ctx *c)
         c->scratch.release(); c->chunk_bits.release(); c->chunk_off.release();
         c->misc.release(); c->flags.release();
         delete c;
+    });
+}
+
+int fwi_ctx_set_overlap(fwi_ctx *c, int on)
+{
+    return guarded([&] {
+        if (!c) throw Error{FWI_EINVAL, "ctx is null"};
+        c->overlap = on != 0;
+        c->drop_graphs();
     });
 }
 

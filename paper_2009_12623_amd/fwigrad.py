@@ -72,7 +72,8 @@ EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_s
            "fwi_backward", "fwi_tape_free", "ckpt_bound", "ckpt_compress",
            "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune", "fwi_ckpt_pool_bytes", "fwi_forward_state", "fwi_gradient_batch", "fwi_ctx_set_graphs",
            "ckpt_compress_view", "ckpt_decompress_view", "fwi_forward_ckpt_batch",
-           "fwi_backward_batch", "fwi_gradient_subsampled", "fwi_forward_span"]
+           "fwi_backward_batch", "fwi_gradient_subsampled", "fwi_forward_span",
+           "fwi_ctx_set_overlap"]
 
 
 def lib():
@@ -90,6 +91,7 @@ def lib():
     L.fwi_ctx_destroy.argtypes = [P]
     L.fwi_ctx_set_timing.argtypes = [P, I]
     L.fwi_ctx_set_graphs.argtypes = [P, I]
+    L.fwi_ctx_set_overlap.argtypes = [P, I]
     CL = ctypes.c_long
     L.ckpt_compress_view.argtypes = [P, P, I, ctypes.POINTER(ctypes.c_int), CL, CL, I, ctypes.c_double, P,
                                      ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]
@@ -257,6 +259,9 @@ class Context:
 
     def set_graphs(self, on: bool):
         check(lib().fwi_ctx_set_graphs(self.h, int(bool(on))))
+
+    def set_overlap(self, on: bool):
+        check(lib().fwi_ctx_set_overlap(self.h, int(bool(on))))
 
     def set_timing(self, on: bool):
         check(lib().fwi_ctx_set_timing(self.h, int(bool(on))))
