@@ -599,6 +599,8 @@ def main():
     ap.add_argument("--atol", type=float, default=1e-4)
     ap.add_argument("--slots", type=int, default=0, help="compressed slots (0: cost model)")
     ap.add_argument("--iterations", type=int, default=30, help="FWI iterations (fwi workload)")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the checkpoint codec on the launch stream instead of beside the stencil")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (HBM counter calibration)")
@@ -657,6 +659,7 @@ def main():
 
     ctx = F.Context(0, pool_bytes=int(os.environ.get("FWI_POOL_BYTES", 140 << 30)))
     ctx.set_timing(True)
+    ctx.set_overlap(not args.no_overlap)
     tune = None
     if not args.no_autotune:
         t0 = time.time()
@@ -768,6 +771,7 @@ def main():
             "atol": args.atol,
             "nslots_compressed": s_c,
             "nslots_uncompressed": s_unc,
+            "codec_overlap": not args.no_overlap,
             "hbm_budget_gb": round(budget / 1e9, 2),
             "stencil_shape": None if tune is None else {
                 "forward": [tune["fwd_xchunk"], tune["fwd_rows_per_lane"], tune["fwd_xcd_order"], tune["fwd_deep"]],

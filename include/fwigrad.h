@@ -286,7 +286,9 @@ int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
  * per lane with two planes of loads in flight}; 2D: x planes in {4..64}), `steps` forward and `steps` adjoint launches each on the model
  * m [device], with the buffer roles alternating as in a sweep, and keeps
  * the fastest forward and adjoint shapes for later calls on a grid of the
- * same dims and order.  Results [host].  Synchronises the stream; the context's
+ * same dims and order.  Every candidate is timed once; the best four of each
+ * sweep are timed three more times, interleaved, and the best mean wins.
+ * Results [host].  Synchronises the stream; the context's
  * working fields are cleared (tapes keep their own state). */
 typedef struct {
     int ncand;

@@ -2254,13 +2254,27 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
             ex.init_fields();
         };
         reset();
-        double bf = 1e30, ba = 1e30;
-        fwi_ctx::Shape sf = cands[0], sa = cands[0];
-        for (const auto &sh : cands) {
-            const double tf = time_it(sh, false), ta = time_it(sh, true);
-            if (tf < bf) { bf = tf; sf = sh; }
-            if (ta < ba) { ba = ta; sa = sh; }
+        // screen every candidate, then re-time the best few of each sweep
+        // three more times, interleaved, and keep the best mean
+        std::vector<std::pair<double, size_t>> rf, ra;
+        for (size_t i = 0; i < cands.size(); ++i) {
+            rf.push_back({time_it(cands[i], false), i});
+            ra.push_back({time_it(cands[i], true), i});
         }
+        std::sort(rf.begin(), rf.end());
+        std::sort(ra.begin(), ra.end());
+        const size_t top = std::min<size_t>(4, cands.size());
+        rf.resize(top);
+        ra.resize(top);
+        for (int round = 0; round < 3; ++round)
+            for (size_t j = 0; j < top; ++j) {
+                rf[j].first += time_it(cands[rf[j].second], false);
+                ra[j].first += time_it(cands[ra[j].second], true);
+            }
+        std::sort(rf.begin(), rf.end());
+        std::sort(ra.begin(), ra.end());
+        const double bf = rf[0].first / 4, ba = ra[0].first / 4;
+        const fwi_ctx::Shape sf = cands[rf[0].second], sa = cands[ra[0].second];
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         c->tuned[ex.grid_key()] = {sf, sa};
