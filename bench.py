@@ -105,7 +105,7 @@ def cpu_baseline(shot, m0_host, counts, seconds=8.0):
         u = p.step(u1, u2, [p.src], [p.q[nf]])
         u2, u1 = u1, u
         nf += 1
-        if time.time() - t0 > seconds:
+        if time.time() - t0 > seconds or nf >= len(p.q):
             break
     tf = (time.time() - t0) / nf
     l1, l2 = p.zeros(), p.zeros()
@@ -118,7 +118,7 @@ def cpu_baseline(shot, m0_host, counts, seconds=8.0):
         p.image(g, u1, l0, l1, l2)
         l2, l1 = l1, l0
         na += 1
-        if time.time() - t0 > seconds:
+        if time.time() - t0 > seconds or na >= shot.nt:
             break
     ta = (time.time() - t0) / na
     del u, u1, u2, l0, l1, l2, g, p

@@ -1139,6 +1139,56 @@ struct BatchExec {
     char *dev_base;            // device tables the launches read
     bool upload;               // copy each table before its launch (eager runs)
     std::vector<StepParams> ps;
+    // codec stream and buffer ordering as in Exec; the shots move in lock
+    // step, so working buffer i (W0 or W1) has the same role in every shot
+    hipStream_t cs = nullptr;
+    hipEvent_t wmain[2] = {nullptr, nullptr}, wcodec[2] = {nullptr, nullptr};
+    int wslot(const float *p) const { return ex[0].wslot(p); }
+    hipStream_t cst() const { return cs ? cs : st; }
+    void main_wait(int i)
+    {
+        if (cs && i >= 0 && wcodec[i]) {
+            HIPCHK(hipStreamWaitEvent(st, wcodec[i], 0));
+            wcodec[i] = nullptr;
+        }
+    }
+    void main_used(int a, int b = -1, int o = -1)
+    {
+        if (!cs) return;
+        hipEvent_t e = c->sev();
+        HIPCHK(hipEventRecord(e, st));
+        for (int i : {a, b, o})
+            if (i >= 0) wmain[i] = e;
+    }
+    void codec_wait(int i)
+    {
+        if (cs && i >= 0 && wmain[i]) HIPCHK(hipStreamWaitEvent(cs, wmain[i], 0));
+    }
+    void codec_used(int i)
+    {
+        if (!cs || i < 0) return;
+        hipEvent_t e = c->sev();
+        HIPCHK(hipEventRecord(e, cs));
+        wcodec[i] = e;
+    }
+    void fork()
+    {
+        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = nullptr;
+        cs = (ex[0].compress && c->overlap) ? c->codec_stream() : nullptr;
+        if (!cs) return;
+        hipEvent_t e = c->sev();
+        HIPCHK(hipEventRecord(e, st));
+        HIPCHK(hipStreamWaitEvent(cs, e, 0));
+    }
+    void join()
+    {
+        if (!cs) return;
+        hipEvent_t e = c->sev();
+        HIPCHK(hipEventRecord(e, cs));
+        HIPCHK(hipStreamWaitEvent(st, e, 0));
+        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = nullptr;
+        cs = nullptr;
+    }
 
     void launch(bool adj)
     {
@@ -1166,7 +1216,12 @@ struct BatchExec {
         ps.resize(ex.size());
         for (int k = a + 1; k <= b; ++k) {
             for (size_t i = 0; i < ex.size(); ++i) ps[i] = ex[i].fwd_params(k, true);
+            const int u1 = wslot(ps[0].u1), u2 = wslot(ps[0].u2), o = wslot(ps[0].out);
+            main_wait(u1);
+            main_wait(u2);
+            main_wait(o);
             launch(false);
+            main_used(u1, u2, o);
             for (size_t i = 0; i < ex.size(); ++i) ex[i].fwd_commit(ps[i]);
         }
         for (auto &e : ex) e.work = b;
@@ -1177,12 +1232,15 @@ struct BatchExec {
     {
         for (auto &e : ex) e.pre_reverse(k);
         ps.resize(ex.size());
+        const int uk = wslot(ex[0].cur);
+        main_wait(uk);
         {
             Timer tm(c, st, K_ADJ);
             for (size_t i = 0; i < ex.size(); ++i) ps[i] = ex[i].adj_params();
             launch(true);
         }
         for (auto &e : ex) e.post_reverse(k);
+        main_used(uk);
     }
 
     // compressed checkpoints: one encode pipeline (decode launch) per level
@@ -1197,10 +1255,15 @@ struct BatchExec {
         const int n = (int)ex.size();
         std::vector<EncodeArgs> args(n);
         for (int lev = 0; lev < (both ? 2 : 1); ++lev) {
-            Timer tm(c, st, K_ENC);
-            for (int i = 0; i < n; ++i) args[i] = ex[i].encode_args(slot, lev);
-            const size_t off = c->btab.take((size_t)n * codec_job_bytes(true));
-            codec_encode_batch(args.data(), n, c->btab.host + off, dev_base + off, upload, st);
+            const int src = wslot(lev == 0 ? ex[0].cur : ex[0].prev);
+            codec_wait(src);
+            {
+                Timer tm(c, cst(), K_ENC);
+                for (int i = 0; i < n; ++i) args[i] = ex[i].encode_args(slot, lev);
+                const size_t off = c->btab.take((size_t)n * codec_job_bytes(true));
+                codec_encode_batch(args.data(), n, c->btab.host + off, dev_base + off, upload, cst());
+            }
+            codec_used(src);
             c->stats.n_encode += n;
         }
     }
@@ -1208,25 +1271,39 @@ struct BatchExec {
     void restore(int slot, int k, bool only_cur)
     {
         if (slot < 0 || !ex[0].compress) {
+            if (slot < 0) {
+                main_wait(0);
+                main_wait(1);
+            }
             for (auto &e : ex) e.restore(slot, k, only_cur);
+            if (slot < 0) main_used(0, 1);
             return;
         }
         const int n = (int)ex.size();
         std::vector<DecodeArgs> args(n);
+        // u^k alone goes to the working buffer the current state is not in
+        const int t0 = only_cur && wslot(ex[0].cur) == 0 ? 1 : 0;
+        auto wbuf = [&](int i, int w) { return w == 0 ? ex[i].W0() : ex[i].W1(); };
         for (int lev = 0; lev < (only_cur ? 1 : 2); ++lev) {
-            Timer tm(c, st, K_DEC);
-            for (int i = 0; i < n; ++i) args[i] = ex[i].decode_args(slot, lev);
-            const size_t off = c->btab.take((size_t)n * codec_job_bytes(false));
-            codec_decode_batch(args.data(), n, c->btab.host + off, dev_base + off, upload, st);
+            const int t = lev == 0 ? t0 : 1 - t0;
+            codec_wait(t);
+            {
+                Timer tm(c, cst(), K_DEC);
+                for (int i = 0; i < n; ++i) args[i] = ex[i].decode_args(slot, lev, wbuf(i, t));
+                const size_t off = c->btab.take((size_t)n * codec_job_bytes(false));
+                codec_decode_batch(args.data(), n, c->btab.host + off, dev_base + off, upload, cst());
+            }
+            codec_used(t);
             c->stats.n_decode += n;
         }
-        for (auto &e : ex) e.restore_commit(k, only_cur);
+        for (int i = 0; i < n; ++i) ex[i].restore_commit(k, only_cur, wbuf(i, t0));
     }
 
     // run acts[from, end); stops before the first REVERSE if stop_at_reverse
     size_t run(const std::vector<fwi_action> &acts, const std::vector<char> &both, size_t from = 0,
                bool stop_at_reverse = false)
     {
+        fork();
         size_t i = from;
         for (; i < acts.size(); ++i) {
             const fwi_action &a = acts[i];
@@ -1240,6 +1317,7 @@ struct BatchExec {
             }
             case FWI_REVERSE:
                 if (stop_at_reverse) {
+                    join();
                     for (auto &e : ex) e.flush_record();
                     return i;
                 }
@@ -1249,6 +1327,7 @@ struct BatchExec {
             default: throw Error{FWI_EINVAL, "internal: bad action"};
             }
         }
+        join();
         return i;
     }
 };

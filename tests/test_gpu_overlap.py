@@ -85,3 +85,32 @@ def test_overlap_tape_form():
     g1 = c.backward(tape1, d1 - d_obs)
     assert torch.equal(d1, d0) and torch.equal(g1, g0)
     c.close()
+
+
+@pytest.mark.parametrize("nslots", [40, 6])
+def test_overlap_batched_equals_single_stream(nslots):
+    c = F.Context(0, pool_bytes=1 << 29)
+    probs = [problem(3, n, 8, nt=40, seed=s) for n, s in ((16, 1), (23, 2), (19, 3))]
+    shots = [p[0] for p in probs]
+    m0s = [p[1] for p in probs]
+    q = probs[0][3]
+    dobs = [c.forward(s, mt, q) for s, _, mt, _ in probs]
+    c.set_overlap(False)
+    phis0, g0 = c.gradient_batch(shots, m0s, q, dobs, nslots=nslots, compress=True, atol=1e-4)
+    d0, tape0 = c.forward_ckpt_batch(shots, m0s, q, nslots=nslots, compress=True, atol=1e-4)
+    gt0 = c.backward_batch(tape0, [a - b for a, b in zip(d0, dobs)])
+    c.set_overlap(True)
+    for graphs in (False, True, True):
+        c.set_graphs(graphs)
+        phis, g = c.gradient_batch(shots, m0s, q, dobs, nslots=nslots, compress=True, atol=1e-4)
+        assert phis == phis0
+        for a, b in zip(g, g0):
+            assert torch.equal(a, b)
+    c.set_graphs(False)
+    d1, tape1 = c.forward_ckpt_batch(shots, m0s, q, nslots=nslots, compress=True, atol=1e-4)
+    gt1 = c.backward_batch(tape1, [a - b for a, b in zip(d1, dobs)])
+    for a, b in zip(d1, d0):
+        assert torch.equal(a, b)
+    for a, b in zip(gt1, gt0):
+        assert torch.equal(a, b)
+    c.close()
