@@ -27,7 +27,6 @@
 // consecutive threads assemble consecutive words).  Interior blocks of
 // 16-byte-aligned fields are read and written one 16-byte row at a time.
 #include <cstring>
-#include <type_traits>
 
 #include "internal.hpp"
 
@@ -173,10 +172,6 @@ __host__ __device__ __forceinline__ long scratch_word(long c, long w, long chunk
     return (c >> 6) * 64 * chunk_words + w * 64 + (c & 63);
 }
 
-// one bit plane of a block: 64 coefficients in 3D, 16 in 2D
-template <int D>
-using PlaneWord = typename std::conditional<D == 3, unsigned long long, uint32_t>::type;
-
 struct BitWriter {
     unsigned long long acc;
     int fill;
@@ -310,7 +305,6 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
     const long chunk_words = k.chunk_words;
     unsigned long long *chunk_bits = k.chunk_bits;
     unsigned int *flags = k.flags;
-    __shared__ PlaneWord<D> planes[32][64];     // bit plane p of lane l
     const long c = blk * 64 + threadIdx.x;
     if (c >= nchunks) return;
     const long nb[3] = {nb0, nb1, nb2};
@@ -415,13 +409,11 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
         bw.put(1u, 1);
         bw.put((uint32_t)(emax + 127), 8);
         bw.put((uint32_t)zs, 3);
-        // planes staged in LDS so the coding loop below stays rolled (small code)
-#pragma unroll
-        for (int p = 0; p < 32; ++p)
-            planes[p][threadIdx.x] = (PlaneWord<D>)(((unsigned long long)hi[p] << 32) | lo[p]);
         int n = 0;
-        for (int p = S; p >= P; --p) {
-            const unsigned long long xp = (unsigned long long)planes[p][threadIdx.x];
+#pragma unroll
+        for (int p = 31; p >= 0; --p) {
+            if (p > S || p < P) continue;
+            const unsigned long long xp = ((unsigned long long)hi[p] << 32) | lo[p];
             bw.put64(xp & lowmask64(n), n);
             if (n < SZ) {
                 const unsigned long long xr = xp >> n;
@@ -678,7 +670,6 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
     const long nsuper = k.nsuper, table_bytes = k.table_bytes;
     unsigned int *flags = k.flags;
     const int vec = k.vec;
-    __shared__ PlaneWord<D> planes[32][64];     // bit plane p of lane l
     const long c = blk * 64 + threadIdx.x;
     if (c >= nchunks) return;
     const unsigned char *s = stream;
@@ -714,33 +705,30 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
             const int S = GC::TP - zs;
             int P = minexp - emax + QB - GC::G;
             P = P < 0 ? 0 : P;
-            // coded planes S..P, one loop iteration each, staged in LDS
-            // (a rolled loop keeps the kernel's code small)
+            uint32_t lo[32], hi[32];
             int n = 0;
             bool bad = false;
-            for (int p = S; p >= P; --p) {
+#pragma unroll
+            for (int p = 31; p >= 0; --p) {
+                lo[p] = 0u;
+                hi[p] = 0u;
+                if (p > S || p < P || bad) continue;
                 unsigned long long xp = br.get64(n);
                 if (n < SZ && br.get(1)) {
                     const uint32_t pk = br.peek32();
                     const int L = pk ? __ffs((int)pk) - 1 : 32;
-                    if (L > 6) { bad = true; break; }
+                    if (L > 6) { bad = true; continue; }
                     br.skip(L + 1);
                     const int t = (int)(((1u << L) | br.get(L)) - 1u);
-                    if (t > SZ - 1 - n) { bad = true; break; }
+                    if (t > SZ - 1 - n) { bad = true; continue; }
                     const unsigned long long raw = br.get64(t);
                     xp |= ((1ull << t) | raw) << n;
                     n += t + 1;
                 }
-                planes[p][threadIdx.x] = (PlaneWord<D>)xp;
+                lo[p] = (uint32_t)xp;
+                hi[p] = (uint32_t)(xp >> 32);
             }
             if (bad || br.pos > pbits) { atomicOr(flags, 4u); return; }
-            uint32_t lo[32], hi[32];
-#pragma unroll
-            for (int p = 0; p < 32; ++p) {
-                const unsigned long long v = (p <= S && p >= P) ? (unsigned long long)planes[p][threadIdx.x] : 0ull;
-                lo[p] = (uint32_t)v;
-                hi[p] = (uint32_t)(v >> 32);
-            }
             transpose32(lo);
             if (D == 3) transpose32(hi);
 #pragma unroll
