@@ -204,6 +204,7 @@ struct BitReader {
     long nw;
     long idx;                       // word index of lo
     unsigned long long lo, hi;
+    unsigned long long nx;          // word idx + 2, loaded ahead of its use
     unsigned long long pos;         // absolute bit position
     __device__ __forceinline__ unsigned long long ld(long i) const { return i < nw && i >= 0 ? w[i] : 0ull; }
     __device__ __forceinline__ void seek(unsigned long long p)
@@ -212,6 +213,7 @@ struct BitReader {
         idx = (long)(p >> 6);
         lo = ld(idx);
         hi = ld(idx + 1);
+        nx = ld(idx + 2);
     }
     __device__ __forceinline__ uint32_t peek32() const
     {
@@ -226,11 +228,12 @@ struct BitReader {
         if (ni != idx) {
             if (ni == idx + 1) {
                 lo = hi;
-                hi = ld(ni + 1);
+                hi = nx;
             } else {
                 lo = ld(ni);
                 hi = ld(ni + 1);
             }
+            nx = ld(ni + 2);
             idx = ni;
         }
     }
@@ -310,6 +313,27 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
     const long nb[3] = {nb0, nb1, nb2};
     BitWriter bw{0ull, 0, scratch + scratch_word(c, 0, chunk_words), 0};
     bool nonfinite = false;
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    // padded fields: the rows of the next block are loaded while the current
+    // one is coded
+    f4v pf[SZ / 4];
+    auto load_rows = [&](long bb) {
+        long qx, qy, qz;
+        block_coords(bb, nb, qx, qy, qz);
+#pragma unroll
+        for (int r = 0; r < SZ / 4; ++r) {
+            const int ix = D == 3 ? (r >> 2) : r;
+            const int iy = D == 3 ? (r & 3) : 0;
+            long x = 4 * qx + ix, y = 4 * qy + iy;
+            x = x < f.n[0] ? x : f.n[0] - 1;
+            y = y < f.n[1] ? y : f.n[1] - 1;
+            pf[r] = __builtin_nontemporal_load((const f4v *)(src + x * f.sx + y * f.sy + 4 * qz));
+        }
+    };
+    if (vec == 2) {
+        const long b0 = chunk_block(c, 0, kblk, nblocks);
+        if (b0 >= 0) load_rows(b0);
+    }
     for (int j = 0; j < kblk; ++j) {
         const long b = chunk_block(c, j, kblk, nblocks);
         if (b < 0) break;
@@ -321,16 +345,15 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
             // padded field: one 16-byte load per row for every block; rows
             // past the end repeat the last row, and the z tail repeats the
             // last valid sample (the extra values read are padding)
-            typedef float f4v __attribute__((ext_vector_type(4)));
             const long zl = f.n[2] - 1 - 4 * bz;             // last valid z in the block (>= 0)
+            f4v cur[SZ / 4];
+#pragma unroll
+            for (int r = 0; r < SZ / 4; ++r) cur[r] = pf[r];
+            const long bn = j + 1 < kblk ? chunk_block(c, j + 1, kblk, nblocks) : -1;
+            if (bn >= 0) load_rows(bn);
 #pragma unroll
             for (int r = 0; r < SZ / 4; ++r) {
-                const int ix = D == 3 ? (r >> 2) : r;
-                const int iy = D == 3 ? (r & 3) : 0;
-                long x = 4 * bx + ix, y = 4 * by + iy;
-                x = x < f.n[0] ? x : f.n[0] - 1;
-                y = y < f.n[1] ? y : f.n[1] - 1;
-                const f4v v = __builtin_nontemporal_load((const f4v *)(src + x * f.sx + y * f.sy + 4 * bz));
+                const f4v v = cur[r];
                 const float e1 = zl >= 1 ? v.y : v.x;
                 const float e2 = zl >= 2 ? v.z : e1;
                 const float e3 = zl >= 3 ? v.w : e2;
