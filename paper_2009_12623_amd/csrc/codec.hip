@@ -764,13 +764,10 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
         // int32 -> float32 (round to nearest even), scaled by 2^(emax - Q)
         // through the exponent field; below 2^-126 -> +0, overflow saturates
         auto val = [&](int li) {
-            const int iv = ci[li];
-            uint32_t bits = __float_as_uint((float)iv);
-            const int E = (int)((bits >> 23) & 0xFFu) + emax - QB;
-            if (iv == 0 || E <= 0) bits = 0u;
-            else if (E >= 255) bits = (bits & 0x80000000u) | 0x7F7FFFFFu;
-            else bits = (bits & ~(0xFFu << 23)) | ((uint32_t)E << 23);
-            return __uint_as_float(bits);
+            const float r = ldexpf((float)ci[li], emax - QB);
+            const float a = fabsf(r);
+            float o = a < 1.17549435e-38f ? 0.0f : r;
+            return a > 3.40282347e38f ? copysignf(3.40282347e38f, r) : o;
         };
         long bx, by, bz;
         block_coords(b, nb, bx, by, bz);

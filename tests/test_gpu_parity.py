@@ -211,9 +211,12 @@ def codec_fields():
     x = (rng.standard_normal((33, 65)) * 2.0 ** rng.integers(-20, 6, (33, 65))).astype(np.float32)
     x[0, :5] = np.float32(1e-42)         # subnormals count as zero
     yield x
+    # tiny magnitudes: at the smallest atol reconstructions below 2^-126
+    # flush to +0
+    yield (rng.standard_normal((12, 9, 11)) * 1e-37).astype(np.float32)
 
 
-@pytest.mark.parametrize("atol", [1e-1, 1e-3, 1e-4, 1e-6, 2.0 ** -70])
+@pytest.mark.parametrize("atol", [1e-1, 1e-3, 1e-4, 1e-6, 2.0 ** -70, 2.0 ** -140])
 def test_codec_streams_bit_exact(ctx, atol):
     for x in codec_fields():
         ref = ocodec.compress(x, atol)
@@ -222,6 +225,21 @@ def test_codec_streams_bit_exact(ctx, atol):
         y = ctx.decompress(dev(np.frombuffer(ref, np.uint8).copy()), x.shape).cpu().numpy()
         yref = ocodec.decompress(ref, x.shape)
         assert np.array_equal(y.view(np.uint32), yref.view(np.uint32))
+
+
+def test_codec_saturation_bit_exact(ctx):
+    """values at the top of float32 whose reconstructions exceed the largest
+    float (they saturate to it): the oracle's stream and decode, bit for bit"""
+    rng = np.random.default_rng(22)
+    x = (rng.uniform(3.4e38, 3.4028234e38, (10, 13)) * rng.choice([-1.0, 1.0], (10, 13))).astype(np.float32)
+    for atol in (1e36, 1e-1):
+        ref = ocodec.compress(x, atol)
+        assert ctx.compress(dev(x), atol).cpu().numpy().tobytes() == ref
+        y = ctx.decompress(dev(np.frombuffer(ref, np.uint8).copy()), x.shape).cpu().numpy()
+        yref = ocodec.decompress(ref, x.shape)
+        assert np.array_equal(y.view(np.uint32), yref.view(np.uint32))
+        if atol == 1e36:
+            assert np.sum(np.abs(yref) == np.float32(3.4028235e38)) > 0    # the case is exercised
 
 
 @pytest.mark.parametrize("shape,kblk", [((100, 100, 100), 1), ((200, 200, 200), 4),
