@@ -159,6 +159,24 @@ def wavefield_like(shape, seed=12624, nshell=6, f_pts=8.0, noise=0.0):
 
 
 # ------------------------------------------------- 3D thrust-faulted layers
+def separable_field(shape, seed=12629, nterm=3):
+    """Cheap large stand-in for a wavefield snapshot: a sum of ``nterm``
+    separable products of seeded 1D wave packets (Gaussian-windowed cosines),
+    values O(1).  float32; memory and time linear in the number of points."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros(shape, np.float32)
+    for _ in range(nterm):
+        prod = None
+        for n in shape:
+            t = np.arange(n, dtype=np.float64)
+            c, w = rng.uniform(0.2, 0.8) * n, rng.uniform(0.1, 0.3) * n
+            k = rng.uniform(0.1, 0.6)
+            prof = (np.cos(k * (t - c)) * np.exp(-((t - c) / w) ** 2)).astype(np.float32)
+            prod = prof if prod is None else np.multiply.outer(prod, prof)
+        out += np.float32(rng.uniform(0.3, 1.0)) * prod
+    return out
+
+
 def _thrust_params(shape, nlayer, seed, fold_pts, fault_pts):
     """Seeded fault planes and folded interface surfaces (2D arrays)."""
     nx, ny, nz = shape
