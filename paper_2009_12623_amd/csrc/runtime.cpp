@@ -2328,9 +2328,15 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
             HIPCHK(hipEventElapsedTime(&ms, e0, e1));
             return (double)ms / steps;
         };
+        // the timed fields hold data (copies of the coefficient field), not
+        // zeros: all-zero traffic ran measurably faster and ranked the
+        // shapes differently from a real sweep
         auto reset = [&] {
             HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, arena_bytes, st));
             ex.init_fields();
+            const size_t ne = c->sb.padded_elems;
+            for (float *f : {c->sb.fa.p, c->sb.fb.p, c->sb.la.p, c->sb.lb.p, c->sb.gacc.p})
+                launch_copy(f, c->sb.coef.p, ne, st);
         };
         reset();
         // screen every candidate, then re-time the best few of each sweep
