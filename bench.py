@@ -10,8 +10,11 @@ thrust-faulted layered model (2.2-6.0 km/s, smoothed for the gradient).
 
 Checkpoint slots for the compressed run are chosen under the HBM budget of
 uncompressed Revolve with 40 slots, by a cost model fed with the kernel
-times of a pilot run.  Prints one JSON line (see README of the metric in
-the design doc).  Inputs are generated on the device before timing starts.
+times of a pilot run; the checkpoint codec runs on a second stream beside
+the stencil.  Prints one JSON line: seconds per shot, the uncompressed
+Revolve time beside it, the roofline of the dominant kernel and the FP64
+oracle timed on the host.  Inputs are generated on the device before timing
+starts.
 """
 from __future__ import annotations
 
@@ -609,7 +612,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path shards by shot with one gradient "
-              "all-reduce, which this build does not run (use --gpus 1)", file=sys.stderr)
+              "all-reduce across GPUs, which is not implemented here (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch
