@@ -568,7 +568,9 @@ struct Exec {
     // the other stream's next use (encode of u^k runs beside the next
     // forward step, decode of the next u^k beside the current adjoint step).
     hipStream_t cs = nullptr;
-    hipEvent_t wmain[2] = {nullptr, nullptr}, wcodec[2] = {nullptr, nullptr};
+    // per working buffer: event after the main stream's last use, after the
+    // codec's last use, and after the codec's last write (decode) into it
+    hipEvent_t wmain[2] = {nullptr, nullptr}, wcodec[2] = {nullptr, nullptr}, wdec[2] = {nullptr, nullptr};
 
     // cur/prev/l1/l2 are allocation bases of padded arrays
     float *at_origin(float *base) const { return base + S.pad.origin; }
@@ -578,13 +580,17 @@ struct Exec {
 
     int wslot(const float *p) const { return p == W0() ? 0 : p == W1() ? 1 : -1; }
     hipStream_t cst() const { return cs ? cs : st; }
-    // main stream: wait for the codec's last use of buffer p
-    void main_wait(const float *p)
+    // main stream, before it reads (writes = false) or writes buffer p: a
+    // read waits for the codec's last write into p, a write for its last use
+    void main_wait(const float *p, bool writes)
     {
         const int i = wslot(p);
-        if (cs && i >= 0 && wcodec[i]) {
-            HIPCHK(hipStreamWaitEvent(st, wcodec[i], 0));
-            wcodec[i] = nullptr;
+        if (!cs || i < 0) return;
+        hipEvent_t &e = writes ? wcodec[i] : wdec[i];
+        if (e) {
+            HIPCHK(hipStreamWaitEvent(st, e, 0));
+            if (writes) wdec[i] = nullptr;
+            e = nullptr;
         }
     }
     // main stream has just used the given buffers
@@ -604,18 +610,19 @@ struct Exec {
         const int i = wslot(p);
         if (cs && i >= 0 && wmain[i]) HIPCHK(hipStreamWaitEvent(cs, wmain[i], 0));
     }
-    void codec_used(const float *p)
+    void codec_used(const float *p, bool wrote)
     {
         const int i = wslot(p);
         if (!cs || i < 0) return;
         hipEvent_t e = c->sev();
         HIPCHK(hipEventRecord(e, cs));
         wcodec[i] = e;
+        if (wrote) wdec[i] = e;
     }
     // start of a run: the codec stream follows everything issued so far
     void fork()
     {
-        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = nullptr;
+        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = wdec[0] = wdec[1] = nullptr;
         cs = (compress && c->overlap) ? c->codec_stream() : nullptr;
         if (!cs) return;
         hipEvent_t e = c->sev();
@@ -629,7 +636,7 @@ struct Exec {
         hipEvent_t e = c->sev();
         HIPCHK(hipEventRecord(e, cs));
         HIPCHK(hipStreamWaitEvent(st, e, 0));
-        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = nullptr;
+        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = wdec[0] = wdec[1] = nullptr;
         cs = nullptr;
     }
 
@@ -750,9 +757,9 @@ struct Exec {
         Timer tm(c, st, K_FWD);
         for (int k = a + 1; k <= b; ++k) {
             const StepParams p = fwd_params(k, record);
-            main_wait(p.u1);
-            main_wait(p.u2);
-            main_wait(p.out);
+            main_wait(p.u1, false);
+            main_wait(p.u2, false);
+            main_wait(p.out, true);
             launch_step(p, S.ndim, S.R, false, st);
             main_used(p.u1, p.u2, p.out);
             fwd_commit(p);
@@ -823,7 +830,7 @@ struct Exec {
                 Timer tm(c, cst(), K_ENC);
                 codec_encode(encode_args(slot, lev), cst());
             }
-            codec_used(src);
+            codec_used(src, false);
             c->stats.n_encode += 1;
         }
     }
@@ -854,8 +861,8 @@ struct Exec {
     void restore(int slot, int k, bool only_cur)
     {
         if (slot < 0) {
-            main_wait(W0());
-            main_wait(W1());
+            main_wait(W0(), true);
+            main_wait(W1(), true);
             launch_fill_zero(B->fa.p, B->padded_elems, st);
             launch_fill_zero(B->fb.p, B->padded_elems, st);
             main_used(W0(), W1());
@@ -878,7 +885,7 @@ struct Exec {
                     Timer tm(c, cst(), K_DEC);
                     codec_decode(decode_args(slot, lev, t), cst());
                 }
-                codec_used(t);
+                codec_used(t, true);
                 c->stats.n_decode += 1;
             }
             restore_commit(k, only_cur, t0);
@@ -940,7 +947,7 @@ struct Exec {
     void reverse(int k)
     {
         pre_reverse(k);
-        main_wait(cur);
+        main_wait(cur, false);
         {
             Timer tm(c, st, K_ADJ);
             launch_step(adj_params(), S.ndim, S.R, true, st);
@@ -1142,14 +1149,17 @@ struct BatchExec {
     // codec stream and buffer ordering as in Exec; the shots move in lock
     // step, so working buffer i (W0 or W1) has the same role in every shot
     hipStream_t cs = nullptr;
-    hipEvent_t wmain[2] = {nullptr, nullptr}, wcodec[2] = {nullptr, nullptr};
+    hipEvent_t wmain[2] = {nullptr, nullptr}, wcodec[2] = {nullptr, nullptr}, wdec[2] = {nullptr, nullptr};
     int wslot(const float *p) const { return ex[0].wslot(p); }
     hipStream_t cst() const { return cs ? cs : st; }
-    void main_wait(int i)
+    void main_wait(int i, bool writes)
     {
-        if (cs && i >= 0 && wcodec[i]) {
-            HIPCHK(hipStreamWaitEvent(st, wcodec[i], 0));
-            wcodec[i] = nullptr;
+        if (!cs || i < 0) return;
+        hipEvent_t &e = writes ? wcodec[i] : wdec[i];
+        if (e) {
+            HIPCHK(hipStreamWaitEvent(st, e, 0));
+            if (writes) wdec[i] = nullptr;
+            e = nullptr;
         }
     }
     void main_used(int a, int b = -1, int o = -1)
@@ -1164,16 +1174,17 @@ struct BatchExec {
     {
         if (cs && i >= 0 && wmain[i]) HIPCHK(hipStreamWaitEvent(cs, wmain[i], 0));
     }
-    void codec_used(int i)
+    void codec_used(int i, bool wrote)
     {
         if (!cs || i < 0) return;
         hipEvent_t e = c->sev();
         HIPCHK(hipEventRecord(e, cs));
         wcodec[i] = e;
+        if (wrote) wdec[i] = e;
     }
     void fork()
     {
-        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = nullptr;
+        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = wdec[0] = wdec[1] = nullptr;
         cs = (ex[0].compress && c->overlap) ? c->codec_stream() : nullptr;
         if (!cs) return;
         hipEvent_t e = c->sev();
@@ -1186,7 +1197,7 @@ struct BatchExec {
         hipEvent_t e = c->sev();
         HIPCHK(hipEventRecord(e, cs));
         HIPCHK(hipStreamWaitEvent(st, e, 0));
-        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = nullptr;
+        wmain[0] = wmain[1] = wcodec[0] = wcodec[1] = wdec[0] = wdec[1] = nullptr;
         cs = nullptr;
     }
 
@@ -1217,9 +1228,9 @@ struct BatchExec {
         for (int k = a + 1; k <= b; ++k) {
             for (size_t i = 0; i < ex.size(); ++i) ps[i] = ex[i].fwd_params(k, true);
             const int u1 = wslot(ps[0].u1), u2 = wslot(ps[0].u2), o = wslot(ps[0].out);
-            main_wait(u1);
-            main_wait(u2);
-            main_wait(o);
+            main_wait(u1, false);
+            main_wait(u2, false);
+            main_wait(o, true);
             launch(false);
             main_used(u1, u2, o);
             for (size_t i = 0; i < ex.size(); ++i) ex[i].fwd_commit(ps[i]);
@@ -1233,7 +1244,7 @@ struct BatchExec {
         for (auto &e : ex) e.pre_reverse(k);
         ps.resize(ex.size());
         const int uk = wslot(ex[0].cur);
-        main_wait(uk);
+        main_wait(uk, false);
         {
             Timer tm(c, st, K_ADJ);
             for (size_t i = 0; i < ex.size(); ++i) ps[i] = ex[i].adj_params();
@@ -1263,7 +1274,7 @@ struct BatchExec {
                 const size_t off = c->btab.take((size_t)n * codec_job_bytes(true));
                 codec_encode_batch(args.data(), n, c->btab.host + off, dev_base + off, upload, cst());
             }
-            codec_used(src);
+            codec_used(src, false);
             c->stats.n_encode += n;
         }
     }
@@ -1272,8 +1283,8 @@ struct BatchExec {
     {
         if (slot < 0 || !ex[0].compress) {
             if (slot < 0) {
-                main_wait(0);
-                main_wait(1);
+                main_wait(0, true);
+                main_wait(1, true);
             }
             for (auto &e : ex) e.restore(slot, k, only_cur);
             if (slot < 0) main_used(0, 1);
@@ -1293,7 +1304,7 @@ struct BatchExec {
                 const size_t off = c->btab.take((size_t)n * codec_job_bytes(false));
                 codec_decode_batch(args.data(), n, c->btab.host + off, dev_base + off, upload, cst());
             }
-            codec_used(t);
+            codec_used(t, true);
             c->stats.n_decode += n;
         }
         for (int i = 0; i < n; ++i) ex[i].restore_commit(k, only_cur, wbuf(i, t0));
