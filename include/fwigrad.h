@@ -287,7 +287,10 @@ int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
  * m [device], with the buffer roles alternating as in a sweep, and keeps
  * the fastest forward and adjoint shapes for later calls on a grid of the
  * same dims and order.  Every candidate is timed once; the best four of each
- * sweep are timed three more times, interleaved, and the best mean wins.
+ * sweep are timed three more times, interleaved; of those within 3 % of the
+ * best mean, a shape with one plane of loads in flight and round-robin order
+ * is preferred, then the most x planes per workgroup (fewest halo re-reads),
+ * since in a sweep the checkpoint codec shares the memory system.
  * Results [host].  Synchronises the stream; the context's
  * working fields are cleared (tapes keep their own state). */
 typedef struct {

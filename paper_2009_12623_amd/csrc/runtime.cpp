@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <tuple>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -2369,8 +2370,24 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
             }
         std::sort(rf.begin(), rf.end());
         std::sort(ra.begin(), ra.end());
-        const double bf = rf[0].first / 4, ba = ra[0].first / 4;
-        const fwi_ctx::Shape sf = cands[rf[0].second], sa = cands[ra[0].second];
+        // among shapes within 3 % of the fastest, prefer one plane of loads
+        // in flight and round-robin order (fewer registers and less traffic
+        // in flight), then the longest x chunk (fewest halo planes re-read):
+        // that pays when the codec shares the memory system with the step
+        // (the sweeps run it beside them)
+        auto pick = [&](const std::vector<std::pair<double, size_t>> &r) {
+            auto key = [&](size_t j) {
+                const fwi_ctx::Shape &h = cands[r[j].second];
+                return std::make_tuple(h.deep == 0, h.remap == 0, h.xchunk);
+            };
+            size_t k = 0;
+            for (size_t j = 1; j < r.size(); ++j)
+                if (r[j].first <= 1.03 * r[0].first && key(j) > key(k)) k = j;
+            return k;
+        };
+        const size_t kf = pick(rf), ka = pick(ra);
+        const double bf = rf[kf].first / 4, ba = ra[ka].first / 4;
+        const fwi_ctx::Shape sf = cands[rf[kf].second], sa = cands[ra[ka].second];
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         c->tuned[ex.grid_key()] = {sf, sa};
