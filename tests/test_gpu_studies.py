@@ -72,3 +72,20 @@ def test_stacking(ctx):
     rows = studies.stacking_error(ctx, shots, [m0] * 3, q, d, 1e-3, 5)
     assert [r["shots"] for r in rows] == [1, 2, 3]
     assert all(0 < r["rel_l2"] < 1e-1 for r in rows)
+
+
+def test_gradient_error_shape_in_atol(ctx):
+    """Sec. 4 "Gradient computation": the lossy gradient's error falls as
+    atol falls and flattens once the codec error is below the FP32 floor;
+    the compression factor falls with it"""
+    shot, m0, mt, q = problem(2, 48, 8, nt=120)
+    d = ctx.forward(shot, mt, q)
+    atols = [1e-1, 1e-3, 1e-5, 1e-7, 1e-9]
+    rows = studies.gradient_error_vs_atol(ctx, shot, m0, q, d, atols)
+    err = [r["rel_l2"] for r in rows]
+    cf = [r["cf"] for r in rows]
+    print("atol", atols, "rel_l2", err, "cf", cf)
+    assert all(b <= a * 1.5 for a, b in zip(err, err[1:]))       # no growth as atol falls
+    assert err[0] > 100 * err[-1]
+    assert err[-1] <= 2 * err[-2] and err[-2] <= 2 * err[-1] + 1e-12   # flat at the floor
+    assert all(b <= a for a, b in zip(cf, cf[1:]))
