@@ -779,7 +779,7 @@ def main():
             "stencil_shape": None if tune is None else {
                 "forward": [tune["fwd_xchunk"], tune["fwd_rows_per_lane"], tune["fwd_xcd_order"], tune["fwd_deep"]],
                 "adjoint": [tune["adj_xchunk"], tune["adj_rows_per_lane"], tune["adj_xcd_order"], tune["adj_deep"]],
-                "fields": ["x_planes_per_workgroup", "rows_per_lane", "xcd_contiguous", "planes_in_flight_2"]},
+                "fields": ["x_planes_per_workgroup", "rows_per_lane", "tile_order_0rr_1contig_2zcol", "planes_in_flight_2"]},
         },
         "roofline": roof,
         # the same kernels timed alone (autotune trials, no codec work beside

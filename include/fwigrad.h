@@ -283,19 +283,21 @@ int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
 /* Autotuner: times every candidate launch shape of the stencil kernels on
  * this grid (3D: x planes per workgroup in {8,16,32,64} x tile order
  * round-robin / XCD-contiguous x {2 rows per lane, 4 rows per lane, 2 rows
- * per lane with two planes of loads in flight}; 2D: x planes in {4..64}), `steps` forward and `steps` adjoint launches each on the model
+ * per lane with two planes of loads in flight}, plus 2 rows per lane with
+ * the z tiles of each column dealt to one XCD; 2D: x planes in {4..64}),
+ * `steps` forward and `steps` adjoint launches each on the model
  * m [device], with the buffer roles alternating as in a sweep, and keeps
  * the fastest forward and adjoint shapes for later calls on a grid of the
  * same dims and order.  Every candidate is timed once; the best four of each
  * sweep are timed three more times, interleaved; of those within 3 % of the
- * best mean, a shape with one plane of loads in flight and round-robin order
- * is preferred, then the most x planes per workgroup (fewest halo re-reads),
+ * best mean, a shape with one plane of loads in flight is preferred, then
+ * the z-column order, then round robin over the XCDs, then the most x planes per workgroup (fewest halo re-reads),
  * since in a sweep the checkpoint codec shares the memory system.
  * Results [host].  Synchronises the stream; the context's
  * working fields are cleared (tapes keep their own state). */
 typedef struct {
     int ncand;
-    int fwd_xchunk, fwd_rows_per_lane, fwd_xcd_order;
+    int fwd_xchunk, fwd_rows_per_lane, fwd_xcd_order;   /* order: 0 round robin, 1 XCD-contiguous, 2 z columns per XCD */
     int adj_xchunk, adj_rows_per_lane, adj_xcd_order;
     double fwd_ms, adj_ms;
     int fwd_deep, adj_deep;       /* two planes of loads in flight */

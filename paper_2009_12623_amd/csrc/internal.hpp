@@ -51,7 +51,7 @@ struct StepParams {
     int step;               // wavelet sample injected by this step
     int xchunk;             // x planes per workgroup
     int rpl;                // 3D: rows per lane (tile height 8 rpl), 2 or 4
-    int remap;              // 3D: XCD-contiguous tile order
+    int remap;              // 3D tile order: 0 round robin, 1 XCD-contiguous, 2 z columns per XCD
     int deep;               // 3D: two planes of loads in flight (2 rows per lane)
     // forward only: sample u1 at the receivers into grow (nullptr: skip)
     const int *rec_off;     // padded offsets from the allocation base

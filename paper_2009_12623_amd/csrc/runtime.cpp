@@ -206,7 +206,7 @@ struct fwi_ctx {
     // stencil launch shape; overridden per grid by fwi_autotune
     int xchunk3 = 0;           // 3D x planes per workgroup (0: default)
     int rpl3 = 2;              // 3D rows per lane
-    int remap3 = 0;            // 3D XCD-contiguous tile order
+    int remap3 = 0;            // 3D tile order: 0 round robin, 1 XCD-contiguous, 2 z columns per XCD
     int deep3 = 0;             // 3D two planes of loads in flight
     struct Shape {
         int xchunk, rpl, remap, deep;
@@ -1490,7 +1490,7 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         c->pool_default = pool_bytes;
         if (const char *e = std::getenv("FWI_XCHUNK")) c->xchunk3 = std::atoi(e);
         if (const char *e = std::getenv("FWI_RPL")) c->rpl3 = std::atoi(e) == 4 ? 4 : 2;
-        if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::atoi(e) != 0;
+        if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::max(0, std::min(std::atoi(e), 2));
         if (const char *e = std::getenv("FWI_DEEP")) c->deep3 = std::atoi(e) != 0;
         *ctx = c;
     });
@@ -2302,12 +2302,14 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         const int xcs3[] = {8, 16, 32, 64};
         const int xcs2[] = {4, 8, 16, 32, 64};
         if (ex.S.ndim == 3) {
-            for (int xc : xcs3)
+            for (int xc : xcs3) {
                 for (int remap : {0, 1}) {
                     cands.push_back({xc, 2, remap, 0});
                     cands.push_back({xc, 4, remap, 0});
                     cands.push_back({xc, 2, remap, 1});
                 }
+                cands.push_back({xc, 2, 2, 0});
+            }
         } else {
             for (int xc : xcs2) cands.push_back({xc, 2, 0, 0});
         }
@@ -2371,14 +2373,15 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         std::sort(rf.begin(), rf.end());
         std::sort(ra.begin(), ra.end());
         // among shapes within 3 % of the fastest, prefer one plane of loads
-        // in flight and round-robin order (fewer registers and less traffic
-        // in flight), then the longest x chunk (fewest halo planes re-read):
+        // in flight, the z-column order (z halos from L2), then round robin
+        // over the XCDs, then the longest x chunk (fewest halo planes
+        // re-read):
         // that pays when the codec shares the memory system with the step
         // (the sweeps run it beside them)
         auto pick = [&](const std::vector<std::pair<double, size_t>> &r) {
             auto key = [&](size_t j) {
                 const fwi_ctx::Shape &h = cands[r[j].second];
-                return std::make_tuple(h.deep == 0, h.remap == 0, h.xchunk);
+                return std::make_tuple(h.deep == 0, h.remap == 2, h.remap != 1, h.xchunk);
             };
             size_t k = 0;
             for (size_t j = 1; j < r.size(); ++j)

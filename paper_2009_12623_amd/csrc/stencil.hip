@@ -80,15 +80,23 @@ __device__ __forceinline__ void gather_block(const StepParams &p, int blk)
 // ------------------------------------------------------------------- 3D
 // Workgroup = 64 (z) x 8 (y) lanes; each lane owns RPL rows (ty + 8 j) of a
 // 64 x 8 RPL (z, y) tile.  Tiles are numbered z fastest, then y, then x
-// chunk; with `remap` they are handed out so that each XCD (workgroups are
-// dealt to the 8 XCDs round robin) works on one contiguous range, keeping
-// halo reuse inside its L2.  Read-once streams (u2, b, u^k, g) use
-// non-temporal loads.
-__device__ __forceinline__ void tile_coords(int hw, int nwg, int ntz, int nty, bool remap, int &tzi,
+// chunk.  Workgroups are dealt to the 8 XCDs round robin; `remap` 1 hands
+// out tiles so that each XCD works on one contiguous range, `remap` 2 so
+// that the z tiles of one (y, x chunk) column go to one XCD in a row (their
+// z halos are then read from that XCD's L2) while columns still go round
+// robin.  Read-once streams (u2, b, u^k, g) use non-temporal loads.
+__device__ __forceinline__ void tile_coords(int hw, int nwg, int ntz, int nty, int remap, int &tzi,
                                             int &tyi, int &txi, bool &valid)
 {
-    const int per = (nwg + 7) >> 3;
-    const int logical = remap ? (hw & 7) * per + (hw >> 3) : hw;
+    int logical = hw;
+    if (remap == 1) {
+        const int per = (nwg + 7) >> 3;
+        logical = (hw & 7) * per + (hw >> 3);
+    } else if (remap == 2) {
+        // a bijection of [0, launched) when launched is a multiple of 8 ntz
+        const int k = hw >> 3;
+        logical = ((k / ntz) * 8 + (hw & 7)) * ntz + k % ntz;
+    }
     valid = logical < nwg;
     tzi = logical % ntz;
     const int rest = logical / ntz;
@@ -108,7 +116,7 @@ __device__ __forceinline__ void step3d_body(const StepParams &p, int hw, int ntz
     }
     int tzi, tyi, txi;
     bool valid;
-    tile_coords(hw, nwg, ntz, nty, p.remap != 0, tzi, tyi, txi, valid);
+    tile_coords(hw, nwg, ntz, nty, p.remap, tzi, tyi, txi, valid);
     if (!valid) return;                            // whole workgroup, before any barrier
 
     const int tz = threadIdx.x;
@@ -262,7 +270,7 @@ __device__ __forceinline__ void step3d_body_deep(const StepParams &p, int hw, in
     }
     int tzi, tyi, txi;
     bool valid;
-    tile_coords(hw, nwg, ntz, nty, p.remap != 0, tzi, tyi, txi, valid);
+    tile_coords(hw, nwg, ntz, nty, p.remap, tzi, tyi, txi, valid);
     if (!valid) return;                            // whole workgroup, before any barrier
 
     const int tz = threadIdx.x;
@@ -720,7 +728,8 @@ int step_geometry(BatchEntry &e, int ndim, bool adjoint)
         e.ntz = (p.nz + TILE_Z - 1) / TILE_Z;
         e.nty = (p.ny + rows - 1) / rows;
         e.nwg = e.ntz * e.nty * nchunk;
-        e.launched = ((e.nwg + 7) / 8) * 8;
+        const int unit = p.remap == 2 ? 8 * e.ntz : 8;
+        e.launched = ((e.nwg + unit - 1) / unit) * unit;
         const int ng = gather ? (p.nrec + 511) / 512 : 0;
         return e.launched + ng;
     }
