@@ -288,8 +288,8 @@ int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
  * `steps` forward and `steps` adjoint launches each on the model
  * m [device], with the buffer roles alternating as in a sweep, and keeps
  * the fastest forward and adjoint shapes for later calls on a grid of the
- * same dims and order.  Every candidate is timed once; the best four of each
- * sweep are timed three more times, interleaved; of those within 3 % of the
+ * same dims and order.  Every candidate is timed once; the best eight of each
+ * sweep are timed three more times, interleaved; of those within 6 % of the
  * best mean, a shape with one plane of loads in flight is preferred, then
  * the z-column order, then round robin over the XCDs, then the most x planes per workgroup (fewest halo re-reads),
  * since in a sweep the checkpoint codec shares the memory system.

@@ -2353,8 +2353,8 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
                 launch_copy(f, c->sb.coef.p, ne, st);
         };
         reset();
-        // screen every candidate, then re-time the best few of each sweep
-        // three more times, interleaved, and keep the best mean
+        // screen every candidate, then re-time the best eight of each sweep
+        // three more times, interleaved
         std::vector<std::pair<double, size_t>> rf, ra;
         for (size_t i = 0; i < cands.size(); ++i) {
             rf.push_back({time_it(cands[i], false), i});
@@ -2362,7 +2362,7 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         }
         std::sort(rf.begin(), rf.end());
         std::sort(ra.begin(), ra.end());
-        const size_t top = std::min<size_t>(4, cands.size());
+        const size_t top = std::min<size_t>(8, cands.size());
         rf.resize(top);
         ra.resize(top);
         for (int round = 0; round < 3; ++round)
@@ -2372,7 +2372,7 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
             }
         std::sort(rf.begin(), rf.end());
         std::sort(ra.begin(), ra.end());
-        // among shapes within 3 % of the fastest, prefer one plane of loads
+        // among shapes within 6 % of the fastest, prefer one plane of loads
         // in flight, the z-column order (z halos from L2), then round robin
         // over the XCDs, then the longest x chunk (fewest halo planes
         // re-read):
@@ -2385,7 +2385,7 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
             };
             size_t k = 0;
             for (size_t j = 1; j < r.size(); ++j)
-                if (r[j].first <= 1.03 * r[0].first && key(j) > key(k)) k = j;
+                if (r[j].first <= 1.06 * r[0].first && key(j) > key(k)) k = j;
             return k;
         };
         const size_t kf = pick(rf), ka = pick(ra);
