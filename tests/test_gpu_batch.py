@@ -131,3 +131,27 @@ def test_batch_pool_overflow_is_reported(ctx):
     # the context stays usable
     phis, grads = ctx.gradient_batch([s for s, _, _ in shots], models, q, dobs, nslots=6)
     assert all(np.isfinite(phis))
+
+
+@pytest.mark.parametrize("xchunk,remap", [(16, 2), (7, 2), (8, 1)])
+def test_batch_tile_orders(xchunk, remap, monkeypatch):
+    """the batched kernel in every tile order (the tuner may pick any per
+    shot): each shot equals its single-shot gradient bit for bit and the
+    oracle's to 1e-4"""
+    monkeypatch.setenv("FWI_XCHUNK", str(xchunk))
+    monkeypatch.setenv("FWI_REMAP", str(remap))
+    c = F.Context(0, pool_bytes=1 << 28)
+    shots, q32 = cropped_shots(3, (14, 23, 19), 20, 8, nt=40, seed=5, amp=3.0)
+    q = dev(q32)
+    models = [dev(m0) for _, m0, _ in shots]
+    dobs = [c.forward(s, dev(mt), q) for s, _, mt in shots]
+    phis, grads = c.gradient_batch([s for s, _, _ in shots], models, q, dobs, nslots=4, compress=True, atol=1e-4)
+    for (s, _, _), m, d, phi, g in zip(shots, models, dobs, phis, grads):
+        phi1, g1 = c.gradient(s, m, q, d, nslots=4, compress=True, atol=1e-4)
+        assert torch.equal(g, g1) and phi == phi1
+    s, m0, mt = shots[1]
+    p0 = solver.Problem(s, m0.astype(np.float64), wavelet=q32.astype(np.float64))
+    _, gref, _ = solver.gradient(p0, np.zeros((s.nt, len(s.rec))))
+    _, ge = c.gradient_batch([t for t, _, _ in shots], models, q, [torch.zeros_like(d) for d in dobs], nslots=4)
+    assert metrics.rel_l2(ge[1].cpu().numpy(), gref) <= 1e-4
+    c.close()
