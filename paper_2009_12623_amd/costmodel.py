@@ -102,3 +102,19 @@ def choose_slots(plan, nt: int, units: UnitCosts, budget_bytes: float, margin: f
         if best is None or t < best[1]:
             best = (s, t)
     return best, table
+
+
+def choose_config(plan, nt: int, units_by_atol: dict, budget_bytes: float, margin: float = 1.3,
+                  candidates=CANDIDATES):
+    """(atol, slots, predicted ms) minimising the predicted time over the
+    tolerances the caller accepts (``units_by_atol``: atol -> UnitCosts,
+    e.g. from a pilot call per atol: the stream size and codec costs depend
+    on atol) and the slot counts that fit the budget; None if nothing fits.
+    The choice of an acceptable atol is the caller's (the error it causes is
+    not modelled)."""
+    best = None
+    for atol, units in sorted(units_by_atol.items()):
+        b, _ = choose_slots(plan, nt, units, budget_bytes, margin, candidates)
+        if b is not None and (best is None or b[1] < best[2]):
+            best = (atol, b[0], b[1])
+    return best

@@ -78,3 +78,18 @@ def test_unit_costs_from_stats():
               n_encode=3, ms_decode=0.0, n_decode=0, ckpt_bytes=300)
     u = C.UnitCosts.from_stats(st)
     assert (u.t_fwd, u.t_adj, u.t_enc, u.t_dec, u.field_bytes) == (2.0, 2.0, 1.0, 0.0, 100.0)
+
+
+def test_choose_config_trades_tolerance_against_slots():
+    nt = 400
+    plan = F.fwi_revolve_plan
+    tight = C.UnitCosts(t_fwd=1.0, t_adj=2.0, t_enc=0.5, t_dec=0.5, field_bytes=4000.0)
+    loose = C.UnitCosts(t_fwd=1.0, t_adj=2.0, t_enc=0.5, t_dec=0.5, field_bytes=1000.0)
+    budget = 130 * 1000.0 * 1.3
+    atol, s, ms = C.choose_config(plan, nt, {1e-6: tight, 1e-3: loose}, budget)
+    # the looser tolerance stores four times more fields in the same budget
+    assert atol == 1e-3
+    assert ms == pytest.approx(C.predict_ms(C.schedule_counts(plan, nt, s), loose, nt))
+    best_tight, _ = C.choose_slots(plan, nt, tight, budget)
+    assert best_tight is None or best_tight[1] >= ms
+    assert C.choose_config(plan, nt, {1e-6: tight}, 1.0) is None
