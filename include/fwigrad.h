@@ -120,7 +120,12 @@ enum { FWI_ADVANCE = 0, FWI_TAKESHOT = 1, FWI_RESTORE = 2, FWI_REVERSE = 3, FWI_
 typedef struct { int op; int a; int b; } fwi_action;
 
 /* Context: device ordinal and default checkpoint pool size.  Workspaces are
- * allocated lazily and reused.  Not thread-safe; one context per thread. */
+ * allocated lazily and reused.  Not thread-safe; one context per thread.
+ * The 3D stencil's launch shape before any fwi_autotune call may be set
+ * from the environment at creation (for experiments and tests):
+ * FWI_XCHUNK (x planes per workgroup, default 16), FWI_RPL (rows per lane,
+ * 2 or 4), FWI_REMAP (tile order 0/1/2), FWI_DEEP (two planes of loads in
+ * flight, 0/1). */
 int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes);
 int fwi_ctx_destroy(fwi_ctx *ctx);
 /* Collect per-kernel HIP-event timings in later calls (small overhead). */
