@@ -33,6 +33,7 @@ if ROOT not in sys.path:
 
 METRIC = "FWI gradient s/shot & stencil Gpt/s at fixed grad error; codec GB/s"
 HBM_PEAK_GBS = 8000.0
+ERROR_BAR = 1e-3        # gradient relative L2 against the uncompressed gradient
 
 
 def log(*a):
@@ -93,11 +94,23 @@ def choose_slots(F, nt, st, budget, margin=1.3):
 # ----------------------------------------------------------- CPU oracle
 def cpu_baseline(shot, m0_host, counts, seconds=8.0):
     """Time the FP64 oracle on a bounded sample of the same workload and
-    extrapolate to one gradient with the same schedule counts."""
+    extrapolate to one gradient with the same schedule counts: on all the
+    host cores the process may use, then on one core."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
+    out = cpu_baseline_at(shot, m0_host, counts, threads, seconds)
+    oracle.set_threads(1)
+    one = cpu_baseline_at(shot, m0_host, counts, 1, seconds)
+    oracle.set_threads(threads)
+    out["single_core"] = one
+    return out
+
+
+def cpu_baseline_at(shot, m0_host, counts, threads, seconds):
     import synth
     from oracle import codec as ocodec
     from oracle import solver
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.time()
     p = solver.Problem(shot, m0_host)
     setup = time.time() - t0
@@ -601,6 +614,8 @@ def main():
     ap.add_argument("--nt", type=int, default=None)
     ap.add_argument("--atol", type=float, default=1e-4)
     ap.add_argument("--slots", type=int, default=0, help="compressed slots (0: cost model)")
+    ap.add_argument("--fixed-atol", action="store_true",
+                    help="pilot only --atol instead of every tolerance 1e-1 .. 1e-6")
     ap.add_argument("--iterations", type=int, default=30, help="FWI iterations (fwi workload)")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the checkpoint codec on the launch stream instead of beside the stencil")
@@ -621,23 +636,32 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     if args.copy_calibration:
-        # 1 GiB streams through the library's probe kernel (one float per lane)
+        # 1 GiB streams through the library's probe kernel: 4, 8 and 16 bytes
+        # per lane; 1 read + 1 write (copy), 3 + 1 (forward stencil mix),
+        # 5 + 2 (adjoint mix); workgroups striding over the arrays (each
+        # variant with its own grid, so counter rows of different variants
+        # are told apart) and one access per lane over a covering grid.
         n = 1 << 28
-        a = torch.ones(n, dtype=torch.float32, device=dev)
-        b, c, d = torch.ones_like(a), torch.ones_like(a), torch.empty_like(a)
+        bufs = [torch.full((n,), 1.0 + i, dtype=torch.float32, device=dev) for i in range(7)]
         res = {}
-        for nsrc in (1, 3):
-            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            for it in range(6):
-                if it == 1:
-                    ev0.record()
-                F.fwi_bandwidth_probe(a, d) if nsrc == 1 else F.fwi_bandwidth_probe(a, d, b, c)
-            ev1.record()
-            torch.cuda.synchronize()
-            ms = ev0.elapsed_time(ev1) / 5
-            res["probe_%d_reads" % nsrc] = {"bytes_read": 4 * n * nsrc, "bytes_written": 4 * n,
-                                            "ms": round(ms, 4),
-                                            "GBs": round(4 * n * (nsrc + 1) / ms / 1e6, 1)}
+        grids = {4: 16384, 8: 8192, 16: 4096}
+        for width, flat in ((4, False), (8, False), (16, False), (4, True), (8, True), (16, True)):
+            for ns, nd in ((1, 1), (3, 1), (5, 2)):
+                grid = 0 if flat else grids[width] + 64 * ns + nd
+                srcs, dsts = bufs[:ns], bufs[5:5 + nd]
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                for it in range(6):
+                    if it == 1:
+                        ev0.record()
+                    F.fwi_bandwidth_probe(srcs, dsts, width, grid)
+                ev1.record()
+                torch.cuda.synchronize()
+                ms = ev0.elapsed_time(ev1) / 5
+                key = "%s_w%d_r%d_w%d" % ("flat" if flat else "loop", width, ns, nd)
+                res[key] = {"grid": grid, "bytes_read": 4 * n * ns, "bytes_written": 4 * n * nd,
+                            "ms": round(ms, 4), "GBs": round(4 * n * (ns + nd) / ms / 1e6, 1)}
+                log("probe %s width %d B, %d reads + %d writes: %.1f GB/s" %
+                    ("flat" if flat else "loop", width, ns, nd, res[key]["GBs"]))
         print(json.dumps(res))
         return
     if args.workload == "fwi":
@@ -683,25 +707,78 @@ def main():
     budget = max(budget, 2 * s_unc * 4 * npts)
     log("uncompressed s=%d: %.2f s, phi %.6e, budget %.1f GB" % (s_unc, t_unc, phi_u, budget / 1e9))
 
-    # pilot compressed run at equal slots: sizes and unit costs
-    t0 = time.time()
-    phi_p, g_p = ctx.gradient(shot, m0, q, d_obs, nslots=s_unc, compress=True, atol=args.atol)
-    torch.cuda.synchronize()
-    t_pilot = time.time() - t0
-    st_p = ctx.stats()
-    err_p = rel_l2(g_p, g_u)
-    log("pilot compressed s=%d: %.2f s, rel err %.2e, %d B/field" %
-        (s_unc, t_pilot, err_p, st_p["ckpt_bytes"] // max(st_p["n_encode"], 1)))
+    # Pilots, one per tolerance (largest first): store-all where its streams
+    # fit the budget, else the uncompressed run's slot count.  Each gives
+    # the gradient error against the uncompressed gradient, the stream size
+    # and codec unit costs, and the share kappa of overlapped codec time on
+    # the critical path (against the uncompressed run's clean step times).
+    from paper_2009_12623_amd import costmodel
+    plan = F.fwi_revolve_plan
+    atols = [args.atol] if args.fixed_atol else [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6]
+    pilots, units_by_atol = [], {}
+    for atol in atols:
+        for s_p in (nt, s_unc):
+            t0 = time.time()
+            try:
+                _, g_p = ctx.gradient(shot, m0, q, d_obs, nslots=s_p, compress=True, atol=atol,
+                                      pool_bytes=int(budget))
+            except F.FwiError as e:
+                if e.code == F.FWI_ECAPACITY and s_p != s_unc:
+                    log("pilot atol %g: store-all streams exceed the budget, %d slots" % (atol, s_unc))
+                    continue
+                if e.code == F.FWI_ERANGE:
+                    log("pilot atol %g refused: values beyond atol 2^23" % atol)
+                    pilots.append({"atol": atol, "refused": "FWI_ERANGE"})
+                    break
+                raise
+            torch.cuda.synchronize()
+            t_p = time.time() - t0
+            st_p = ctx.stats()
+            err_p = rel_l2(g_p, g_u)
+            del g_p
+            c_p = costmodel.schedule_counts(plan, nt, s_p)
+            u_p = costmodel.UnitCosts.from_stats(st_p, st_u)
+            kap = costmodel.overlap_kappa(c_p, u_p, nt, st_p["ms_total"])
+            u_p.kappa = kap
+            rec = {"atol": atol, "nslots": s_p, "s": round(t_p, 3), "grad_rel_l2": float("%.3e" % err_p),
+                   "bytes_per_field": int(u_p.field_bytes),
+                   "compression_factor": round(st_p["ckpt_raw_bytes"] / max(st_p["ckpt_bytes"], 1), 2),
+                   "kappa": round(kap, 4), "t_enc_ms": round(u_p.t_enc, 4), "t_dec_ms": round(u_p.t_dec, 4)}
+            pilots.append(rec)
+            log("pilot %s" % rec)
+            if err_p <= ERROR_BAR:
+                units_by_atol[atol] = u_p
+            break
+    if not units_by_atol:
+        raise SystemExit("no tolerance keeps the gradient within %g of the uncompressed one" % ERROR_BAR)
     if args.slots:
-        s_c, table, unit = args.slots, [], {}
+        atol_c, s_c = max(units_by_atol), args.slots
     else:
-        best, table, unit = choose_slots(F, nt, st_p, budget)
-        s_c = best[0] if best else s_unc
-        log("cost model (slots, predicted s):", table, "->", s_c)
-    del g_p
+        atol_c, s_c, _ = costmodel.choose_config(plan, nt, units_by_atol, budget)
+    unit_c = units_by_atol[atol_c]
+    _, table = costmodel.choose_slots(plan, nt, unit_c, budget)
+    pred_c = costmodel.predict_ms(costmodel.schedule_counts(plan, nt, s_c), unit_c, nt) / 1e3
+    log("accepted tolerances %s -> atol %g, %d slots, predicted %.2f s" %
+        (sorted(units_by_atol), atol_c, s_c, pred_c))
+
+    # equal slots, compressed (the memory-saving mode) at the chosen tolerance
+    t0 = time.time()
+    _, g_40 = ctx.gradient(shot, m0, q, d_obs, nslots=s_unc, compress=True, atol=atol_c,
+                           pool_bytes=int(budget))
+    torch.cuda.synchronize()
+    t_40 = time.time() - t0
+    st_40 = ctx.stats()
+    equal_slots = {"nslots": s_unc, "atol": atol_c, "s_per_shot": round(t_40, 3),
+                   "grad_rel_l2_vs_uncompressed": float("%.3e" % rel_l2(g_40, g_u)),
+                   "predicted_s": round(costmodel.predict_ms(costmodel.schedule_counts(plan, nt, s_unc),
+                                                             unit_c, nt) / 1e3, 3),
+                   "counts": {k: st_40[k] for k in ("n_forward", "n_adjoint", "n_encode", "n_decode")},
+                   "pool_high_gb": round(st_40["pool_high"] / 1e9, 2)}
+    del g_40
+    log("compressed s=%d: %s" % (s_unc, equal_slots))
 
     def run():
-        return ctx.gradient(shot, m0, q, d_obs, nslots=s_c, compress=True, atol=args.atol,
+        return ctx.gradient(shot, m0, q, d_obs, nslots=s_c, compress=True, atol=atol_c,
                             pool_bytes=int(budget))
 
     while True:
@@ -745,7 +822,7 @@ def main():
     if tune is not None and dom in ("forward_step", "adjoint_imaging_step"):
         pre = "fwd" if dom == "forward_step" else "adj"
         shape = (tune[pre + "_xchunk"], tune[pre + "_rows_per_lane"], tune[pre + "_xcd_order"],
-                 tune[pre + "_deep"])
+                 tune[pre + "_deep"], tune[pre + "_vz"])
     traffic = counted_traffic(dom, shape) if args.workload == "c3" else None
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -771,15 +848,18 @@ def main():
             "computational_grid": list(shot.comp_shape),
             "nt": nt,
             "space_order": shot.so,
-            "atol": args.atol,
+            "atol": atol_c,
             "nslots_compressed": s_c,
             "nslots_uncompressed": s_unc,
             "codec_overlap": not args.no_overlap,
             "hbm_budget_gb": round(budget / 1e9, 2),
             "stencil_shape": None if tune is None else {
-                "forward": [tune["fwd_xchunk"], tune["fwd_rows_per_lane"], tune["fwd_xcd_order"], tune["fwd_deep"]],
-                "adjoint": [tune["adj_xchunk"], tune["adj_rows_per_lane"], tune["adj_xcd_order"], tune["adj_deep"]],
-                "fields": ["x_planes_per_workgroup", "rows_per_lane", "tile_order_0rr_1contig_2zcol", "planes_in_flight_2"]},
+                "forward": [tune["fwd_xchunk"], tune["fwd_rows_per_lane"], tune["fwd_xcd_order"], tune["fwd_deep"],
+                            tune["fwd_vz"]],
+                "adjoint": [tune["adj_xchunk"], tune["adj_rows_per_lane"], tune["adj_xcd_order"], tune["adj_deep"],
+                            tune["adj_vz"]],
+                "fields": ["x_planes_per_workgroup", "rows_per_lane", "tile_order_0rr_1contig_2zcol", "planes_in_flight_2",
+                           "z_points_per_lane"]},
         },
         "roofline": roof,
         # the same kernels timed alone (autotune trials, no codec work beside
@@ -803,13 +883,21 @@ def main():
         "phi": phi_c,
         "counts": {k: st[k] for k in ("n_forward", "n_adjoint", "n_encode", "n_decode")},
         "kernel_ms": {k: round(st[k], 1) for k in ("ms_forward", "ms_adjoint", "ms_encode", "ms_decode", "ms_total")},
-        "cost_model": {"table": table, "unit_ms": {k: round(v, 4) for k, v in unit.items()}},
+        "fixed_error": {"bar": ERROR_BAR, "pilots": pilots, "accepted": sorted(units_by_atol),
+                        "chosen_atol": atol_c, "chosen_slots": s_c},
+        "cost_model": {"predicted_s": round(pred_c, 3), "measured_s": round(s_per_shot, 3),
+                       "rel_deviation": round(s_per_shot / pred_c - 1.0, 4), "table": table,
+                       "unit_ms": {"t_fwd": round(unit_c.t_fwd, 4), "t_adj": round(unit_c.t_adj, 4),
+                                   "t_enc": round(unit_c.t_enc, 4), "t_dec": round(unit_c.t_dec, 4),
+                                   "kappa": round(unit_c.kappa, 4),
+                                   "bytes_per_field": int(unit_c.field_bytes)}},
+        "equal_slots_compressed": equal_slots,
     }
     if not args.no_cpu_baseline:
         m_host = m0.double().cpu().numpy()
         del g_u, g_c
         counts = dict(n_forward=st["n_forward"], n_adjoint=st["n_adjoint"],
-                      n_encode=st["n_encode"], n_decode=st["n_decode"], atol=args.atol)
+                      n_encode=st["n_encode"], n_decode=st["n_decode"], atol=atol_c)
         ctx.close()
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(shot, m_host, counts)

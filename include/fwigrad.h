@@ -54,7 +54,9 @@ enum {
     FWI_ECORRUPT = -4,    /* compressed stream fails validation */
     FWI_ENONFINITE = -5,  /* NaN/Inf handed to the codec */
     FWI_EUNSTABLE = -6,   /* dt above the leapfrog stability limit */
-    FWI_EHIP = -7         /* HIP runtime error */
+    FWI_EHIP = -7,        /* HIP runtime error */
+    FWI_ERANGE = -8       /* a value at or above atol * 2^23 reached the codec:
+                             |decoded - x| <= atol cannot be guaranteed */
 };
 
 typedef struct fwi_ctx fwi_ctx;
@@ -125,7 +127,7 @@ typedef struct { int op; int a; int b; } fwi_action;
  * from the environment at creation (for experiments and tests):
  * FWI_XCHUNK (x planes per workgroup, default 16), FWI_RPL (rows per lane,
  * 2 or 4), FWI_REMAP (tile order 0/1/2), FWI_DEEP (two planes of loads in
- * flight, 0/1). */
+ * flight, 0/1), FWI_VZ (z points per lane, 1 or 2; 2 ignores FWI_DEEP). */
 int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes);
 int fwi_ctx_destroy(fwi_ctx *ctx);
 /* Collect per-kernel HIP-event timings in later calls (small overhead). */
@@ -214,6 +216,32 @@ int fwi_gradient_batch(fwi_ctx *ctx, int nshots, const fwi_grid *grids,
                        const float *const *d_obs, const fwi_ckpt_cfg *cfg,
                        float *const *grads, double *phis, hipStream_t stream);
 
+/* Stacking (Sec. 2: the gradient of a survey is the sum of its shots'
+ * gradients; Sec. 4 "Stacking"): the shots of a batched call add into one
+ * gradient array grad [device, dims n, C order, z contiguous, overwritten].
+ * region 0 adds each shot's whole computational-grid gradient (shots that
+ * share one grid, origin all zero); region 1 adds only its physical part,
+ * the absorbing layer dropped (uneven crops of one model: the physical
+ * point (0,0,0) of shot i lands at origin[i*ndim .. i*ndim+ndim-1] [host]
+ * of the model's physical grid; the layer's velocities are not model
+ * parameters).  The sum runs in shot order, one shot at a time, in FP32,
+ * so it is deterministic (bitwise repeatable).  FWI_EINVAL if a shot's
+ * region falls outside dims n or ndim differs from the shots'. */
+typedef struct {
+    int ndim;
+    int n[3];
+    int region;
+    const int *origin;
+} fwi_stack;
+
+/* fwi_gradient_batch whose shot gradients are stacked into grad
+ * [device] as described by *stack; phis[i] [host] per shot. */
+int fwi_gradient_stack(fwi_ctx *ctx, int nshots, const fwi_grid *grids,
+                       const float *const *models, const fwi_shot *shots,
+                       const float *const *d_obs, const fwi_ckpt_cfg *cfg,
+                       const fwi_stack *stack, float *grad, double *phis,
+                       hipStream_t stream);
+
 /* Split form for automatic differentiation: the forward sweep writes d_sim
  * and keeps its checkpoints in a new tape (owns device memory until
  * fwi_tape_free); fwi_backward then runs the reverse sweep with any
@@ -240,6 +268,25 @@ int fwi_forward_ckpt_batch(fwi_ctx *ctx, int nshots, const fwi_grid *grids,
 int fwi_backward_batch(fwi_ctx *ctx, fwi_tape *tape, const float *const *dd,
                        float *const *grads, hipStream_t stream);
 
+/* One stored checkpoint stream of a compressed tape: the stream of level
+ * `level` (0: u^k, 1: u^(k-1), held only where the schedule restarts
+ * forward propagation from the checkpoint) in slot `slot` of shot `shot`
+ * (0 for a single-shot tape).  After fwi_forward_ckpt(_batch) the tape holds
+ * the checkpoints of the forward sweep; each stream is the codec stream of
+ * that level as stored in the pool, byte for byte what ckpt_compress writes
+ * for the same field.  *nbytes [host] receives its size; with out [device,
+ * cap bytes] non-NULL the stream is copied there (asynchronous on stream;
+ * FWI_ECAPACITY if cap is too small).  FWI_EINVAL for an exact-checkpoint
+ * tape, an empty slot or a level the checkpoint does not hold.  Reads the
+ * slot table after synchronising the stream. */
+int fwi_tape_stream(fwi_tape *tape, int shot, int slot, int level, void *out,
+                    size_t cap, size_t *nbytes, hipStream_t stream);
+
+/* fwi_backward_batch whose shot gradients J_i^T dd[i] are stacked into
+ * grad [device] as described by *stack (see fwi_stack). */
+int fwi_backward_stack(fwi_ctx *ctx, fwi_tape *tape, const float *const *dd,
+                       const fwi_stack *stack, float *grad, hipStream_t stream);
+
 /* Pool bytes [host] that the checkpoints of cfg.nslots slots on grid g can
  * take: exact checkpoints need exactly this much; for compressed ones it is
  * the worst case (every stream at ckpt_bound), so callers usually size a
@@ -248,7 +295,10 @@ int fwi_ckpt_pool_bytes(const fwi_grid *g, const fwi_ckpt_cfg *cfg, size_t *byte
 
 /* Codec (Sec. 1.4 / Sec. 3: ZFP-style fixed accuracy).  field [device]
  * float32, C order, ndim in {2, 3}; every decoded value is within atol of
- * the input when max|x| over each 4^ndim block is below atol * 2^23.
+ * the input.  That bound needs every |x| below 2^(floor(log2 atol) + 23)
+ * (at most atol * 2^23): a field with a larger value is refused with
+ * FWI_ERANGE (so is a compressed checkpoint schedule that meets one), since
+ * the 24-bit block conversion alone would lose more than atol.
  * ckpt_bound: worst-case stream bytes [host].  ckpt_compress writes the
  * stream to out [device, cap bytes] and its size to *nbytes [host] (after a
  * stream sync); FWI_ECAPACITY if cap is too small, FWI_ENONFINITE on NaN or
@@ -286,10 +336,13 @@ int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
                      int *nactions, long long *nforward);
 
 /* Autotuner: times every candidate launch shape of the stencil kernels on
- * this grid (3D: x planes per workgroup in {8,16,32,64} x tile order
- * round-robin / XCD-contiguous x {2 rows per lane, 4 rows per lane, 2 rows
- * per lane with two planes of loads in flight}, plus 2 rows per lane with
- * the z tiles of each column dealt to one XCD; 2D: x planes in {4..64}),
+ * this grid (3D, one z point per lane: x planes per workgroup in
+ * {8,16,32,64} x tile order round-robin / XCD-contiguous x {2 rows per
+ * lane, 4 rows per lane, 2 rows per lane with two planes of loads in
+ * flight}, plus 2 rows per lane with the z tiles of each column dealt to
+ * one XCD; two z points per lane: x planes in {8,16,32,64} x the three tile
+ * orders x {2, 4} rows per lane, and 128 planes with 4 rows per lane;
+ * 2D: x planes in {4..64}),
  * `steps` forward and `steps` adjoint launches each on the model
  * m [device], with the buffer roles alternating as in a sweep, and keeps
  * the fastest forward and adjoint shapes for later calls on a grid of the
@@ -306,17 +359,39 @@ typedef struct {
     int adj_xchunk, adj_rows_per_lane, adj_xcd_order;
     double fwd_ms, adj_ms;
     int fwd_deep, adj_deep;       /* two planes of loads in flight */
+    int fwd_vz, adj_vz;           /* z points per lane: 1 (64-point z tiles) or 2 (128-point tiles, 8-byte accesses) */
 } fwi_tune_result;
 int fwi_autotune(fwi_ctx *ctx, const fwi_grid *g, const float *m,
                  const fwi_shot *shot, int steps, fwi_tune_result *out,
                  hipStream_t stream);
 
-/* Bandwidth probe with the stencils' access width (one float per lane):
- * d = a (nsrc = 1) or d = a + b + c (nsrc = 3), n floats, all [device].
- * Measures the practical streaming ceiling and calibrates HBM counters
- * against a kernel of known traffic; not part of the gradient path. */
-int fwi_bandwidth_probe(const float *a, const float *b, const float *c, float *d,
-                        size_t n, int nsrc, hipStream_t stream);
+/* Times one stencil launch shape on grid g the way fwi_autotune times its
+ * candidates (steps forward and steps adjoint launches on non-zero fields,
+ * buffer roles alternating as in a sweep, after one untimed launch), without
+ * changing the context's chosen shapes.  shape [host] = {x planes per
+ * workgroup, rows per lane (2 or 4), tile order (0..2), two planes of loads
+ * in flight (0/1, one z point per lane only), z points per lane (1 or 2)};
+ * 2D grids use only the first.  *fwd_ms, *adj_ms [host]: mean milliseconds
+ * per launch.  Synchronises the stream; the context's working fields are
+ * cleared. */
+int fwi_time_shape(fwi_ctx *ctx, const fwi_grid *g, const float *m,
+                   const fwi_shot *shot, const int shape[5], int steps,
+                   double *fwd_ms, double *adj_ms, hipStream_t stream);
+
+/* Streaming bandwidth probe (not part of the gradient path): every
+ * dst[j] (j < ndst <= 2) receives the element-wise sum of the nsrc (1..5)
+ * arrays src[i]; n floats per array [device, aligned to width].  Each lane
+ * accesses width bytes (4, 8 or 16) at a time with non-temporal loads and
+ * stores; grid = 0 gives every lane one access (the grid covers the
+ * arrays), grid > 0 lets that many workgroups of 256 lanes stride over the
+ * arrays.  3 sources + 1 destination is the forward
+ * stencil's stream mix, 5 + 2 the adjoint's.  Measures the practical HBM
+ * ceiling per access width and serves as the kernel of known traffic that
+ * calibrates hardware counters.  FWI_EINVAL for other counts, widths,
+ * misaligned pointers or a grid outside 0..2^20. */
+int fwi_bandwidth_probe(const float *const *src, int nsrc, float *const *dst,
+                        int ndst, size_t n, int width, int grid,
+                        hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -68,6 +68,12 @@ def lib():
     return _lib
 
 
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops in this thread's later calls."""
+    lib()
+    ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+
+
 def ptr(a: np.ndarray, ct):
     return a.ctypes.data_as(ctypes.POINTER(ct))
 

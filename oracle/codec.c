@@ -51,7 +51,9 @@
  *
  * The guard G makes |x - decoded| <= atol hold whenever
  * emax <= minexp + Q - 1 (the codec then never drops information the float32
- * block cannot hold); see the derivation in the design notes.
+ * block cannot hold); see the derivation in the design notes.  A field with
+ * a value at or above 2^(minexp + Q - 1) is refused (OR_ERANGE): the Q-bit
+ * conversion alone would then lose more than atol.
  */
 #include <stdint.h>
 #include <string.h>
@@ -62,6 +64,7 @@
 #define OR_ECAPACITY (-3)
 #define OR_ECORRUPT (-4)
 #define OR_ENONFINITE (-5)
+#define OR_ERANGE (-8)
 
 typedef struct {
     int ndim;
@@ -368,12 +371,19 @@ long or_compress(const float *x, int ndim, const long *n, double atol,
     if (!(atol > 0) || !isfinite(atol) || atol < 2.2250738585072014e-308)
         return OR_EINVAL;
     long nval = g.n[0] * g.n[1] * g.n[2];
+    int minexp = minexp_of(atol);
+    /* the fixed-accuracy bound needs every block exponent emax (|x| < 2^emax)
+     * at most minexp + Q - 1, i.e. every |x| below 2^(minexp + Q - 1) <= atol 2^23;
+     * a larger value loses more than atol to the Q-bit conversion alone */
+    int range = 0;
     for (long i = 0; i < nval; ++i) {
         uint32_t w;
         memcpy(&w, &x[i], 4);
-        if (((w >> 23) & 0xFF) == 0xFF) return OR_ENONFINITE;
+        int E = (w >> 23) & 0xFF;
+        if (E == 0xFF) return OR_ENONFINITE;
+        if (E != 0 && E - 126 > minexp + QBITS - 1) range = 1;
     }
-    int minexp = minexp_of(atol);
+    if (range) return OR_ERANGE;
     int perm[64];
     sequency_order(ndim, perm);
     long hdr = 64 + table_bytes(&g);

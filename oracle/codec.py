@@ -11,7 +11,7 @@ import numpy as np
 
 from . import dims, lib, ptr
 
-EINVAL, ECAPACITY, ECORRUPT, ENONFINITE = -1, -3, -4, -5
+EINVAL, ECAPACITY, ECORRUPT, ENONFINITE, ERANGE = -1, -3, -4, -5, -8
 
 
 class CodecError(RuntimeError):

@@ -4,15 +4,22 @@ model of recomputation vs storage; this is that model for this library).
 
 One gradient with s slots on nt steps costs
 
-    T(s) = F(s) t_fwd + nt t_adj + E(s) t_enc + (R1(s) + 2 R2(s)) t_dec
+    T(s) = F(s) t_fwd + nt t_adj + 2 R2(s) t_dec + kappa (E(s) t_enc + R1(s) t_dec)
 
 where F is the schedule's forward steps, E the fields encoded (a checkpoint
 keeps the older leapfrog level only where forward propagation restarts from
 it), R1 the restores that decode u^k alone and R2 those that decode both
-levels.  Its checkpoints need at most peak(s) fields at once.  Unit costs
-come from a measured call (fwi_stats); the schedule counts from the
-library's own planner (fwi_revolve_plan), so the model follows exactly the
-action list the executor runs.
+levels.  The library runs encodes beside the following forward steps and a
+decode of u^k alone beside the current adjoint step, on a second stream:
+only the share kappa of that codec time shows up, as the stencil steps it
+overlaps slowing down (they share the memory system).  A restore of both
+levels is followed by forward steps that read them, so its decodes stay on
+the critical path.  kappa = 1 is a serial run (codec overlap off); it is
+measured from a compressed call against the stencil's own step times
+(``overlap_kappa``).  Its checkpoints need at most peak(s) fields at once.
+Unit costs come from measured calls (fwi_stats); the schedule counts from
+the library's own planner (fwi_revolve_plan), so the model follows exactly
+the action list the executor runs.
 """
 from __future__ import annotations
 
@@ -66,19 +73,35 @@ class UnitCosts:
     t_enc: float          # ms per field encoded
     t_dec: float          # ms per field decoded
     field_bytes: float    # mean compressed bytes per field
+    kappa: float = 1.0    # share of overlapped codec time on the critical path
 
     @classmethod
-    def from_stats(cls, st: dict) -> "UnitCosts":
-        """from fwi_stats of a compressed call with per-kernel timing on"""
+    def from_stats(cls, st: dict, stencil: dict | None = None, kappa: float = 1.0) -> "UnitCosts":
+        """from fwi_stats of a compressed call with per-kernel timing on;
+        ``stencil`` (fwi_stats of a call without codec work, e.g. the
+        uncompressed run) supplies the stencil step times when given"""
         n = lambda k: max(st[k], 1)
-        return cls(st["ms_forward"] / n("n_forward"), st["ms_adjoint"] / n("n_adjoint"),
+        src = stencil if stencil is not None else st
+        m = lambda k: max(src[k], 1)
+        return cls(src["ms_forward"] / m("n_forward"), src["ms_adjoint"] / m("n_adjoint"),
                    st["ms_encode"] / n("n_encode"), st["ms_decode"] / n("n_decode"),
-                   st["ckpt_bytes"] / n("n_encode"))
+                   st["ckpt_bytes"] / n("n_encode"), kappa)
 
 
 def predict_ms(c: ScheduleCounts, u: UnitCosts, nt: int) -> float:
-    return (c.forward * u.t_fwd + nt * u.t_adj + c.encodes * u.t_enc
-            + (c.restores_uk + 2 * c.restores_both) * u.t_dec)
+    return (c.forward * u.t_fwd + nt * u.t_adj + 2 * c.restores_both * u.t_dec
+            + u.kappa * (c.encodes * u.t_enc + c.restores_uk * u.t_dec))
+
+
+def overlap_kappa(c: ScheduleCounts, u: UnitCosts, nt: int, measured_ms: float) -> float:
+    """kappa that makes predict_ms equal a measured call of schedule ``c``
+    (u: clean stencil step times and that call's codec times), clipped to
+    [0, 1]; 1 when the call has no overlappable codec work"""
+    hidden = c.encodes * u.t_enc + c.restores_uk * u.t_dec
+    if hidden <= 0:
+        return 1.0
+    base = c.forward * u.t_fwd + nt * u.t_adj + 2 * c.restores_both * u.t_dec
+    return min(1.0, max(0.0, (measured_ms - base) / hidden))
 
 
 CANDIDATES = (40, 50, 64, 80, 100, 128, 160, 200, 256, 320, 400, 512, 640, 800, 1000,

@@ -312,7 +312,7 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
     if (c >= nchunks) return;
     const long nb[3] = {nb0, nb1, nb2};
     BitWriter bw{0ull, 0, scratch + scratch_word(c, 0, chunk_words), 0};
-    bool nonfinite = false;
+    bool nonfinite = false, outrange = false;
     typedef float f4v __attribute__((ext_vector_type(4)));
     // padded fields: the rows of the next block are loaded while the current
     // one is coded
@@ -402,6 +402,8 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
             bw.put(0u, 1);
             continue;
         }
+        // fixed-accuracy bound needs emax <= minexp + Q - 1 (|x| < atol 2^23)
+        outrange |= emax > minexp + QB - 1;
         int ci[SZ];
 #pragma unroll
         for (int li = 0; li < SZ; ++li) {
@@ -458,6 +460,7 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
     if (bw.fill) bw.out[64 * bw.w] = bw.acc;
     chunk_bits[c] = (unsigned long long)bw.w * 64ull + (unsigned long long)bw.fill;
     if (nonfinite) atomicOr(flags, 1u);
+    if (outrange) atomicOr(flags, 8u);
 }
 
 // --------------------------------------------------------------- placement

@@ -17,6 +17,7 @@ constexpr int PAD_X = 8;
 constexpr int PAD_Y = 8;
 constexpr int PAD_Z0 = 32;
 constexpr int TILE_Z = 64;     // one wave64 along z
+constexpr int TILE_ZW = 128;   // one wave64 along z, two points per lane (z rounding of padded 3D arrays)
 constexpr int TILE_Y = 32;     // y rounding of padded 3D arrays (largest stencil tile height)
 constexpr int TILE_Z2 = 256;   // z extent of a 2D stencil workgroup
 
@@ -53,6 +54,7 @@ struct StepParams {
     int rpl;                // 3D: rows per lane (tile height 8 rpl), 2 or 4
     int remap;              // 3D tile order: 0 round robin, 1 XCD-contiguous, 2 z columns per XCD
     int deep;               // 3D: two planes of loads in flight (2 rows per lane)
+    int vz;                 // 3D: z points per lane, 1 (64-point z tiles) or 2 (128-point tiles, 8-byte accesses)
     // forward only: sample u1 at the receivers into grow (nullptr: skip)
     const int *rec_off;     // padded offsets from the allocation base
     int nrec;
@@ -86,10 +88,26 @@ struct PadMap {
 void launch_coef(const float *m, float *b_padded, const PadMap &pm, double dt, hipStream_t st);
 void launch_unpad(const float *acc_padded, float *g, const PadMap &pm, hipStream_t st);
 void launch_pad(const float *f, float *dst_padded, const PadMap &pm, hipStream_t st);
+// dst[(o0 + x) d0 + (o1 + y) d1 + o2 + z] += acc at computational point
+// (r0 + x, r1 + y, r2 + z), over an n0 x n1 x n2 region of a padded
+// accumulator (2D: index 1 unused); every target point of one launch is
+// touched once, so launches issued in a fixed order sum deterministically
+struct StackMap {
+    PadMap pm;              // the accumulator's padded layout
+    long r[3];              // region start in the computational grid
+    long n[3];              // region dims
+    long o[3];              // target offset
+    long d0, d1;            // target strides (z contiguous)
+};
+void launch_stack_add(const float *acc_padded, float *dst, const StackMap &sm, hipStream_t st);
 void launch_fill_zero(float *p, size_t n, hipStream_t st);
 void launch_copy(float *dst, const float *src, size_t n, hipStream_t st);
-void launch_probe(const float *a, const float *b, const float *c, float *d, size_t n, int nsrc,
-                  hipStream_t st);
+struct ProbeArgs {
+    const float *src[5];
+    float *dst[2];
+    size_t n;               // floats per stream (a multiple of the access width)
+};
+void launch_probe(const ProbeArgs &a, int nsrc, int ndst, int width_bytes, int grid, hipStream_t st);
 void launch_gather(const float *field_origin, const int *rec_off, int nrec,
                    float *out_row, hipStream_t st);
 void launch_residual(const float *d_sim, const float *d_obs, float *res,
@@ -170,6 +188,9 @@ struct EncodeArgs {
     unsigned long long *total_bytes; // device: running sum of stream bytes
 };
 void codec_encode(const EncodeArgs &a, hipStream_t st);
+
+// message returned by fwi_last_error() on this thread
+void set_last_error(const char *msg);
 
 struct DecodeArgs {
     FieldView f;

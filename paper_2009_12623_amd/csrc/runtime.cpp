@@ -208,8 +208,9 @@ struct fwi_ctx {
     int rpl3 = 2;              // 3D rows per lane
     int remap3 = 0;            // 3D tile order: 0 round robin, 1 XCD-contiguous, 2 z columns per XCD
     int deep3 = 0;             // 3D two planes of loads in flight
+    int vz3 = 1;               // 3D z points per lane (1: 64-point z tiles, 2: 128-point)
     struct Shape {
-        int xchunk, rpl, remap, deep;
+        int xchunk, rpl, remap, deep, vz;
     };
     std::map<std::vector<int>, std::pair<Shape, Shape>> tuned;   // grid key -> (forward, adjoint)
     fwi_stats stats{};
@@ -325,6 +326,13 @@ void stencil_weights(int so, double *a)
         sum += a[k];
     }
     a[0] = -2.0 * sum;
+}
+
+// two z points per lane with four rows per lane would spill registers at
+// radius 8 (SO16): such shapes run two rows per lane
+int shape_rpl(int vz, int rpl, int radius)
+{
+    return (vz == 2 && radius >= 8) ? 2 : rpl;
 }
 
 void validate_grid(const fwi_grid *g)
@@ -691,6 +699,8 @@ struct Exec {
         p.rpl = sh.rpl;
         p.remap = sh.remap;
         p.deep = sh.deep;
+        p.vz = sh.vz;
+        p.rpl = shape_rpl(p.vz, p.rpl, S.R);
     }
 
     StepParams params() const
@@ -711,6 +721,8 @@ struct Exec {
         p.rpl = c->rpl3;
         p.remap = c->remap3;
         p.deep = c->deep3;
+        p.vz = c->vz3;
+        p.rpl = shape_rpl(p.vz, p.rpl, S.R);
         // short x chunks: many workgroups in flight; the 2R halo planes
         // re-read per chunk come from L2
         p.xchunk = c->xchunk3 > 0 ? c->xchunk3 : 16;
@@ -1105,6 +1117,9 @@ void finish_status(fwi_ctx *c, hipStream_t st)
     if (misc[1]) c->stats.pool_high = (long long)misc[1];
     if (misc[2]) c->stats.ckpt_bytes = (long long)misc[2];
     if (fl & 1u) throw Error{FWI_ENONFINITE, "non-finite wavefield reached the codec"};
+    if (fl & 8u)
+        throw Error{FWI_ERANGE, "a value at or above atol * 2^23 reached the codec: the fixed-accuracy "
+                                "bound cannot hold at this atol (raise atol)"};
     if (fl & 2u) throw Error{FWI_ECAPACITY, "checkpoint pool overflow (use fewer slots or a larger pool)"};
     if (fl & 4u) throw Error{FWI_ECORRUPT, "checkpoint stream failed to decode"};
 }
@@ -1212,7 +1227,8 @@ struct BatchExec {
         for (int i = 0; i < n; ++i) {
             h[i] = BatchEntry{};
             h[i].p = ps[i];
-            h[i].p.rpl = 2;             // the batched 3D kernel uses 2 rows per lane
+            h[i].p.rpl = 2;             // the batched 3D kernel uses 2 rows per lane, one z point each
+            h[i].p.vz = 1;
             h[i].first = first;
             first += step_geometry(h[i], ndim, adj);
         }
@@ -1386,7 +1402,7 @@ void key_shot(KeyBuilder &k, fwi_ctx *c, const fwi_grid *g, const fwi_shot *sh, 
     k.bytes(sh->rec, sizeof(int32_t) * (size_t)sh->nrec * (size_t)g->ndim);
     auto it = c->tuned.find({S.ndim, S.pad.nx, S.pad.ny, S.pad.nz, S.R});
     if (it != c->tuned.end()) k.add(it->second.first).add(it->second.second);
-    k.add(c->xchunk3).add(c->rpl3).add(c->remap3).add(c->deep3);
+    k.add(c->xchunk3).add(c->rpl3).add(c->remap3).add(c->deep3).add(c->vz3);
 }
 
 // Enqueue a schedule: directly, or (graphs on) by replaying the graph
@@ -1473,6 +1489,145 @@ void run_schedule(fwi_ctx *c, hipStream_t caller, const std::string &key, size_t
 
 }  // namespace
 
+namespace {
+
+// Times `steps` forward (adj = false) or adjoint launches of one launch
+// shape on the context's working fields, alternating the buffer roles the
+// way the sweeps rotate them, after one untimed launch.  The fields must
+// hold data (see fill_tuning_fields).
+double time_shape(fwi_ctx *c, Exec &ex, const fwi_shot *shot, const fwi_ctx::Shape &sh, bool adj, int steps,
+                  hipEvent_t e0, hipEvent_t e1, hipStream_t st)
+{
+    StepParams p = ex.params();
+    p.xchunk = sh.xchunk;
+    p.rpl = sh.rpl;
+    p.remap = sh.remap;
+    p.deep = sh.deep;
+    p.vz = sh.vz;
+    p.rpl = shape_rpl(p.vz, p.rpl, ex.S.R);
+    auto one = [&](int i) {
+        float *a = (i & 1) ? c->sb.fb.p : c->sb.fa.p, *b = (i & 1) ? c->sb.fa.p : c->sb.fb.p;
+        if (adj) {
+            float *l1 = (i & 1) ? c->sb.lb.p : c->sb.la.p, *l2 = (i & 1) ? c->sb.la.p : c->sb.lb.p;
+            p.u1 = l1; p.u2 = l2; p.out = l2; p.uk = a; p.g = c->sb.gacc.p;
+        } else {
+            p.u1 = a; p.u2 = b; p.out = b; p.wav = shot->wavelet; p.step = 0;
+        }
+        launch_step(p, ex.S.ndim, ex.S.R, adj, st);
+    };
+    one(0);
+    HIPCHK(hipEventRecord(e0, st));
+    for (int i = 0; i < steps; ++i) one(i + 1);
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    return (double)ms / steps;
+}
+
+// The timed fields hold data (copies of the coefficient field), not zeros:
+// all-zero traffic ran measurably faster and ranked the shapes differently
+// from a real sweep.
+void fill_tuning_fields(fwi_ctx *c, Exec &ex, hipStream_t st)
+{
+    HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, c->sb.arena.n, st));
+    ex.init_fields();
+    const size_t ne = c->sb.padded_elems;
+    for (float *f : {c->sb.fa.p, c->sb.fb.p, c->sb.la.p, c->sb.lb.p, c->sb.gacc.p})
+        launch_copy(f, c->sb.coef.p, ne, st);
+}
+
+bool valid_shape(int ndim, const fwi_ctx::Shape &s)
+{
+    if (s.xchunk < 1) return false;
+    if (ndim == 2) return true;
+    return (s.rpl == 2 || s.rpl == 4) && s.remap >= 0 && s.remap <= 2 && (s.vz == 1 || s.vz == 2) &&
+           (s.deep == 0 || (s.deep == 1 && s.vz == 1));
+}
+
+
+}  // namespace
+
+namespace {
+
+// Stacking of batched shot gradients into one array (fwi_stack): one
+// StackMap per shot, validated against the target dims.
+std::vector<StackMap> stack_maps(const fwi_stack *sk, const std::vector<Setup> &setups)
+{
+    if (!sk || !sk->origin) throw Error{FWI_EINVAL, "stack description or origins are null"};
+    const int nd = setups[0].ndim;
+    if (sk->ndim != nd) throw Error{FWI_EINVAL, "stack ndim differs from the shots'"};
+    if (sk->region != 0 && sk->region != 1) throw Error{FWI_EINVAL, "stack region must be 0 or 1"};
+    for (int d = 0; d < nd; ++d)
+        if (sk->n[d] < 1) throw Error{FWI_EINVAL, "stack dims must be >= 1"};
+    std::vector<StackMap> out;
+    for (size_t i = 0; i < setups.size(); ++i) {
+        const Setup &S = setups[i];
+        StackMap m{};
+        m.pm.nx = S.pad.nx;
+        m.pm.ny = S.pad.ny;
+        m.pm.nz = S.pad.nz;
+        m.pm.sx = S.pad.sx;
+        m.pm.sy = nd == 3 ? S.pad.sy : 0;
+        m.pm.origin = S.pad.origin;
+        const long comp[3] = {S.pad.nx, S.pad.ny, S.pad.nz};
+        const int axis[3] = {0, nd == 3 ? 1 : -1, nd == 3 ? 2 : 1};   // target/origin index per (x, y, z)
+        for (int a = 0; a < 3; ++a) {
+            if (axis[a] < 0) {
+                m.r[a] = 0;
+                m.n[a] = 1;
+                m.o[a] = 0;
+                continue;
+            }
+            const long lay = sk->region ? S.nbl : 0;
+            m.r[a] = lay;
+            m.n[a] = comp[a] - 2 * lay;
+            m.o[a] = sk->origin[i * (size_t)nd + axis[a]];
+            if (m.o[a] < 0 || m.o[a] + m.n[a] > sk->n[axis[a]])
+                throw Error{FWI_EINVAL, "shot " + std::to_string(i) + " falls outside the stacked gradient"};
+        }
+        if (nd == 3) {
+            m.d0 = (long)sk->n[1] * sk->n[2];
+            m.d1 = sk->n[2];
+        } else {
+            m.d0 = sk->n[1];
+            m.d1 = 0;
+        }
+        out.push_back(m);
+    }
+    return out;
+}
+
+// per-shot gradients unpadded into grads[i], or (stacking) the target
+// cleared and every shot's region added in shot order
+void finish_gradients(fwi_ctx *c, std::vector<Exec> &ex, float *const *grads, const std::vector<StackMap> &smaps,
+                      const fwi_stack *sk, float *gstack, hipStream_t st)
+{
+    const size_t n = ex.size();
+    if (!sk) {
+        for (size_t i = 0; i < n; ++i) launch_unpad(c->batch[i]->gacc.p, grads[i], ex[i].padmap(), st);
+        return;
+    }
+    size_t tot = 1;
+    for (int d = 0; d < sk->ndim; ++d) tot *= (size_t)sk->n[d];
+    launch_fill_zero(gstack, tot, st);
+    for (size_t i = 0; i < n; ++i) launch_stack_add(c->batch[i]->gacc.p, gstack, smaps[i], st);
+}
+
+void key_stack(KeyBuilder &k, const fwi_stack *sk, int nshots, const float *grad)
+{
+    if (!sk) {
+        k.add('-');
+        return;
+    }
+    k.add('S').add(sk->ndim).add(sk->n).add(sk->region).add(grad);
+    k.bytes(sk->origin, sizeof(int) * (size_t)nshots * (size_t)sk->ndim);
+}
+
+}  // namespace
+
+void fwi::set_last_error(const char *msg) { g_err = msg; }
+
 // ================================================================== C ABI
 extern "C" {
 
@@ -1492,6 +1647,7 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         if (const char *e = std::getenv("FWI_RPL")) c->rpl3 = std::atoi(e) == 4 ? 4 : 2;
         if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::max(0, std::min(std::atoi(e), 2));
         if (const char *e = std::getenv("FWI_DEEP")) c->deep3 = std::atoi(e) != 0;
+        if (const char *e = std::getenv("FWI_VZ")) c->vz3 = std::atoi(e) == 2 ? 2 : 1;
         *ctx = c;
     });
 }
@@ -1709,16 +1865,17 @@ int fwi_forward_span(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_sh
     });
 }
 
-int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const float *const *models,
-                       const fwi_shot *shots, const float *const *d_obs, const fwi_ckpt_cfg *cfg,
-                       float *const *grads, double *phis, hipStream_t st)
+static int gradient_batch_impl(fwi_ctx *c, int nshots, const fwi_grid *grids, const float *const *models,
+                               const fwi_shot *shots, const float *const *d_obs, const fwi_ckpt_cfg *cfg,
+                               float *const *grads, const fwi_stack *sk, float *gstack, double *phis,
+                               hipStream_t st)
 {
     return guarded([&] {
-        if (!c || nshots < 1 || !grids || !models || !shots || !grads || !phis || !d_obs)
+        if (!c || nshots < 1 || !grids || !models || !shots || !phis || !d_obs || (sk ? !gstack : !grads))
             throw Error{FWI_EINVAL, "null argument or nshots < 1"};
         check_cfg(cfg);
         for (int i = 0; i < nshots; ++i) {
-            if (!models[i] || !grads[i] || (!d_obs[i] && shots[i].nrec > 0))
+            if (!models[i] || (!sk && !grads[i]) || (!d_obs[i] && shots[i].nrec > 0))
                 throw Error{FWI_EINVAL, "null model, gradient or data of shot " + std::to_string(i)};
             const fwi_grid &a = grids[0], &b = grids[i];
             if (b.ndim != a.ndim || b.space_order != a.space_order || b.nt != a.nt || b.dt != a.dt)
@@ -1728,6 +1885,7 @@ int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const floa
         std::vector<Setup> setups;
         setups.reserve(nshots);
         for (int i = 0; i < nshots; ++i) setups.push_back(make_setup(&grids[i], &shots[i], true));
+        const std::vector<StackMap> smaps = sk ? stack_maps(sk, setups) : std::vector<StackMap>();
         while ((int)c->batch.size() < nshots) c->batch.push_back(std::make_unique<ShotBufs>());
         const int nt = setups[0].nt;
         const auto &acts = plan_for(c, nt, cfg->nslots);
@@ -1786,7 +1944,7 @@ int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const floa
             HIPCHK(hipMemsetAsync(b->phi.p, 0, sizeof(double), st));
             e.dsim = b->dsim.p;
             e.d_obs = d_obs[i];
-            e.grad = grads[i];
+            e.grad = grads ? grads[i] : gstack;
             e.init_fields();
             e.init_adjoint();
             ex.push_back(std::move(e));
@@ -1796,16 +1954,16 @@ int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const floa
         key.add('B').add(nshots).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
         for (int i = 0; i < nshots; ++i) {
             key_shot(key, c, &grids[i], &shots[i], setups[i]);
-            key.add(models[i]).add(d_obs[i]).add(grads[i]);
+            key.add(models[i]).add(d_obs[i]).add(grads ? grads[i] : nullptr);
         }
+        key_stack(key, sk, nshots, gstack);
         c->btab.ensure(nbytes_tab);     // before any capture: it may allocate
         run_schedule(c, st, key.s, nbytes_tab, [&](char *gtab, hipStream_t rs) {
             c->btab.used = 0;
             for (auto &e : ex) e.st = rs;
             BatchExec bx{c, rs, ex, setups[0].ndim, setups[0].R, gtab ? gtab : c->btab.dev.p, gtab == nullptr, {}};
             bx.run(acts, both);
-            for (int i = 0; i < nshots; ++i)
-                launch_unpad(c->batch[i]->gacc.p, grads[i], ex[i].padmap(), rs);
+            finish_gradients(c, ex, grads, smaps, sk, gstack, rs);
             for (auto &e : ex) e.st = st;
         });
         std::vector<double> ph(nshots, 0.0);
@@ -1830,6 +1988,21 @@ int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const floa
         }
         end_call(c, st);
     });
+}
+
+int fwi_gradient_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const float *const *models,
+                       const fwi_shot *shots, const float *const *d_obs, const fwi_ckpt_cfg *cfg,
+                       float *const *grads, double *phis, hipStream_t st)
+{
+    return gradient_batch_impl(c, nshots, grids, models, shots, d_obs, cfg, grads, nullptr, nullptr, phis, st);
+}
+
+int fwi_gradient_stack(fwi_ctx *c, int nshots, const fwi_grid *grids, const float *const *models,
+                       const fwi_shot *shots, const float *const *d_obs, const fwi_ckpt_cfg *cfg,
+                       const fwi_stack *stack, float *grad, double *phis, hipStream_t st)
+{
+    if (!stack) return guarded([] { throw Error{FWI_EINVAL, "stack description is null"}; });
+    return gradient_batch_impl(c, nshots, grids, models, shots, d_obs, cfg, nullptr, stack, grad, phis, st);
 }
 
 // per-shot codec scratch regions of a batched call (offsets in words / entries)
@@ -1951,19 +2124,21 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
     });
 }
 
-int fwi_backward_batch(fwi_ctx *c, fwi_tape *t, const float *const *dd, float *const *grads, hipStream_t st)
+static int backward_batch_impl(fwi_ctx *c, fwi_tape *t, const float *const *dd, float *const *grads,
+                               const fwi_stack *sk, float *gstack, hipStream_t st)
 {
     return guarded([&] {
-        if (!c || !t || !grads || !dd) throw Error{FWI_EINVAL, "null argument"};
+        if (!c || !t || !dd || (sk ? !gstack : !grads)) throw Error{FWI_EINVAL, "null argument"};
         if (t->shots.empty()) throw Error{FWI_EINVAL, "a single-shot tape needs fwi_backward"};
         if (t->used) throw Error{FWI_EINVAL, "tape already back-propagated"};
         const int nshots = (int)t->shots.size();
         for (int i = 0; i < nshots; ++i)
-            if (!grads[i] || (!dd[i] && t->shots[i]->shot.nrec > 0))
+            if ((!sk && !grads[i]) || (!dd[i] && t->shots[i]->shot.nrec > 0))
                 throw Error{FWI_EINVAL, "null gradient or adjoint source of shot " + std::to_string(i)};
         begin_call(c, st);
         std::vector<Setup> setups;
         for (auto &sh : t->shots) setups.push_back(make_setup(&sh->grid, &sh->shot, true));
+        const std::vector<StackMap> smaps = sk ? stack_maps(sk, setups) : std::vector<StackMap>();
         while ((int)c->batch.size() < nshots) c->batch.push_back(std::make_unique<ShotBufs>());
         const int used = max_slot_used(t->acts);
         std::vector<size_t> so, cb, co;
@@ -1983,7 +2158,7 @@ int fwi_backward_batch(fwi_ctx *c, fwi_tape *t, const float *const *dd, float *c
                 e.coff = c->chunk_off.p + co[i];
             }
             setup_ckpt(e, &t->cfg, sh.pool.p, sh.cap, sh.slots.p, used);
-            e.grad = grads[i];
+            e.grad = grads ? grads[i] : gstack;
             e.adj_src = dd[i];
             e.init_fields();
             e.init_adjoint();
@@ -1997,12 +2172,24 @@ int fwi_backward_batch(fwi_ctx *c, fwi_tape *t, const float *const *dd, float *c
         c->btab.ensure(table_bytes_of(t->acts, (size_t)nshots));
         BatchExec bx{c, st, ex, setups[0].ndim, setups[0].R, c->btab.dev.p, true, {}};
         bx.run(t->acts, t->both, t->next, false);
-        for (int i = 0; i < nshots; ++i) launch_unpad(c->batch[i]->gacc.p, grads[i], ex[i].padmap(), st);
+        finish_gradients(c, ex, grads, smaps, sk, gstack, st);
         HIPCHK(hipGetLastError());
         finish_status(c, st);
         t->used = true;
         end_call(c, st);
     });
+}
+
+int fwi_backward_batch(fwi_ctx *c, fwi_tape *t, const float *const *dd, float *const *grads, hipStream_t st)
+{
+    return backward_batch_impl(c, t, dd, grads, nullptr, nullptr, st);
+}
+
+int fwi_backward_stack(fwi_ctx *c, fwi_tape *t, const float *const *dd, const fwi_stack *stack, float *grad,
+                       hipStream_t st)
+{
+    if (!stack) return guarded([] { throw Error{FWI_EINVAL, "stack description is null"}; });
+    return backward_batch_impl(c, t, dd, nullptr, stack, grad, st);
 }
 
 int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot,
@@ -2095,6 +2282,32 @@ int fwi_tape_free(fwi_tape *t)
         t->pool.release(); t->slots.release(); t->xcur.release(); t->xprev.release();
         for (auto &sh : t->shots) sh->release();
         delete t;
+    });
+}
+
+int fwi_tape_stream(fwi_tape *t, int shot, int slot, int level, void *out, size_t cap, size_t *nbytes,
+                    hipStream_t st)
+{
+    return guarded([&] {
+        if (!t || !nbytes) throw Error{FWI_EINVAL, "null argument"};
+        if (!t->cfg.compress) throw Error{FWI_EINVAL, "the tape holds exact checkpoints, not streams"};
+        if (level != 0 && level != 1) throw Error{FWI_EINVAL, "level must be 0 (u^k) or 1 (u^(k-1))"};
+        const bool batched = !t->shots.empty();
+        if (shot < 0 || shot >= (batched ? (int)t->shots.size() : 1)) throw Error{FWI_EINVAL, "no such shot"};
+        const std::vector<char> &both = batched ? t->shots[shot]->slot_both : t->slot_both;
+        const StreamSlot *slots = batched ? t->shots[shot]->slots.p : t->slots.p;
+        const unsigned char *pool = batched ? t->shots[shot]->pool.p : t->pool.p;
+        if (slot < 0 || slot >= (int)both.size()) throw Error{FWI_EINVAL, "no checkpoint in that slot"};
+        if (level == 1 && !both[slot]) throw Error{FWI_EINVAL, "that checkpoint holds u^k alone"};
+        HIPCHK(hipSetDevice(t->ctx->device));
+        StreamSlot sl{};
+        HIPCHK(hipMemcpyAsync(&sl, slots + 2 * slot + level, sizeof(sl), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (!sl.valid) throw Error{FWI_EINVAL, "no stream stored in that slot"};
+        *nbytes = (size_t)sl.bytes;
+        if (!out) return;
+        if (cap < sl.bytes) throw Error{FWI_ECAPACITY, "output buffer smaller than the stream"};
+        HIPCHK(hipMemcpyAsync(out, pool + sl.offset, (size_t)sl.bytes, hipMemcpyDeviceToDevice, st));
     });
 }
 
@@ -2297,62 +2510,31 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         HIPCHK(hipSetDevice(c->device));
         Exec ex{c, make_setup(g, shot, true), st, m, shot};
         ensure_fields(&c->sb, ex.S);
-        const size_t arena_bytes = c->sb.arena.n;
         std::vector<fwi_ctx::Shape> cands;
         const int xcs3[] = {8, 16, 32, 64};
         const int xcs2[] = {4, 8, 16, 32, 64};
         if (ex.S.ndim == 3) {
             for (int xc : xcs3) {
                 for (int remap : {0, 1}) {
-                    cands.push_back({xc, 2, remap, 0});
-                    cands.push_back({xc, 4, remap, 0});
-                    cands.push_back({xc, 2, remap, 1});
+                    cands.push_back({xc, 2, remap, 0, 1});
+                    cands.push_back({xc, 4, remap, 0, 1});
+                    cands.push_back({xc, 2, remap, 1, 1});
                 }
-                cands.push_back({xc, 2, 2, 0});
+                cands.push_back({xc, 2, 2, 0, 1});
+                for (int remap : {0, 1, 2}) {
+                    cands.push_back({xc, 2, remap, 0, 2});
+                    cands.push_back({xc, 4, remap, 0, 2});
+                }
             }
+            for (int remap : {0, 1, 2}) cands.push_back({128, 4, remap, 0, 2});
         } else {
-            for (int xc : xcs2) cands.push_back({xc, 2, 0, 0});
+            for (int xc : xcs2) cands.push_back({xc, 2, 0, 0, 1});
         }
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        // steps alternate the buffer roles the way the sweeps rotate them
-        auto time_it = [&](const fwi_ctx::Shape &sh, bool adj) {
-            StepParams p = ex.params();
-            p.xchunk = sh.xchunk;
-            p.rpl = sh.rpl;
-            p.remap = sh.remap;
-            p.deep = sh.deep;
-            auto one = [&](int i) {
-                float *a = (i & 1) ? c->sb.fb.p : c->sb.fa.p, *b = (i & 1) ? c->sb.fa.p : c->sb.fb.p;
-                if (adj) {
-                    float *l1 = (i & 1) ? c->sb.lb.p : c->sb.la.p, *l2 = (i & 1) ? c->sb.la.p : c->sb.lb.p;
-                    p.u1 = l1; p.u2 = l2; p.out = l2; p.uk = a; p.g = c->sb.gacc.p;
-                } else {
-                    p.u1 = a; p.u2 = b; p.out = b; p.wav = shot->wavelet; p.step = 0;
-                }
-                launch_step(p, ex.S.ndim, ex.S.R, adj, st);
-            };
-            one(0);                                              // warm-up
-            HIPCHK(hipEventRecord(e0, st));
-            for (int i = 0; i < steps; ++i) one(i + 1);
-            HIPCHK(hipEventRecord(e1, st));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            return (double)ms / steps;
-        };
-        // the timed fields hold data (copies of the coefficient field), not
-        // zeros: all-zero traffic ran measurably faster and ranked the
-        // shapes differently from a real sweep
-        auto reset = [&] {
-            HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, arena_bytes, st));
-            ex.init_fields();
-            const size_t ne = c->sb.padded_elems;
-            for (float *f : {c->sb.fa.p, c->sb.fb.p, c->sb.la.p, c->sb.lb.p, c->sb.gacc.p})
-                launch_copy(f, c->sb.coef.p, ne, st);
-        };
-        reset();
+        auto time_it = [&](const fwi_ctx::Shape &sh, bool adj) { return time_shape(c, ex, shot, sh, adj, steps, e0, e1, st); };
+        fill_tuning_fields(c, ex, st);
         // screen every candidate, then re-time the best eight of each sweep
         // three more times, interleaved
         std::vector<std::pair<double, size_t>> rf, ra;
@@ -2381,7 +2563,7 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         auto pick = [&](const std::vector<std::pair<double, size_t>> &r) {
             auto key = [&](size_t j) {
                 const fwi_ctx::Shape &h = cands[r[j].second];
-                return std::make_tuple(h.deep == 0, h.remap == 2, h.remap != 1, h.xchunk);
+                return std::make_tuple(h.deep == 0, h.vz == 2, h.remap == 2, h.remap != 1, h.xchunk);
             };
             size_t k = 0;
             for (size_t j = 1; j < r.size(); ++j)
@@ -2400,20 +2582,61 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         out->adj_xchunk = sa.xchunk; out->adj_rows_per_lane = sa.rpl; out->adj_xcd_order = sa.remap;
         out->fwd_deep = sf.deep;
         out->adj_deep = sa.deep;
+        out->fwd_vz = sf.vz;
+        out->adj_vz = sa.vz;
         out->fwd_ms = bf;
         out->adj_ms = ba;
-        HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, arena_bytes, st));
+        HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, c->sb.arena.n, st));
         HIPCHK(hipStreamSynchronize(st));
     });
 }
 
-int fwi_bandwidth_probe(const float *a, const float *b, const float *c, float *d, size_t n, int nsrc,
-                        hipStream_t st)
+int fwi_time_shape(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *shot, const int shape[5],
+                   int steps, double *fwd_ms, double *adj_ms, hipStream_t st)
 {
     return guarded([&] {
-        if (!a || !d || (nsrc == 3 && (!b || !c)) || (nsrc != 1 && nsrc != 3))
-            throw Error{FWI_EINVAL, "bad arguments"};
-        launch_probe(a, b, c, d, n, nsrc, st);
+        if (!c || !m || !shape || !fwd_ms || !adj_ms) throw Error{FWI_EINVAL, "null argument"};
+        if (steps < 1) throw Error{FWI_EINVAL, "steps must be >= 1"};
+        HIPCHK(hipSetDevice(c->device));
+        Exec ex{c, make_setup(g, shot, true), st, m, shot};
+        const fwi_ctx::Shape sh{shape[0], shape[1], shape[2], shape[3], shape[4]};
+        if (!valid_shape(ex.S.ndim, sh)) throw Error{FWI_EINVAL, "invalid launch shape"};
+        ensure_fields(&c->sb, ex.S);
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        fill_tuning_fields(c, ex, st);
+        *fwd_ms = time_shape(c, ex, shot, sh, false, steps, e0, e1, st);
+        *adj_ms = time_shape(c, ex, shot, sh, true, steps, e0, e1, st);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, c->sb.arena.n, st));
+        HIPCHK(hipStreamSynchronize(st));
+    });
+}
+
+int fwi_bandwidth_probe(const float *const *src, int nsrc, float *const *dst, int ndst, size_t n,
+                        int width, int grid, hipStream_t st)
+{
+    return guarded([&] {
+        if (!src || !dst || nsrc < 1 || nsrc > 5 || ndst < 1 || ndst > 2)
+            throw Error{FWI_EINVAL, "need 1..5 sources and 1..2 destinations"};
+        if (width != 4 && width != 8 && width != 16) throw Error{FWI_EINVAL, "width must be 4, 8 or 16 bytes"};
+        if (n % (size_t)(width / 4) != 0) throw Error{FWI_EINVAL, "n must be a multiple of the access width"};
+        if (grid < 0 || grid > (1 << 20)) throw Error{FWI_EINVAL, "grid must be in 0..2^20 workgroups"};
+        if (grid == 0 && n / (size_t)(width / 4) > ((size_t)1 << 31) * 255)
+            throw Error{FWI_EINVAL, "arrays too long for a one-vector-per-lane grid"};
+        ProbeArgs a{};
+        for (int i = 0; i < nsrc; ++i) {
+            if (!src[i] || (uintptr_t)src[i] % (size_t)width) throw Error{FWI_EINVAL, "null or misaligned source"};
+            a.src[i] = src[i];
+        }
+        for (int j = 0; j < ndst; ++j) {
+            if (!dst[j] || (uintptr_t)dst[j] % (size_t)width) throw Error{FWI_EINVAL, "null or misaligned destination"};
+            a.dst[j] = dst[j];
+        }
+        a.n = n;
+        launch_probe(a, nsrc, ndst, width, grid, st);
         HIPCHK(hipGetLastError());
     });
 }

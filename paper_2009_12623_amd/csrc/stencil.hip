@@ -52,6 +52,13 @@ __device__ __forceinline__ void st(float *base, unsigned off, float v)
     *(float *)((char *)base + off) = v;
 }
 
+// streaming store: the 3D levels and gradient are far larger than the
+// caches and are next read a whole step later
+__device__ __forceinline__ void stnt(float *base, unsigned off, float v)
+{
+    __builtin_nontemporal_store(v, (float *)((char *)base + off));
+}
+
 // new level from the Laplacian and the point values
 template <bool ADJ>
 __device__ __forceinline__ float update(const StepParams &p, int dsum, bool is_src, float c,
@@ -230,8 +237,8 @@ __device__ __forceinline__ void step3d_body(const StepParams &p, int hw, int ntz
                                  (tile[cur][r][tz + R - k] + tile[cur][r][tz + R + k]));
             const unsigned o = pa + j * rstep;
             const float ov = update<ADJ>(p, dx * dx + dyz[j], o == srcb, c, lap, u2v[j], bv[j]);
-            st(p.out, o, ov);
-            if (ADJ) st(p.g, o, gv[j] - ukv[j] * (ov - 2.0f * c + u2v[j]) * p.inv_dt2);
+            stnt(p.out, o, ov);
+            if (ADJ) stnt(p.g, o, gv[j] - ukv[j] * (ov - 2.0f * c + u2v[j]) * p.inv_dt2);
         }
         if (!nxt) break;
         // ---- advance the queues and stage plane x+1 in the other buffer
@@ -390,8 +397,8 @@ __device__ __forceinline__ void step3d_body_deep(const StepParams &p, int hw, in
                                  (tile[cur][r][tz + R - k] + tile[cur][r][tz + R + k]));
             const unsigned o = pa + j * rstep;
             const float ov = update<ADJ>(p, dx * dx + dyz[j], o == srcb, c, lap, u2v[j], bv[j]);
-            st(p.out, o, ov);
-            if (ADJ) st(p.g, o, gv[j] - ukv[j] * (ov - 2.0f * c + u2v[j]) * p.inv_dt2);
+            stnt(p.out, o, ov);
+            if (ADJ) stnt(p.g, o, gv[j] - ukv[j] * (ov - 2.0f * c + u2v[j]) * p.inv_dt2);
         }
         if (x + 1 >= xe) break;
         // ---- advance the queues and stage plane x+1 (loads issued one plane ago)
@@ -429,6 +436,213 @@ __global__ __launch_bounds__(TILE_Z * 8)
 void step3d_deep_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
 {
     step3d_body_deep<R, ADJ, 2>(p, blockIdx.x, ntz, nty, nwg, launched);
+}
+
+// ----------------------------------------------------- 3D, 8-byte lanes
+// Same streaming scheme with two consecutive z points per lane: a wave
+// covers 128 z points, every global access moves 8 bytes per lane and the
+// z neighbours come from 8-byte LDS reads.  The tile is 128 (z) x 8 RPL (y);
+// wider z tiles halve the z-halo lines per point and the wider accesses keep
+// more bytes in flight per load instruction.  Lanes whose second point lies
+// past the field end load padding (zero) and store only the first point.
+typedef float f2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ f2v ld2(const float *base, unsigned off)
+{
+    return *(const f2v *)((const char *)base + off);
+}
+
+__device__ __forceinline__ f2v ldnt2(const float *base, unsigned off)
+{
+    return __builtin_nontemporal_load((const f2v *)((const char *)base + off));
+}
+
+__device__ __forceinline__ void st2(float *base, unsigned off, f2v v, bool both)
+{
+    if (both) __builtin_nontemporal_store(v, (f2v *)((char *)base + off));
+    else __builtin_nontemporal_store(v.x, (float *)((char *)base + off));
+}
+
+template <int R, bool ADJ, int RPL>
+__device__ __forceinline__ void step3w_body(const StepParams &p, int hw, int ntz, int nty, int nwg,
+                                            int launched)
+{
+    constexpr int ROWS = 8 * RPL;
+    constexpr int TZ = TILE_ZW;
+    constexpr int WL = TZ + 2 * R;                 // LDS row (floats)
+    constexpr int HP = R / 2;                      // z-halo pairs per side
+    __shared__ __attribute__((aligned(16))) float tile[2][ROWS + 2 * R][WL];
+    if (hw >= launched) {                          // receiver sampling blocks
+        gather_block(p, hw - launched);
+        return;
+    }
+    int tzi, tyi, txi;
+    bool valid;
+    tile_coords(hw, nwg, ntz, nty, p.remap, tzi, tyi, txi, valid);
+    if (!valid) return;                            // whole workgroup, before any barrier
+
+    const int tz = threadIdx.x;
+    const int ty = threadIdx.y;
+    const int z0 = tzi * TZ;
+    const int y0 = tyi * ROWS;
+    const int za = z0 + 2 * tz;                    // the lane's points za, za + 1
+    const int xb = txi * p.xchunk;
+    const int xe = min(xb + p.xchunk, p.nx);
+    const bool zin = za < p.nz;
+    const bool both = za + 1 < p.nz;
+    const unsigned bsx = 4u * (unsigned)p.psx, bsy = 4u * (unsigned)p.psy;
+    const unsigned org = 4u * (unsigned)p.origin;
+    const unsigned srcb = p.src >= 0 ? org + 4u * (unsigned)p.src : 0xFFFFFFFFu;
+    const float *__restrict__ u1 = p.u1;
+    const float *__restrict__ u2 = p.u2;
+    const float *__restrict__ bq = p.b;
+    const bool hy = ty < R;
+    const unsigned hy_top = org + (unsigned)(y0 - R + ty) * bsy + 4u * za;
+    const unsigned hy_bot = org + (unsigned)(y0 + ROWS + ty) * bsy + 4u * za;
+    // z halo: lanes 0..HP-1 load the pairs left of the tile, lanes
+    // 64-HP..63 the pairs right of it
+    const bool hzl = tz < HP, hzr = tz >= 64 - HP;
+    const bool hz = hzl || hzr;
+    const int hzz = hzl ? z0 - R + 2 * tz : z0 + TZ + 2 * (tz - (64 - HP));
+    const int hcol = hzl ? 2 * tz : TZ + R + 2 * (tz - (64 - HP));
+    const int ccol = R + 2 * tz;                   // LDS column of za
+    const unsigned col0 = org + (unsigned)(y0 + ty) * bsy + 4u * za;
+    const unsigned hz0 = org + (unsigned)(y0 + ty) * bsy + 4u * (unsigned)hzz;
+    const unsigned rstep = 8u * bsy;
+    const int dza = layer_depth(za, p.nz, p.nbl), dzb = layer_depth(za + 1, p.nz, p.nbl);
+    bool act[RPL];
+    int dya[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+        const int y = y0 + ty + 8 * j;
+        act[j] = zin && y < p.ny;
+        dya[j] = layer_depth(y, p.ny, p.nbl);
+        dya[j] *= dya[j];
+    }
+
+    f2v q[RPL][2 * R + 1];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j)
+#pragma unroll
+        for (int i = 0; i <= 2 * R; ++i) q[j][i] = ld2(u1, col0 + j * rstep + (unsigned)(xb - R + i) * bsx);
+    {
+        const unsigned pl = (unsigned)xb * bsx;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) *(f2v *)&tile[0][ty + 8 * j + R][ccol] = q[j][R];
+        if (hy) {
+            *(f2v *)&tile[0][ty][ccol] = ld2(u1, pl + hy_top);
+            *(f2v *)&tile[0][ty + ROWS + R][ccol] = ld2(u1, pl + hy_bot);
+        }
+        if (hz) {
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) *(f2v *)&tile[0][ty + 8 * j + R][hcol] = ld2(u1, pl + hz0 + j * rstep);
+        }
+    }
+    unsigned pa = col0 + (unsigned)xb * bsx;
+    const f2v zero2 = {0.f, 0.f};
+    f2v u2v[RPL], bv[RPL], ukv[RPL], gv[RPL];
+#pragma unroll
+    for (int j = 0; j < RPL; ++j) {
+        const unsigned o = pa + j * rstep;
+        u2v[j] = act[j] ? ldnt2(u2, o) : zero2;
+        bv[j] = act[j] ? ldnt2(bq, o) : zero2;
+        ukv[j] = (ADJ && act[j]) ? ldnt2(p.uk, o) : zero2;
+        gv[j] = (ADJ && act[j]) ? ldnt2(p.g, o) : zero2;
+    }
+    __syncthreads();
+
+    for (int x = xb; x < xe; ++x) {
+        const int cur = (x - xb) & 1;
+        const bool nxt = x + 1 < xe;
+        f2v nq[RPL], nhz[RPL], nu2[RPL], nb_[RPL], nuk[RPL], ng[RPL];
+        f2v nht = zero2, nhb = zero2;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) nq[j] = nhz[j] = nu2[j] = nb_[j] = nuk[j] = ng[j] = zero2;
+        if (nxt) {
+            const unsigned pl = (unsigned)(x + 1) * bsx;
+            if (hy) {
+                nht = ld2(u1, pl + hy_top);
+                nhb = ld2(u1, pl + hy_bot);
+            }
+            if (hz) {
+#pragma unroll
+                for (int j = 0; j < RPL; ++j) nhz[j] = ld2(u1, pl + hz0 + j * rstep);
+            }
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) nq[j] = ld2(u1, col0 + j * rstep + pl + (unsigned)R * bsx);
+#pragma unroll
+            for (int j = 0; j < RPL; ++j) {
+                const unsigned na = pa + bsx + j * rstep;
+                if (act[j]) {
+                    nu2[j] = ldnt2(u2, na);
+                    nb_[j] = ldnt2(bq, na);
+                    if (ADJ) { nuk[j] = ldnt2(p.uk, na); ng[j] = ldnt2(p.g, na); }
+                }
+            }
+        }
+        const int dx = layer_depth(x, p.nx, p.nbl);
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+            if (!act[j]) continue;
+            const int r = ty + 8 * j + R;
+            const f2v c = q[j][R];
+            // zr[i] = tile row r at column ccol - R + i, i = 0..2R+1
+            float zr[2 * R + 2];
+#pragma unroll
+            for (int m = 0; m <= R; ++m) {
+                const f2v v = m == HP ? c : *(const f2v *)&tile[cur][r][ccol - R + 2 * m];
+                zr[2 * m] = v.x;
+                zr[2 * m + 1] = v.y;
+            }
+            float la = 3.0f * p.w[0] * c.x, lb = 3.0f * p.w[0] * c.y;
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                const f2v ym = *(const f2v *)&tile[cur][r - k][ccol];
+                const f2v yp = *(const f2v *)&tile[cur][r + k][ccol];
+                la += p.w[k] * ((q[j][R - k].x + q[j][R + k].x) + (ym.x + yp.x) + (zr[R - k] + zr[R + k]));
+                lb += p.w[k] * ((q[j][R - k].y + q[j][R + k].y) + (ym.y + yp.y) +
+                                (zr[R + 1 - k] + zr[R + 1 + k]));
+            }
+            const unsigned o = pa + j * rstep;
+            const int dxy = dx * dx + dya[j];
+            f2v ov;
+            ov.x = update<ADJ>(p, dxy + dza * dza, o == srcb, c.x, la, u2v[j].x, bv[j].x);
+            ov.y = update<ADJ>(p, dxy + dzb * dzb, o + 4u == srcb, c.y, lb, u2v[j].y, bv[j].y);
+            st2(p.out, o, ov, both);
+            if (ADJ) {
+                f2v gn;
+                gn.x = gv[j].x - ukv[j].x * (ov.x - 2.0f * c.x + u2v[j].x) * p.inv_dt2;
+                gn.y = gv[j].y - ukv[j].y * (ov.y - 2.0f * c.y + u2v[j].y) * p.inv_dt2;
+                st2(p.g, o, gn, both);
+            }
+        }
+        if (!nxt) break;
+        const int nb = cur ^ 1;
+#pragma unroll
+        for (int j = 0; j < RPL; ++j) {
+#pragma unroll
+            for (int i = 0; i < 2 * R; ++i) q[j][i] = q[j][i + 1];
+            q[j][2 * R] = nq[j];
+            *(f2v *)&tile[nb][ty + 8 * j + R][ccol] = q[j][R];
+            if (hz) *(f2v *)&tile[nb][ty + 8 * j + R][hcol] = nhz[j];
+            u2v[j] = nu2[j];
+            bv[j] = nb_[j];
+            if (ADJ) { ukv[j] = nuk[j]; gv[j] = ng[j]; }
+        }
+        if (hy) {
+            *(f2v *)&tile[nb][ty][ccol] = nht;
+            *(f2v *)&tile[nb][ty + ROWS + R][ccol] = nhb;
+        }
+        pa += bsx;
+        __syncthreads();
+    }
+}
+
+template <int R, bool ADJ, int RPL>
+__global__ __launch_bounds__(64 * 8)
+void step3w_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
+{
+    step3w_body<R, ADJ, RPL>(p, blockIdx.x, ntz, nty, nwg, launched);
 }
 
 // ------------------------------------------------------------------- 2D
@@ -568,7 +782,14 @@ void launch_r(const StepParams &p, int ndim, hipStream_t st)
     e.p = p;
     const int total = step_geometry(e, ndim, ADJ);
     if (ndim == 3) {
-        if (p.deep)
+        if (p.vz == 2) {
+            if (p.rpl == 4)
+                hipLaunchKernelGGL((step3w_kernel<R, ADJ, 4>), dim3(total), dim3(64, 8, 1), 0, st,
+                                   p, e.ntz, e.nty, e.nwg, e.launched);
+            else
+                hipLaunchKernelGGL((step3w_kernel<R, ADJ, 2>), dim3(total), dim3(64, 8, 1), 0, st,
+                                   p, e.ntz, e.nty, e.nwg, e.launched);
+        } else if (p.deep)
             hipLaunchKernelGGL((step3d_deep_kernel<R, ADJ>), dim3(total), dim3(TILE_Z, 8, 1), 0, st,
                                p, e.ntz, e.nty, e.nwg, e.launched);
         else if (p.rpl == 4)
@@ -592,18 +813,56 @@ void launch_batch_r(const BatchEntry *tab, const BatchIndex &ix, int nshot, int 
 }
 
 // ------------------------------------------------------------- small kernels
-// streams with the stencil's access width (one float per lane): dst = src
-// (nsrc = 1) or dst = src + src2 + src3 (nsrc = 3)
-__global__ __launch_bounds__(256) void probe_kernel(const float *__restrict__ a, const float *__restrict__ b,
-                                                    const float *__restrict__ c, float *__restrict__ d,
-                                                    size_t n, int nsrc)
+// Streaming probe: dst_j = sum of the nsrc sources (j < ND), W floats per
+// lane per access (4, 8 or 16 bytes), non-temporal loads and stores.  With
+// flat = 1 every lane moves one vector and the grid covers the arrays (many
+// short workgroups: the fastest streaming form measured on this part);
+// otherwise `gridDim.x` workgroups stride over the arrays with four
+// accesses per lane in flight.  Measures the practical HBM ceiling of a
+// stream mix and serves as the kernel of known traffic for counter
+// calibration.
+template <int W>
+struct VecOf;
+template <> struct VecOf<1> { typedef float T; };
+template <> struct VecOf<2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<4> { typedef float T __attribute__((ext_vector_type(4))); };
+
+template <int W, int NS, int ND>
+__global__ __launch_bounds__(256) void probe_kernel(ProbeArgs a, int flat)
 {
+    typedef typename VecOf<W>::T V;
+    const size_t nv = a.n / W;
     size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
-    const size_t step = (size_t)gridDim.x * 256;
-    if (nsrc == 1)
-        for (; i < n; i += step) d[i] = a[i];
-    else
-        for (; i < n; i += step) d[i] = a[i] + b[i] + c[i];
+    if (flat) {
+        if (i >= nv) return;
+        V s = __builtin_nontemporal_load(&((const V *)a.src[0])[i]);
+#pragma unroll
+        for (int k = 1; k < NS; ++k) s += __builtin_nontemporal_load(&((const V *)a.src[k])[i]);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) __builtin_nontemporal_store(s, &((V *)a.dst[j])[i]);
+        return;
+    }
+    const size_t stride = (size_t)gridDim.x * 256;
+    for (; i + 3 * stride < nv; i += 4 * stride) {
+        V s[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] = __builtin_nontemporal_load(&((const V *)a.src[0])[i + u * stride]);
+#pragma unroll
+        for (int k = 1; k < NS; ++k)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) s[u] += __builtin_nontemporal_load(&((const V *)a.src[k])[i + u * stride]);
+#pragma unroll
+        for (int j = 0; j < ND; ++j)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(s[u], &((V *)a.dst[j])[i + u * stride]);
+    }
+    for (; i < nv; i += stride) {
+        V s = __builtin_nontemporal_load(&((const V *)a.src[0])[i]);
+#pragma unroll
+        for (int k = 1; k < NS; ++k) s += __builtin_nontemporal_load(&((const V *)a.src[k])[i]);
+#pragma unroll
+        for (int j = 0; j < ND; ++j) __builtin_nontemporal_store(s, &((V *)a.dst[j])[i]);
+    }
 }
 
 // p[0..n) = 0 and dst = src (n floats): kernels rather than memset/memcpy
@@ -653,6 +912,20 @@ __global__ void unpad_kernel(const float *acc, float *g, PadMap pm)
         const size_t z = i % pm.nz, r = i / pm.nz;
         const size_t y = r % pm.ny, x = r / pm.ny;
         g[i] = acc[pm.origin + x * pm.sx + y * pm.sy + z];
+    }
+}
+
+// one shot's gradient region added into the stacked gradient
+__global__ void stack_add_kernel(const float *acc, float *dst, StackMap sm)
+{
+    const size_t n = (size_t)sm.n[0] * sm.n[1] * sm.n[2];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const size_t z = i % sm.n[2], r = i / sm.n[2];
+        const size_t y = r % sm.n[1], x = r / sm.n[1];
+        const size_t src = sm.pm.origin + (sm.r[0] + x) * sm.pm.sx + (sm.r[1] + y) * sm.pm.sy + sm.r[2] + z;
+        const size_t d = (sm.o[0] + x) * sm.d0 + (sm.o[1] + y) * sm.d1 + sm.o[2] + z;
+        dst[d] += acc[src];
     }
 }
 
@@ -725,7 +998,8 @@ int step_geometry(BatchEntry &e, int ndim, bool adjoint)
     const bool gather = !adjoint && p.grow && p.nrec > 0;
     if (ndim == 3) {
         const int rows = 8 * p.rpl;
-        e.ntz = (p.nz + TILE_Z - 1) / TILE_Z;
+        const int tzw = p.vz == 2 ? TILE_ZW : TILE_Z;
+        e.ntz = (p.nz + tzw - 1) / tzw;
         e.nty = (p.ny + rows - 1) / rows;
         e.nwg = e.ntz * e.nty * nchunk;
         const int unit = p.remap == 2 ? 8 * e.ntz : 8;
@@ -779,10 +1053,33 @@ static int grid_for(size_t n)
     return (int)(blocks > 65536 ? 65536 : blocks);
 }
 
-void launch_probe(const float *a, const float *b, const float *c, float *d, size_t n, int nsrc,
-                  hipStream_t st)
+template <int W, int NS>
+static void probe_nd(const ProbeArgs &a, int nd, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL(probe_kernel, dim3(256 * 32), dim3(256), 0, st, a, b, c, d, n, nsrc);
+    // grid 0: one vector per lane over the whole arrays
+    const int flat = grid == 0;
+    const size_t g = flat ? (a.n / W + 255) / 256 : (size_t)grid;
+    if (nd == 1) hipLaunchKernelGGL((probe_kernel<W, NS, 1>), dim3((unsigned)g), dim3(256), 0, st, a, flat);
+    else hipLaunchKernelGGL((probe_kernel<W, NS, 2>), dim3((unsigned)g), dim3(256), 0, st, a, flat);
+}
+
+template <int W>
+static void probe_w(const ProbeArgs &a, int ns, int nd, int grid, hipStream_t st)
+{
+    switch (ns) {
+    case 1: probe_nd<W, 1>(a, nd, grid, st); break;
+    case 2: probe_nd<W, 2>(a, nd, grid, st); break;
+    case 3: probe_nd<W, 3>(a, nd, grid, st); break;
+    case 4: probe_nd<W, 4>(a, nd, grid, st); break;
+    default: probe_nd<W, 5>(a, nd, grid, st); break;
+    }
+}
+
+void launch_probe(const ProbeArgs &a, int nsrc, int ndst, int width, int grid, hipStream_t st)
+{
+    if (width == 16) probe_w<4>(a, nsrc, ndst, grid, st);
+    else if (width == 8) probe_w<2>(a, nsrc, ndst, grid, st);
+    else probe_w<1>(a, nsrc, ndst, grid, st);
 }
 
 void launch_fill_zero(float *p, size_t n, hipStream_t st)
@@ -805,6 +1102,12 @@ void launch_unpad(const float *acc, float *g, const PadMap &pm, hipStream_t st)
 {
     hipLaunchKernelGGL(unpad_kernel, dim3(grid_for((size_t)pm.nx * pm.ny * pm.nz)), dim3(256), 0, st, acc,
                        g, pm);
+}
+
+void launch_stack_add(const float *acc, float *dst, const StackMap &sm, hipStream_t st)
+{
+    const size_t n = (size_t)sm.n[0] * sm.n[1] * sm.n[2];
+    if (n) hipLaunchKernelGGL(stack_add_kernel, dim3(grid_for(n)), dim3(256), 0, st, acc, dst, sm);
 }
 
 void launch_pad(const float *f, float *dst, const PadMap &pm, hipStream_t st)
@@ -840,7 +1143,7 @@ Padded make_padded(int ndim, const int *comp)
     f.ny = ndim == 3 ? comp[1] : 1;
     f.nz = ndim == 3 ? comp[2] : comp[1];
     f.px = f.nx + 2 * PAD_X;
-    const int tz = ndim == 3 ? TILE_Z : TILE_Z2;
+    const int tz = ndim == 3 ? TILE_ZW : TILE_Z2;
     f.pz = PAD_Z0 + (long)((f.nz + tz - 1) / tz) * tz + PAD_Z0;
     if (ndim == 3) {
         f.py = (long)((f.ny + TILE_Y - 1) / TILE_Y) * TILE_Y + 2 * PAD_Y;

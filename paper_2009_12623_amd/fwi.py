@@ -8,8 +8,9 @@ norm of the first iteration's gradient.  The paper does not state its step
 rule; here the first trial step is sized so that its largest update is
 ``step`` times the smallest squared slowness of the starting model, and a
 step that does not lower the objective is halved (up to ``backtracks``
-times, each trial a forward-only evaluation); the accepted length carries
-over to the next iteration.  Updates are projected onto the velocity bounds.
+times, each trial a forward-only evaluation; after the last halving the
+trial is taken as it is); the accepted length carries over to the next
+iteration.  Updates are projected onto the velocity bounds.
 ``mask`` (same shape as the model, optional) multiplies the gradient, e.g.
 to keep the absorbing layer and the acquisition rows fixed.
 """
@@ -70,10 +71,10 @@ def run_fwi(ctx, shots, m0, wavelet, d_obs, iterations=30, nslots=40, compress=T
                 break
             alpha = step * float(m0.abs().min()) / float((g / scale).abs().max())
         d = g / scale
-        for _ in range(backtracks + 1):
+        for k in range(backtracks + 1):
             trial = project(m - alpha * d)
             phi_t = objective(ctx, trial, shots, wavelet, d_obs)
-            if phi_t < phi:
+            if phi_t < phi or k == backtracks:
                 break
             alpha *= 0.5
         m = trial

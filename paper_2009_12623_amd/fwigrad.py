@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfwigrad.so")
 
 FWI_OK, FWI_EINVAL, FWI_ENOMEM, FWI_ECAPACITY = 0, -1, -2, -3
-FWI_ECORRUPT, FWI_ENONFINITE, FWI_EUNSTABLE, FWI_EHIP = -4, -5, -6, -7
+FWI_ECORRUPT, FWI_ENONFINITE, FWI_EUNSTABLE, FWI_EHIP, FWI_ERANGE = -4, -5, -6, -7, -8
 ADVANCE, TAKESHOT, RESTORE, REVERSE, FREE = range(5)
 _OPNAME = {ADVANCE: "advance", TAKESHOT: "takeshot", RESTORE: "restore",
            REVERSE: "reverse", FREE: "free"}
@@ -58,7 +58,23 @@ class fwi_tune_result(ctypes.Structure):
                 ("fwd_rows_per_lane", ctypes.c_int), ("fwd_xcd_order", ctypes.c_int),
                 ("adj_xchunk", ctypes.c_int), ("adj_rows_per_lane", ctypes.c_int),
                 ("adj_xcd_order", ctypes.c_int), ("fwd_ms", ctypes.c_double),
-                ("adj_ms", ctypes.c_double), ("fwd_deep", ctypes.c_int), ("adj_deep", ctypes.c_int)]
+                ("adj_ms", ctypes.c_double), ("fwd_deep", ctypes.c_int), ("adj_deep", ctypes.c_int),
+                ("fwd_vz", ctypes.c_int), ("adj_vz", ctypes.c_int)]
+
+
+class fwi_stack(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_int * 3), ("region", ctypes.c_int),
+                ("origin", ctypes.c_void_p)]
+
+
+def make_stack(dims, region, origins):
+    """fwi_stack for target dims, region (0 whole computational grids, 1
+    physical parts) and per-shot origins; returns (struct, keep-alive)"""
+    nd = len(dims)
+    org = (ctypes.c_int * (len(origins) * nd))(*[int(v) for o in origins for v in o])
+    st = fwi_stack(nd, (ctypes.c_int * 3)(*(list(dims) + [1] * (3 - nd))), int(region),
+                   ctypes.cast(org, ctypes.c_void_p))
+    return st, org
 
 
 class fwi_action(ctypes.Structure):
@@ -73,7 +89,8 @@ EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_s
            "ckpt_decompress", "fwi_revolve_plan", "fwi_bandwidth_probe", "fwi_autotune", "fwi_ckpt_pool_bytes", "fwi_forward_state", "fwi_gradient_batch", "fwi_ctx_set_graphs",
            "ckpt_compress_view", "ckpt_decompress_view", "fwi_forward_ckpt_batch",
            "fwi_backward_batch", "fwi_gradient_subsampled", "fwi_forward_span",
-           "fwi_ctx_set_overlap"]
+           "fwi_ctx_set_overlap", "fwi_time_shape", "fwi_tape_stream", "fwi_gradient_stack",
+           "fwi_backward_stack"]
 
 
 def lib():
@@ -112,7 +129,7 @@ def lib():
     L.ckpt_decompress.argtypes = [P, P, ctypes.c_size_t, P, I, ctypes.POINTER(ctypes.c_int), P]
     L.fwi_revolve_plan.argtypes = [I, I, ctypes.POINTER(fwi_action), I, ctypes.POINTER(I),
                                    ctypes.POINTER(ctypes.c_longlong)]
-    L.fwi_bandwidth_probe.argtypes = [P, P, P, P, ctypes.c_size_t, I, P]
+    L.fwi_bandwidth_probe.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(P), I, ctypes.c_size_t, I, I, P]
     L.fwi_forward_state.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), P, P,
                                     P, P]
     L.fwi_gradient_batch.argtypes = [P, I, ctypes.POINTER(fwi_grid), ctypes.POINTER(P),
@@ -131,6 +148,15 @@ def lib():
                                       ctypes.POINTER(ctypes.c_size_t)]
     L.fwi_autotune.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), I,
                                ctypes.POINTER(fwi_tune_result), P]
+    L.fwi_gradient_stack.argtypes = [P, I, ctypes.POINTER(fwi_grid), ctypes.POINTER(P),
+                                     ctypes.POINTER(fwi_shot), ctypes.POINTER(P),
+                                     ctypes.POINTER(fwi_ckpt_cfg), ctypes.POINTER(fwi_stack), P,
+                                     ctypes.POINTER(ctypes.c_double), P]
+    L.fwi_backward_stack.argtypes = [P, P, ctypes.POINTER(P), ctypes.POINTER(fwi_stack), P, P]
+    L.fwi_tape_stream.argtypes = [P, I, I, I, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]
+    L.fwi_time_shape.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot),
+                                 ctypes.POINTER(ctypes.c_int), I, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double), P]
     _lib = L
     return L
 
@@ -156,9 +182,16 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def fwi_bandwidth_probe(a, d, b=None, c=None):
-    nsrc = 1 if b is None else 3
-    check(lib().fwi_bandwidth_probe(_ptr(a), _ptr(b), _ptr(c), _ptr(d), a.numel(), nsrc, _stream()))
+def fwi_bandwidth_probe(srcs, dsts, width=4, grid=8192):
+    """dst = sum(srcs) for every dst; width bytes per lane per access."""
+    n = srcs[0].numel()
+    if any(t.numel() != n for t in list(srcs) + list(dsts)):
+        raise ValueError("all probe arrays need the same length")
+    sp = (ctypes.c_void_p * len(srcs))(*[t.data_ptr() for t in srcs])
+    dp = (ctypes.c_void_p * len(dsts))(*[t.data_ptr() for t in dsts])
+    for t in list(srcs) + list(dsts):
+        _ptr(t)
+    check(lib().fwi_bandwidth_probe(sp, len(srcs), dp, len(dsts), n, int(width), int(grid), _stream()))
 
 
 # ---------------------------------------------------------- host-only calls
@@ -225,6 +258,17 @@ class Tape:
     def __init__(self, ctx, handle, shot_args, m):
         self.ctx, self.handle, self.shot_args, self.m = ctx, handle, shot_args, m
 
+    def stream(self, slot: int, level: int = 0, shot: int = 0) -> torch.Tensor:
+        """fwi_tape_stream: the stored codec stream of one checkpoint level
+        (uint8 device tensor)"""
+        n = ctypes.c_size_t()
+        check(lib().fwi_tape_stream(self.handle, int(shot), int(slot), int(level), None, 0,
+                                    ctypes.byref(n), _stream()))
+        out = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+        check(lib().fwi_tape_stream(self.handle, int(shot), int(slot), int(level), _ptr(out), n.value,
+                                    ctypes.byref(n), _stream()))
+        return out
+
     def free(self):
         if self.handle:
             check(lib().fwi_tape_free(self.handle))
@@ -278,6 +322,17 @@ class Context:
         check(lib().fwi_autotune(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), int(steps),
                                  ctypes.byref(r), _stream()))
         return {k: getattr(r, k) for k, _ in fwi_tune_result._fields_}
+
+    def time_shape(self, shot, m, wavelet, shape, steps=4):
+        """fwi_time_shape: (forward ms, adjoint ms) per launch of one launch
+        shape (xchunk, rows per lane, tile order, deep, z points per lane)"""
+        sa = ShotArgs(shot, wavelet)
+        g = grid_of(shot)
+        sh = (ctypes.c_int * 5)(*[int(v) for v in shape])
+        f, a = ctypes.c_double(), ctypes.c_double()
+        check(lib().fwi_time_shape(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), sh, int(steps),
+                                   ctypes.byref(f), ctypes.byref(a), _stream()))
+        return f.value, a.value
 
     # Eq. (2)
     def forward(self, shot, m: torch.Tensor, wavelet: torch.Tensor) -> torch.Tensor:
@@ -353,6 +408,39 @@ class Context:
         check(lib().fwi_gradient_batch(self.h, n, grids, ms, cshots, ds, ctypes.byref(cfg), gs, phis,
                                        _stream()))
         return list(phis), outs
+
+    def gradient_stack(self, shots, models, wavelets, d_obs, dims, region, origins, nslots=10,
+                       compress=False, atol=1e-4, pool_bytes=0, grad=None):
+        """fwi_gradient_stack: (phis, stacked gradient of dims) -- region 0
+        sums whole computational-grid gradients, 1 places each shot's
+        physical part at its origin"""
+        n = len(shots)
+        if not isinstance(wavelets, (list, tuple)):
+            wavelets = [wavelets] * n
+        sas = [ShotArgs(s, w) for s, w in zip(shots, wavelets)]
+        grids = (fwi_grid * n)(*[grid_of(s) for s in shots])
+        cshots = (fwi_shot * n)(*[sa.c for sa in sas])
+        ms = (ctypes.c_void_p * n)(*[_ptr(m) for m in models])
+        ds = (ctypes.c_void_p * n)(*[_ptr(d) for d in d_obs])
+        out = torch.empty(tuple(dims), dtype=torch.float32, device=models[0].device) if grad is None else grad
+        st, keep = make_stack(dims, region, origins)
+        phis = (ctypes.c_double * n)()
+        cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), float(atol), int(pool_bytes))
+        check(lib().fwi_gradient_stack(self.h, n, grids, ms, cshots, ds, ctypes.byref(cfg), ctypes.byref(st),
+                                       _ptr(out), phis, _stream()))
+        del keep
+        return list(phis), out
+
+    def backward_stack(self, tape, dds, dims, region, origins, grad=None):
+        """fwi_backward_stack: the stacked J_i^T dd_i of a batched tape"""
+        n = len(dds)
+        m0 = tape.m[0] if isinstance(tape.m, list) else tape.m
+        out = torch.empty(tuple(dims), dtype=torch.float32, device=m0.device) if grad is None else grad
+        dp = (ctypes.c_void_p * n)(*[_ptr(d.contiguous()) for d in dds])
+        st, keep = make_stack(dims, region, origins)
+        check(lib().fwi_backward_stack(self.h, tape.handle, dp, ctypes.byref(st), _ptr(out), _stream()))
+        del keep
+        return out
 
     def forward_ckpt_batch(self, shots, models, wavelets, nslots=10, compress=False, atol=1e-4,
                            pool_bytes=0):
@@ -509,8 +597,9 @@ class FwiOperator:
 class FwiBatchFunction(torch.autograd.Function):
     """d_sim of several shots of one model m (Eq. 2) as one differentiable
     op: forward runs fwi_forward_ckpt_batch (one stencil launch per time step
-    for all shots), backward runs fwi_backward_batch and returns the sum over
-    shots of J_i^T dd_i.  Returns one trace tensor per shot."""
+    for all shots), backward runs fwi_backward_stack, whose library kernels
+    sum J_i^T dd_i over the shots (they share m's grid).  Returns one trace
+    tensor per shot."""
 
     @staticmethod
     def forward(fctx, m, wavelet, context, shots, nslots, compress, atol, pool_bytes):
@@ -521,6 +610,7 @@ class FwiBatchFunction(torch.autograd.Function):
                                               nslots=nslots, compress=compress, atol=atol,
                                               pool_bytes=pool_bytes)
         fctx.context, fctx.tape = context, tape
+        fctx.dshapes = [tuple(d.shape) for d in ds]
         fctx.save_for_backward(m, wavelet)
         return tuple(ds)
 
@@ -528,13 +618,11 @@ class FwiBatchFunction(torch.autograd.Function):
     @torch.autograd.function.once_differentiable
     def backward(fctx, *dds):
         m, _ = fctx.saved_tensors
-        dds = [torch.zeros_like(d) if d is None else d for d in dds]
-        gs = fctx.context.backward_batch(fctx.tape, dds)
+        dds = [torch.zeros(sh, dtype=torch.float32, device=m.device) if d is None else d
+               for d, sh in zip(dds, fctx.dshapes)]
+        g = fctx.context.backward_stack(fctx.tape, dds, tuple(m.shape), 0, [(0,) * m.dim()] * len(dds))
         fctx.tape.free()
         fctx.tape = None
-        g = gs[0]
-        for x in gs[1:]:
-            g = g + x
         return g, None, None, None, None, None, None, None
 
 

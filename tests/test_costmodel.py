@@ -93,3 +93,38 @@ def test_choose_config_trades_tolerance_against_slots():
     best_tight, _ = C.choose_slots(plan, nt, tight, budget)
     assert best_tight is None or best_tight[1] >= ms
     assert C.choose_config(plan, nt, {1e-6: tight}, 1.0) is None
+
+
+@pytest.mark.parametrize("nt,s", [(50, 50), (200, 12), (2000, 40)])
+def test_overlap_share_is_recovered_from_a_measured_call(nt, s):
+    # a call that took the stencil time, both-level restores in full and
+    # 40 % of the overlappable codec time gives kappa = 0.4 back; with that
+    # kappa the prediction reproduces the call
+    u = C.UnitCosts(t_fwd=1.3, t_adj=2.2, t_enc=0.8, t_dec=1.1, field_bytes=1e6)
+    c = C.schedule_counts(F.fwi_revolve_plan, nt, s)
+    stencil = c.forward * 1.3 + nt * 2.2 + 2 * c.restores_both * 1.1
+    hidden = c.encodes * 0.8 + c.restores_uk * 1.1
+    k = C.overlap_kappa(c, u, nt, stencil + 0.4 * hidden)
+    assert k == pytest.approx(0.4)
+    u.kappa = k
+    assert C.predict_ms(c, u, nt) == pytest.approx(stencil + 0.4 * hidden)
+    # clipped to [0, 1]
+    assert C.overlap_kappa(c, u, nt, stencil - 5.0) == 0.0
+    assert C.overlap_kappa(c, u, nt, stencil + 3 * hidden) == 1.0
+
+
+def test_full_overlap_leaves_stencil_and_both_level_restores():
+    # kappa = 0: encodes and u^k restores cost nothing; restores of both
+    # levels precede forward steps that read them and stay
+    u = C.UnitCosts(t_fwd=1.0, t_adj=2.0, t_enc=0.5, t_dec=0.25, field_bytes=100.0, kappa=0.0)
+    c = C.schedule_counts(F.fwi_revolve_plan, 60, 4)
+    assert c.restores_both > 0
+    assert C.predict_ms(c, u, 60) == pytest.approx(c.forward + 120.0 + 2 * c.restores_both * 0.25)
+
+
+def test_unit_costs_take_stencil_times_from_a_codec_free_call():
+    st = dict(ms_forward=300.0, n_forward=200, ms_adjoint=500.0, n_adjoint=200, ms_encode=80.0,
+              n_encode=100, ms_decode=90.0, n_decode=90, ckpt_bytes=5e8)
+    clean = dict(ms_forward=240.0, n_forward=200, ms_adjoint=400.0, n_adjoint=200)
+    u = C.UnitCosts.from_stats(st, clean, kappa=0.3)
+    assert (u.t_fwd, u.t_adj, u.t_enc, u.t_dec, u.field_bytes, u.kappa) == (1.2, 2.0, 0.8, 1.0, 5e6, 0.3)

@@ -155,3 +155,96 @@ def test_batch_tile_orders(xchunk, remap, monkeypatch):
     _, ge = c.gradient_batch([t for t, _, _ in shots], models, q, [torch.zeros_like(d) for d in dobs], nslots=4)
     assert metrics.rel_l2(ge[1].cpu().numpy(), gref) <= 1e-4
     c.close()
+
+
+def crops_with_origins(ndim, widths, depth, so, nbl=5, nt=50, seed=4, amp=3.0):
+    """Uneven crops of one model with their origins in the model's physical
+    grid: (model shape, [(shot, m0, mt, origin)], wavelet)"""
+    rng = np.random.default_rng(seed)
+    full = (max(widths) + 12,) * (ndim - 1) + (depth,)
+    v0, vt = synth.tiny_models(full, seed=seed)
+    vt = v0 * (1.0 + amp * (vt / v0 - 1.0))
+    ref = synth.tiny_shot(ndim, n=depth, so=so, nbl=nbl, nt=nt)
+    out = []
+    for w in widths:
+        o = [int(rng.integers(0, full[d] - w + 1)) for d in range(ndim - 1)]
+        sl = tuple(slice(o[d], o[d] + w) for d in range(ndim - 1)) + (slice(None),)
+        shape = (w,) * (ndim - 1) + (depth,)
+        if ndim == 2:
+            xs = np.arange(0, w, 2)
+            rec = np.stack([xs, np.full(len(xs), 2)], 1)
+        else:
+            ix, iy = np.meshgrid(np.arange(0, w, 2), np.arange(0, w, 2), indexing="ij")
+            rec = np.stack([ix.ravel(), iy.ravel(), np.full(ix.size, 2)], 1)
+        shot = synth.Shot(ndim, shape, ref.h, so, nbl, nt, ref.dt, ref.vmax, ref.f0,
+                          (w // 2,) * (ndim - 1) + (2,), rec.astype(np.int32))
+        m0 = synth.slowness2(synth.extend(v0[sl], nbl)).astype(np.float32)
+        mt = synth.slowness2(synth.extend(vt[sl], nbl)).astype(np.float32)
+        out.append((shot, m0, mt, tuple(o) + (0,)))
+    return full, out, ref.wavelet().astype(np.float32)
+
+
+@pytest.mark.parametrize("ndim,widths,depth,so", [(3, (9, 14, 11, 17), 16, 8), (2, (30, 47, 38), 40, 16)])
+@pytest.mark.parametrize("compress", [False, True])
+def test_stacked_crops_match_oracle_placed_sum(ctx, ndim, widths, depth, so, compress):
+    """Sec. 2 / Sec. 4 "Stacking": the library adds each crop's physical
+    gradient into the model grid at the crop's origin, in shot order; the
+    FP64 oracle's per-crop gradients placed and summed in FP64 match it to
+    1e-4 (exact checkpoints; compressed within 1e-3 of exact), and two runs
+    are bitwise equal"""
+    full, shots, q32 = crops_with_origins(ndim, widths, depth, so)
+    nbl = shots[0][0].nbl
+    q = dev(q32)
+    d_obs, ref = [], np.zeros(full)
+    for shot, m0, mt, o in shots:
+        p0 = solver.Problem(shot, m0.astype(np.float64), wavelet=q32.astype(np.float64))
+        d = solver.forward(solver.Problem(shot, mt.astype(np.float64), wavelet=q32.astype(np.float64)))
+        _, g, dsim = solver.gradient(p0, d)
+        assert np.linalg.norm(dsim - d) >= 0.02 * np.linalg.norm(d)
+        phys = g[(slice(nbl, -nbl),) * ndim]
+        sl = tuple(slice(o[a], o[a] + phys.shape[a]) for a in range(ndim - 1)) + (slice(None),)
+        ref[sl] += phys
+        d_obs.append(dev(d.astype(np.float32)))
+    ms = [dev(m0) for _, m0, _, _ in shots]
+    sh = [s for s, _, _, _ in shots]
+    org = [o[:ndim - 1] + (0,) for _, _, _, o in shots]
+    phis, g1 = ctx.gradient_stack(sh, ms, q, d_obs, full, 1, org, nslots=6)
+    _, g2 = ctx.gradient_stack(sh, ms, q, d_obs, full, 1, org, nslots=6)
+    assert torch.equal(g1, g2)
+    err = metrics.rel_l2(g1.cpu().numpy(), ref)
+    print("stacked crops vs oracle placed sum %.2e" % err)
+    assert err <= 1e-4
+    if compress:
+        _, gc = ctx.gradient_stack(sh, ms, q, d_obs, full, 1, org, nslots=6, compress=True, atol=1e-4)
+        _, gc2 = ctx.gradient_stack(sh, ms, q, d_obs, full, 1, org, nslots=6, compress=True, atol=1e-4)
+        assert torch.equal(gc, gc2)
+        assert metrics.rel_l2(gc.cpu().numpy(), g1.cpu().numpy()) <= 1e-3
+    # the per-shot gradients of fwi_gradient_batch, placed in shot order in
+    # FP32, give the same bits
+    _, gs = ctx.gradient_batch(sh, ms, q, d_obs, nslots=6)
+    acc = torch.zeros(full, device=DEV)
+    for (shot, _, _, o), g in zip(shots, gs):
+        phys = g[(slice(nbl, -nbl),) * ndim]
+        sl = tuple(slice(o[a], o[a] + phys.shape[a]) for a in range(ndim - 1)) + (slice(None),)
+        acc[sl] += phys
+    assert torch.equal(acc, g1)
+
+
+def test_stack_whole_grids_and_rejects_bad_origins(ctx):
+    """region 0: shots sharing one grid sum their full computational-grid
+    gradients (what the batched autograd op returns); a crop that does not
+    fit the target is refused"""
+    shots = [synth.tiny_shot(2, n=36, so=8, nbl=5, nt=40) for _ in range(3)]
+    for i, s in enumerate(shots):
+        s.src = (6 + 10 * i, 2)
+    v0, vt = synth.tiny_models(shots[0].shape, seed=5)
+    m0 = dev(synth.slowness2(synth.extend(v0, 5)).astype(np.float32))
+    mt = dev(synth.slowness2(synth.extend(vt, 5)).astype(np.float32))
+    q = dev(shots[0].wavelet().astype(np.float32))
+    d_obs = [ctx.forward(s, mt, q) for s in shots]
+    _, gs = ctx.gradient_batch(shots, [m0] * 3, q, d_obs, nslots=5)
+    _, g = ctx.gradient_stack(shots, [m0] * 3, q, d_obs, tuple(m0.shape), 0, [(0, 0)] * 3, nslots=5)
+    assert torch.equal(g, gs[0] + gs[1] + gs[2])
+    with pytest.raises(F.FwiError) as e:
+        ctx.gradient_stack(shots, [m0] * 3, q, d_obs, (36, 36), 1, [(0, 0), (1, 0), (0, 0)], nslots=5)
+    assert e.value.code == F.FWI_EINVAL

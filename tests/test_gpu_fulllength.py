@@ -1,0 +1,86 @@
+"""Parity over the workloads' full time axes (paper Eqs. 1-4 over every
+step; FP32 on the GPU against the FP64 oracle), in the launch configuration
+the benchmark uses (autotuned stencil shapes, 40 checkpoint slots, codec
+overlapped):
+
+* one shot of the 2D survey workload at full size and full length (1001 x
+  401 at 10 m, 1081 x 481 with the layer, SO16, 3000 steps): traces, Phi and
+  the exact-checkpoint gradient against the oracle's store-all gradient;
+* a 3D SO8 shot over the 3D workload's 2000 steps (its spacing, time step,
+  wavelet and model generator) on a reduced 40^3 grid with a 20-point layer.
+
+The FP32 drift measured here over thousands of steps is reported with each
+result.  Each test runs the oracle for thousands of steps and holds its
+store-all states (12.5 GB and 8 GB of host memory); tens of seconds each."""
+import time
+
+import numpy as np
+import pytest
+import torch
+from scipy import ndimage
+
+import synth
+from oracle import metrics, solver
+
+pytestmark = pytest.mark.gpu
+
+F = pytest.importorskip("paper_2009_12623_amd.fwigrad")
+
+DEV = "cuda:0"
+
+
+def say(*a):
+    print("[fulllength]", *a, flush=True)
+
+
+def _compare(shot, m0h, mth, q32, tag):
+    t0 = time.time()
+    p0 = solver.Problem(shot, m0h.astype(np.float64), wavelet=q32.astype(np.float64))
+    dobs = solver.forward(solver.Problem(shot, mth.astype(np.float64), wavelet=q32.astype(np.float64)))
+    say("%s: oracle observed data %.1f s" % (tag, time.time() - t0))
+    phi_ref, gref, dref = solver.gradient(p0, dobs)
+    rr = np.linalg.norm(dref - dobs) / np.linalg.norm(dobs)
+    say("%s: oracle gradient %.1f s, residual/data %.3f" % (tag, time.time() - t0, rr))
+    c = F.Context(0, pool_bytes=16 << 30)
+    m, q, dd = (torch.from_numpy(np.ascontiguousarray(a)).to(DEV) for a in (m0h, q32, dobs.astype(np.float32)))
+    tune = c.autotune(shot, m, q, steps=2)
+    say("%s: autotuned %s" % (tag, {k: tune[k] for k in tune if "ms" not in k}))
+    d = c.forward(shot, m, q)
+    phi, g = c.gradient(shot, m, q, dd, nslots=40)
+    phi_c, g_c = c.gradient(shot, m, q, dd, nslots=40, compress=True, atol=1e-4)
+    torch.cuda.synchronize()
+    e_tr = metrics.rel_l2(d.cpu().numpy(), dref)
+    e_g = metrics.rel_l2(g.cpu().numpy(), gref)
+    e_phi = abs(phi - phi_ref) / phi_ref
+    e_c = metrics.rel_l2(g_c.cpu().numpy(), g.cpu().numpy())
+    e_co = metrics.rel_l2(g_c.cpu().numpy(), gref)
+    say("%s: FP32 vs FP64 over %d steps: traces %.2e, phi %.2e, gradient %.2e; compressed vs exact %.2e, "
+        "compressed vs oracle %.2e (%.1f s)" % (tag, shot.nt, e_tr, e_phi, e_g, e_c, e_co, time.time() - t0))
+    c.close()
+    assert rr >= 0.02
+    assert e_tr <= 1e-4 and e_phi <= 1e-4 and e_g <= 1e-4
+    assert e_c <= 1e-3
+
+
+@pytest.mark.timeout(900)
+def test_2d_survey_shot_full_length():
+    shot = synth.config5_shots(nt=3000)[7]
+    v0 = synth.smooth_2d()
+    vt = synth.blobs_2d(v0)
+    m0h = synth.slowness2(synth.extend(v0, shot.nbl)).astype(np.float32)
+    mth = synth.slowness2(synth.extend(vt, shot.nbl)).astype(np.float32)
+    _compare(shot, m0h, mth, shot.wavelet().astype(np.float32), "2D SO16 1081x481 3000 steps")
+
+
+@pytest.mark.timeout(900)
+def test_3d_so8_full_length():
+    c3 = synth.config3_shot(nt=2000)
+    shape = (40, 40, 40)
+    ix, iy = np.meshgrid(np.arange(0, 40, 4), np.arange(0, 40, 4), indexing="ij")
+    rec = np.stack([ix.ravel(), iy.ravel(), np.full(ix.size, 2)], 1).astype(np.int32)
+    shot = synth.Shot(3, shape, c3.h, 8, 20, c3.nt, c3.dt, c3.vmax, c3.f0, (20, 20, 2), rec)
+    vt = synth.thrust_3d(shape, fold_pts=3.0, fault_pts=4.0)
+    vs = ndimage.gaussian_filter(vt, 3.0, mode="nearest")
+    m0h = synth.slowness2(synth.extend(vs, shot.nbl)).astype(np.float32)
+    mth = synth.slowness2(synth.extend(vt, shot.nbl)).astype(np.float32)
+    _compare(shot, m0h, mth, shot.wavelet().astype(np.float32), "3D SO8 80^3 2000 steps")

@@ -46,3 +46,35 @@ def test_fwi_decreases_and_compressed_follows_exact():
     assert torch.equal(ex["m"][mask == 0], m0[mask == 0])
     assert not torch.equal(ex["m"][mask == 1], m0[mask == 1])
     c.close()
+
+
+def test_fwi_iterations_match_the_oracle_loop():
+    """three iterations of the GPU loop (exact checkpoints) against the FP64
+    oracle loop (oracle/fwi.py, the same reading of the step rule written
+    independently): objective before each iteration and after the last, and
+    the final model update; every line-search decision of the oracle run
+    clears its threshold by a wide margin, so both runs take the same ones"""
+    from oracle import fwi as ofwi
+    from oracle import solver
+    c = F.Context(0, pool_bytes=1 << 28)
+    shots, m0, mt, q, mask = survey()
+    qh = q.double().cpu().numpy()
+    mth = mt.double().cpu().numpy()
+    d_obs_h = [solver.forward(solver.Problem(s, mth, wavelet=qh)) for s in shots]
+    d_obs = [torch.from_numpy(d.astype(np.float32)).to(DEV) for d in d_obs_h]
+    ref = ofwi.run_fwi(shots, m0.double().cpu().numpy(), qh, d_obs_h, 3, 0.05, 1400.0, 2600.0,
+                       mask.double().cpu().numpy())
+    print("oracle objective", ref["objective"], "decreases", ref["decreases"])
+    assert min(abs(x) for x in ref["decreases"]) > 1e-3
+    run = fwi.run_fwi(c, shots, m0, q, d_obs, iterations=3, nslots=20, compress=False, step=0.05,
+                      vmin=1400.0, vmax=2600.0, mask=mask)
+    po, pr = np.array(run["objective"]), np.array(ref["objective"])
+    print("gpu objective", po)
+    assert np.max(np.abs(po - pr) / pr) <= 1e-4
+    m0h = m0.double().cpu().numpy()
+    upd_g = run["m"].double().cpu().numpy() - m0h
+    upd_o = ref["m"] - m0h
+    err = np.linalg.norm(upd_g - upd_o) / np.linalg.norm(upd_o)
+    print("model update rel L2 %.2e" % err)
+    assert err <= 1e-4
+    c.close()

@@ -94,20 +94,41 @@ def test_forward_state_matches_oracle(ctx, ndim, n, so):
     assert metrics.rel_l2(u0.cpu().numpy(), states[shot.nt - 1]) <= 1e-4
 
 
-@pytest.mark.parametrize("xchunk,rpl,remap,deep", [(3, 2, 0, 0), (7, 4, 1, 0), (64, 2, 1, 0), (16, 4, 0, 0),
-                                                   (16, 2, 2, 0), (7, 4, 2, 0), (5, 2, 2, 1),
-                                                   (3, 2, 0, 1), (16, 2, 1, 1), (64, 2, 0, 1), (1, 2, 0, 1),
-                                                   (2, 2, 0, 1)])
+def _deep_shot(so, zsrc, nt=30):
+    """3D shot whose computational depth (281) spans three 128-point z tiles
+    with an odd tail and whose y extent (31) leaves a ragged tile; source and
+    receivers at physical depth zsrc (123: across the first tile boundary,
+    268: in the tail tile), so both sweeps run there"""
+    shape, nbl = (18, 21, 271), 5
+    dt = synth.stable_dt(10.0, 2500.0, 3, so, 0.8)
+    ix, iy = np.meshgrid(np.arange(0, 18, 3), np.arange(0, 21, 4), indexing="ij")
+    rz = np.clip(zsrc + (ix + iy) % 7 - 3, 0, 270)
+    rec = np.stack([ix.ravel(), iy.ravel(), rz.ravel()], 1).astype(np.int32)
+    return synth.Shot(3, shape, 10.0, so, nbl, nt, dt, 2500.0, 1500.0 / 80.0, (9, 10, zsrc), rec)
+
+
+@pytest.mark.parametrize("xchunk,rpl,remap,deep,vz", [(3, 2, 0, 0, 1), (7, 4, 1, 0, 1), (64, 2, 1, 0, 1),
+                                                      (16, 4, 0, 0, 1), (16, 2, 2, 0, 1), (7, 4, 2, 0, 1),
+                                                      (5, 2, 2, 1, 1), (3, 2, 0, 1, 1), (16, 2, 1, 1, 1),
+                                                      (64, 2, 0, 1, 1), (1, 2, 0, 1, 1), (2, 2, 0, 1, 1),
+                                                      (3, 2, 0, 0, 2), (7, 4, 1, 0, 2), (16, 2, 2, 0, 2),
+                                                      (64, 4, 2, 0, 2), (1, 4, 0, 0, 2), (5, 2, 1, 0, 2)])
 @pytest.mark.parametrize("so", [4, 8, 16])
-def test_3d_stencil_launch_shapes_match_oracle(xchunk, rpl, remap, deep, so, monkeypatch):
+@pytest.mark.parametrize("grid", ["cube", "deep_mid", "deep_tail"])
+def test_3d_stencil_launch_shapes_match_oracle(xchunk, rpl, remap, deep, vz, so, grid, monkeypatch):
     """every launch shape (x planes per workgroup, rows per lane, tile order,
-    loads of one or two planes in flight)"""
+    loads of one or two planes in flight, one or two z points per lane); the
+    deep grids span several 128-point z tiles with a ragged, odd tail"""
+    if grid != "cube" and (so == 4 or (vz == 1 and (xchunk, rpl) not in ((16, 2), (7, 4)))):
+        pytest.skip("the deep grids cover the two-point lanes and two one-point shapes")
     monkeypatch.setenv("FWI_XCHUNK", str(xchunk))
     monkeypatch.setenv("FWI_RPL", str(rpl))
     monkeypatch.setenv("FWI_REMAP", str(remap))
     monkeypatch.setenv("FWI_DEEP", str(deep))
+    monkeypatch.setenv("FWI_VZ", str(vz))
     c = F.Context(0, pool_bytes=1 << 28)
-    shot = synth.tiny_shot(3, n=23, so=so, nbl=5, nt=35)
+    shot = (synth.tiny_shot(3, n=23, so=so, nbl=5, nt=35) if grid == "cube"
+            else _deep_shot(so, 123 if grid == "deep_mid" else 268))
     m0, mt, q = inputs(shot)
     p0 = oracle_problem(shot, m0, q)
     dobs = solver.forward(oracle_problem(shot, mt, q))
@@ -116,6 +137,34 @@ def test_3d_stencil_launch_shapes_match_oracle(xchunk, rpl, remap, deep, so, mon
     assert metrics.rel_l2(d, dref) <= 1e-4
     phi, g = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=3)
     assert metrics.rel_l2(g.cpu().numpy(), gref) <= 1e-4
+    c.close()
+
+
+@pytest.mark.parametrize("xchunk,rpl,remap,vz", [(16, 2, 2, 1), (7, 4, 0, 1), (3, 2, 0, 2), (7, 4, 1, 2),
+                                                 (16, 2, 2, 2), (64, 4, 2, 2), (1, 4, 0, 2)])
+@pytest.mark.parametrize("so", [8, 16])
+def test_forward_steps_from_random_states_every_tile(xchunk, rpl, remap, vz, so, monkeypatch):
+    """three forward steps from seeded random states on the deep grid: every
+    z tile, the odd z tail and the ragged y tile hold data, against the
+    oracle's steps on every point"""
+    monkeypatch.setenv("FWI_XCHUNK", str(xchunk))
+    monkeypatch.setenv("FWI_RPL", str(rpl))
+    monkeypatch.setenv("FWI_REMAP", str(remap))
+    monkeypatch.setenv("FWI_VZ", str(vz))
+    c = F.Context(0, pool_bytes=1 << 26)
+    shot = _deep_shot(so, 123, nt=8)
+    m0, _, q = inputs(shot)
+    rng = np.random.default_rng(21)
+    u1 = rng.standard_normal(shot.comp_shape).astype(np.float32)
+    u0 = rng.standard_normal(shot.comp_shape).astype(np.float32)
+    p = oracle_problem(shot, m0, q)
+    cur, prev = u1.astype(np.float64), u0.astype(np.float64)
+    for k in range(3, 6):
+        cur, prev = p.step(cur, prev, [p.src], [p.q[k]]), cur
+    g1, g0 = dev(u1), dev(u0)
+    c.forward_span(shot, dev(m0), dev(q), 3, 6, g1, g0)
+    assert metrics.rel_l2(g1.cpu().numpy(), cur) <= 1e-5
+    assert metrics.rel_l2(g0.cpu().numpy(), prev) <= 1e-5
     c.close()
 
 
@@ -132,7 +181,7 @@ def test_autotuned_shapes_keep_the_gradient(ndim, n, so):
     _, g_def = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=4)
     r = c.autotune(shot, dev(m0), dev(q), steps=2)
     print("autotune", ndim, r)
-    assert r["ncand"] == (28 if ndim == 3 else 5)
+    assert r["ncand"] == (55 if ndim == 3 else 5)
     assert r["fwd_xchunk"] in (4, 8, 16, 32, 64) and r["adj_xchunk"] in (4, 8, 16, 32, 64)
     assert r["fwd_rows_per_lane"] in (2, 4) and r["fwd_ms"] > 0 and r["adj_ms"] > 0
     _, g = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=4)
@@ -175,15 +224,26 @@ def test_compressed_gradient_close_to_exact(ctx, ndim, so):
     assert errs[2] <= errs[0]
 
 
-def test_compressed_gradient_matches_oracle_compressed(ctx):
-    shot = synth.tiny_shot(2, n=40, so=4, nbl=6, nt=60)
+@pytest.mark.parametrize("ndim,n,so,nt,nslots", [(2, 40, 4, 60, 4), (2, 90, 16, 160, 6),
+                                                (3, 24, 8, 90, 5), (3, 20, 16, 60, 60)])
+def test_compressed_gradient_matches_oracle_compressed(ctx, ndim, n, so, nt, nslots):
+    """lossy GPU gradient (atol 1e-4) against the oracle's lossy gradient
+    (FP64 states rounded to float32 and compressed, Sec. 3) at the same bar
+    as the exact gradient; each side compresses its own states, so the
+    streams may differ where a value sits on a quantisation boundary"""
+    shot = synth.tiny_shot(ndim, n=n, so=so, nbl=6, nt=nt)
     m0, mt, q = inputs(shot)
     p0 = oracle_problem(shot, m0, q)
     dobs = solver.forward(oracle_problem(shot, mt, q))
-    _, gref = solver.gradient_checkpointed(p0, dobs, 4, atol=1e-4)
-    _, g = ctx.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=4,
+    st = {}
+    _, gref = solver.gradient_checkpointed(p0, dobs, nslots, atol=1e-4, stats=st)
+    rr = np.linalg.norm(st["d_sim"] - dobs) / np.linalg.norm(dobs)
+    _, g = ctx.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=nslots,
                         compress=True, atol=1e-4)
-    assert metrics.rel_l2(g.cpu().numpy(), gref) <= 1e-3
+    err = metrics.rel_l2(g.cpu().numpy(), gref)
+    print("lossy vs lossy oracle", ndim, so, "residual/data %.3f" % rr, "err %.2e" % err)
+    assert rr >= 0.02
+    assert err <= 1e-4
 
 
 def test_autograd_split_equals_gradient(ctx):
@@ -219,8 +279,18 @@ def codec_fields():
 
 @pytest.mark.parametrize("atol", [1e-1, 1e-3, 1e-4, 1e-6, 2.0 ** -70, 2.0 ** -140])
 def test_codec_streams_bit_exact(ctx, atol):
+    """streams and decodes byte-identical to the oracle's; where the oracle
+    refuses a field (a value at or above atol 2^23) the library refuses it
+    too, with FWI_ERANGE"""
     for x in codec_fields():
-        ref = ocodec.compress(x, atol)
+        try:
+            ref = ocodec.compress(x, atol)
+        except ocodec.CodecError as e:
+            assert e.code == ocodec.ERANGE
+            with pytest.raises(F.FwiError) as ge:
+                ctx.compress(dev(x), atol)
+            assert ge.value.code == F.FWI_ERANGE
+            continue
         s = ctx.compress(dev(x), atol).cpu().numpy().tobytes()
         assert s == ref, (x.shape, atol, len(s), len(ref))
         y = ctx.decompress(dev(np.frombuffer(ref, np.uint8).copy()), x.shape).cpu().numpy()
@@ -233,7 +303,10 @@ def test_codec_saturation_bit_exact(ctx):
     float (they saturate to it): the oracle's stream and decode, bit for bit"""
     rng = np.random.default_rng(22)
     x = (rng.uniform(3.4e38, 3.4028234e38, (10, 13)) * rng.choice([-1.0, 1.0], (10, 13))).astype(np.float32)
-    for atol in (1e36, 1e-1):
+    with pytest.raises(F.FwiError) as e:            # far beyond atol 2^23
+        ctx.compress(dev(x), 1e-1)
+    assert e.value.code == F.FWI_ERANGE
+    for atol in (1e36, 2.0 ** 105):
         ref = ocodec.compress(x, atol)
         assert ctx.compress(dev(x), atol).cpu().numpy().tobytes() == ref
         y = ctx.decompress(dev(np.frombuffer(ref, np.uint8).copy()), x.shape).cpu().numpy()
@@ -328,6 +401,32 @@ def test_codec_on_oracle_wavefields(ctx):
                 assert s == ref
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_codec_refuses_values_beyond_the_accuracy_range(ctx, ndim):
+    """|x - x_hat| <= atol needs every |x| below 2^(floor(log2 atol) + 23):
+    just below the limit the stream is the oracle's and the bound holds; at
+    it the library returns FWI_ERANGE, also from a compressed gradient"""
+    atol = 2.0 ** -20
+    shape = (9, 6, 7) if ndim == 3 else (13, 10)
+    rng = np.random.default_rng(31)
+    x = rng.uniform(-1, 1, shape).astype(np.float32)
+    x.flat[17] = np.nextafter(np.float32(8.0), np.float32(0))
+    s = ctx.compress(dev(x), atol).cpu().numpy().tobytes()
+    assert s == ocodec.compress(x, atol)
+    x.flat[17] = -8.0
+    with pytest.raises(F.FwiError) as e:
+        ctx.compress(dev(x), atol)
+    assert e.value.code == F.FWI_ERANGE
+    # a compressed schedule whose wavefield exceeds the range: the source
+    # node alone carries b q with b = dt^2/m
+    shot = synth.tiny_shot(2, n=20, so=4, nbl=4, nt=30)
+    m0, _, q = inputs(shot)
+    dobs = torch.zeros((shot.nt, len(shot.rec)), device="cuda:0")
+    with pytest.raises(F.FwiError) as e:
+        ctx.gradient(shot, dev(m0), dev(q * 1e3), dobs, nslots=3, compress=True, atol=2.0 ** -60)
+    assert e.value.code == F.FWI_ERANGE
+
+
 def test_codec_error_paths(ctx):
     x = dev(synth.wavefield_like((20, 20, 20), seed=4))
     s = ctx.compress(x, 1e-4)
@@ -376,6 +475,24 @@ def test_gradient_error_paths(ctx):
         small.gradient(shot, dev(m0), dev(q), dobs, nslots=3)
     assert e.value.code == F.FWI_ECAPACITY
     with pytest.raises(F.FwiError) as e:
-        small.gradient(shot, dev(m0), dev(q), dobs, nslots=3, compress=True, atol=1e-9)
+        small.gradient(shot, dev(m0), dev(q), dobs, nslots=3, compress=True, atol=1e-6)
     assert e.value.code == F.FWI_ECAPACITY
     small.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("width", [4, 8, 16])
+@pytest.mark.parametrize("ns,nd", [(1, 1), (3, 1), (5, 2)])
+@pytest.mark.parametrize("grid", [37, 0])
+def test_bandwidth_probe_sums_sources(width, ns, nd, grid):
+    # the probe is the kernel of known traffic behind the counter
+    # calibration: every destination must hold the sum of the sources
+    import torch
+    n = 4096 * 7 + 12          # ragged against the grid stride
+    g = torch.Generator().manual_seed(4)
+    srcs = [torch.randn(n, generator=g).to("cuda:0") for _ in range(ns)]
+    dsts = [torch.zeros(n, device="cuda:0") for _ in range(nd)]
+    F.fwi_bandwidth_probe(srcs, dsts, width, grid)
+    ref = sum(s.double() for s in srcs)
+    for d in dsts:
+        assert torch.allclose(d.double(), ref, rtol=0, atol=1e-5)

@@ -196,10 +196,13 @@ def test_constant_block_length_closed_form(ndim, value, atol):
 @pytest.mark.parametrize("shape", [(4, 4), (13, 7), (3, 5, 6), (9, 4, 11)])
 def test_tiny_atol_decodes_block_floating_point_exactly(shape):
     # with every plane kept the decoder must return trunc(x 2^(24-emax))
-    # 2^(emax-24) with emax the block's exponent -- computed here with numpy
+    # 2^(emax-24) with emax the block's exponent -- computed here with numpy.
+    # Every plane is kept when the lowest plane minexp - emax + 24 - G is
+    # <= 0 for every block while emax stays within the accuracy range
+    # (emax <= minexp + 23): |x| in [1/2, 4) at atol 2^-20 (emax 0..2)
     rng = np.random.default_rng(4)
-    x = (rng.standard_normal(shape) * 2.0 ** rng.integers(-6, 6, shape)).astype(np.float32)
-    y = codec.decompress(codec.compress(x, 2.0 ** -80), shape)
+    x = (rng.uniform(0.5, 4.0, shape) * rng.choice([-1.0, 1.0], shape)).astype(np.float32)
+    y = codec.decompress(codec.compress(x, 2.0 ** -20), shape)
     nd = len(shape)
     pad = [(0, (-n) % 4) for n in shape]
     xp = np.pad(x.astype(np.float64), pad, mode="edge")
@@ -222,7 +225,7 @@ def test_compression_factor_monotone_in_atol():
 def test_bound_is_never_exceeded():
     rng = np.random.default_rng(6)
     x = rng.standard_normal((12, 12, 12)).astype(np.float32) * 1e3
-    s = codec.compress(x, 2.0 ** -70)
+    s = codec.compress(x, 2.0 ** -11)     # every plane of most blocks coded
     assert len(s) <= codec.bound(x.shape)
 
 
@@ -264,3 +267,24 @@ def test_header_records_chunk_length(shape, log2k):
     kmax = 16 if len(shape) == 3 else 64
     assert k == 1 or -(-nblocks // k) >= 16384               # enough chunks
     assert k == kmax or -(-nblocks // (2 * k)) < 16384        # and no more halving than needed
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_values_beyond_the_accuracy_range_are_refused(ndim):
+    # Sec. 1.4 fixed accuracy: |x - x_hat| <= atol needs every |x| below
+    # 2^(floor(log2 atol) + 23); at atol = 2^-20 that limit is 8.  A field
+    # just below it keeps the bound (all planes coded, only the 24-bit
+    # conversion error remains); one value at the limit is refused.
+    atol = 2.0 ** -20
+    shape = (9, 6, 7) if ndim == 3 else (13, 10)
+    rng = np.random.default_rng(31)
+    x = rng.uniform(-1, 1, shape).astype(np.float32)
+    x.flat[17] = np.nextafter(np.float32(8.0), np.float32(0))
+    y = codec.decompress(codec.compress(x, atol), shape)
+    assert np.max(np.abs(y.astype(np.float64) - x)) <= atol
+    x.flat[17] = -8.0
+    with pytest.raises(codec.CodecError) as e:
+        codec.compress(x, atol)
+    assert e.value.code == codec.ERANGE
+    # a larger atol accepts the same field
+    codec.compress(x, 2.0 ** -19)
