@@ -35,6 +35,7 @@ namespace fwi {
 namespace {
 
 constexpr int QB = 24;
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 // ------------------------------------------------------- sequency tables
 template <int D>
@@ -313,7 +314,6 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
     const long nb[3] = {nb0, nb1, nb2};
     BitWriter bw{0ull, 0, scratch + scratch_word(c, 0, chunk_words), 0};
     bool nonfinite = false, outrange = false;
-    typedef float f4v __attribute__((ext_vector_type(4)));
     // padded fields: the rows of the next block are loaded while the current
     // one is coded
     f4v pf[SZ / 4];
@@ -368,8 +368,7 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
             for (int r = 0; r < SZ / 4; ++r) {
                 const int ix = D == 3 ? (r >> 2) : r;
                 const int iy = D == 3 ? (r & 3) : 0;
-                typedef float f4v __attribute__((ext_vector_type(4)));
-                const f4v v = __builtin_nontemporal_load(
+                            const f4v v = __builtin_nontemporal_load(
                     (const f4v *)(src + (4 * bx + ix) * f.sx + (4 * by + iy) * f.sy + 4 * bz));
                 w[4 * r + 0] = __float_as_uint(v.x);
                 w[4 * r + 1] = __float_as_uint(v.y);
@@ -784,9 +783,15 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
                 const int iy = D == 3 ? (r & 3) : 0;
                 const long x = 4 * bx + ix, y = 4 * by + iy;
                 const bool row = x < f.n[0] && y < f.n[1];
-                *(float4 *)(dst + x * f.sx + y * f.sy + 4 * bz) =
-                    make_float4(row ? val(4 * r) : 0.0f, row && zl >= 1 ? val(4 * r + 1) : 0.0f,
-                                row && zl >= 2 ? val(4 * r + 2) : 0.0f, row && zl >= 3 ? val(4 * r + 3) : 0.0f);
+                f4v v;
+                v.x = row ? val(4 * r) : 0.0f;
+                v.y = row && zl >= 1 ? val(4 * r + 1) : 0.0f;
+                v.z = row && zl >= 2 ? val(4 * r + 2) : 0.0f;
+                v.w = row && zl >= 3 ? val(4 * r + 3) : 0.0f;
+                // 3D working fields are far larger than the caches and are
+                // read by the next stencil step: stream them out
+                if (D == 3) __builtin_nontemporal_store(v, (f4v *)(dst + x * f.sx + y * f.sy + 4 * bz));
+                else *(f4v *)(dst + x * f.sx + y * f.sy + 4 * bz) = v;
             }
         } else if (vec && 4 * bx + 3 < f.n[0] && (D == 2 || 4 * by + 3 < f.n[1]) && 4 * bz + 3 < f.n[2]) {
             // whole block inside: one 16-byte store per (x, y) row

@@ -131,6 +131,8 @@ struct InjectParams {
     float kappa, inv_dt2;
 };
 void launch_inject(const InjectParams &p, hipStream_t st);
+// all shots of a batched step: dev_tab holds nshot entries on the device
+void launch_inject_batch(const InjectParams *dev_tab, int nshot, int max_nodes, hipStream_t st);
 
 // -------------------------------------------------------------------- codec
 struct FieldView {

@@ -934,6 +934,12 @@ struct Exec {
     // scaled by img; img = 0: the step images nothing)
     void post_reverse(int k, float img = 1.0f)
     {
+        launch_inject(inject_params(k, img), st);
+        end_reverse();
+    }
+
+    InjectParams inject_params(int k, float img) const
+    {
         InjectParams ip{};
         ip.lam = l2;
         ip.g = img != 0.0f ? B->gacc.p : nullptr;
@@ -952,7 +958,12 @@ struct Exec {
         ip.ndim = S.ndim;
         ip.kappa = S.kappa;
         ip.inv_dt2 = S.inv_dt2 * img;
-        launch_inject(ip, st);
+        return ip;
+    }
+
+    // the new adjoint level becomes the newer one
+    void end_reverse()
+    {
         std::swap(l1, l2);
         c->stats.n_adjoint += 1;
     }
@@ -1267,7 +1278,20 @@ struct BatchExec {
             for (size_t i = 0; i < ex.size(); ++i) ps[i] = ex[i].adj_params();
             launch(true);
         }
-        for (auto &e : ex) e.post_reverse(k);
+        // receiver residuals of every shot in one launch
+        const int n = (int)ex.size();
+        BatchTables &t = c->btab;
+        const size_t off = t.take((size_t)n * sizeof(InjectParams));
+        InjectParams *h = (InjectParams *)(t.host + off);
+        int maxn = 0;
+        for (int i = 0; i < n; ++i) {
+            h[i] = ex[i].inject_params(k, 1.0f);
+            maxn = std::max(maxn, h[i].nnode);
+        }
+        InjectParams *d = (InjectParams *)(dev_base + off);
+        if (upload) HIPCHK(hipMemcpyAsync(d, h, (size_t)n * sizeof(InjectParams), hipMemcpyHostToDevice, st));
+        launch_inject_batch(d, n, maxn, st);
+        for (auto &e : ex) e.end_reverse();
         main_used(uk);
     }
 
@@ -1366,12 +1390,13 @@ size_t table_bytes_of(const std::vector<fwi_action> &acts, size_t nshots)
 {
     auto slice = [](size_t b) { return (b + 255) & ~(size_t)255; };
     const size_t step = slice(nshots * sizeof(BatchEntry));
+    const size_t inj = slice(nshots * sizeof(InjectParams));
     const size_t enc = 2 * slice(nshots * codec_job_bytes(true));
     const size_t dec = 2 * slice(nshots * codec_job_bytes(false));
     size_t n = 0;
     for (auto &a : acts) {
         if (a.op == FWI_ADVANCE) n += (size_t)(a.b - a.a) * step;
-        else if (a.op == FWI_REVERSE) n += step;
+        else if (a.op == FWI_REVERSE) n += step + inj;
         else if (a.op == FWI_TAKESHOT) n += enc;
         else if (a.op == FWI_RESTORE) n += dec;
     }

@@ -59,23 +59,30 @@ __device__ __forceinline__ void stnt(float *base, unsigned off, float v)
     __builtin_nontemporal_store(v, (float *)((char *)base + off));
 }
 
-// new level from the Laplacian and the point values
+// Increment out - c of the new level.  The recurrence row is written around
+// the current level,
+//   (1 + e) (out - c) = (1 - e) (c - u2) + b (Lap_h c + s),
+// so the small time difference c - u2 is formed before anything is rounded
+// (FP32 rounding of 2c - u2 is what drifts over thousands of steps).
 template <bool ADJ>
-__device__ __forceinline__ float update(const StepParams &p, int dsum, bool is_src, float c,
-                                        float lap, float u2v, float bb)
+__device__ __forceinline__ float increment(const StepParams &p, int dsum, bool is_src, float c, float lap,
+                                           float u2v, float bb)
 {
-    float outv;
-    if (dsum == 0) {
-        float num = 2.0f * c + bb * lap - u2v;
-        if (!ADJ && is_src) num += bb * p.wav[p.step];
-        outv = num;
-    } else {
-        const float e = p.kappa * bb * (float)dsum;
-        float num = 2.0f * c + bb * lap - (1.0f - e) * u2v;
-        if (!ADJ && is_src) num += bb * p.wav[p.step];
-        outv = num / (1.0f + e);
-    }
-    return outv;
+    const float d = c - u2v;
+    float rhs = lap;
+    if (!ADJ && is_src) rhs += p.wav[p.step];
+    if (dsum == 0) return fmaf(bb, rhs, d);
+    const float e = p.kappa * bb * (float)dsum;
+    return fmaf(bb, rhs, (1.0f - e) * d) / (1.0f + e);
+}
+
+// one axis pair of the Laplacian without the centre weight:
+// a_0 = -2 sum_k a_k, so Lap_h c = sum_k w_k sum_axes (u_-k + u_+k - 2c), and
+// each pair minus 2c is small where the field is smooth (no large centre
+// term left to cancel)
+__device__ __forceinline__ float pair2(float a, float b, float c)
+{
+    return fmaf(-2.0f, c, a + b);
 }
 
 __device__ __forceinline__ void gather_block(const StepParams &p, int blk)
@@ -229,16 +236,17 @@ __device__ __forceinline__ void step3d_body(const StepParams &p, int hw, int ntz
             if (!act[j]) continue;
             const int r = ty + 8 * j + R;
             const float c = q[j][R];
-            float lap = 3.0f * p.w[0] * c;
+            float lap = 0.0f;
 #pragma unroll
             for (int k = 1; k <= R; ++k)
-                lap += p.w[k] * ((q[j][R - k] + q[j][R + k]) +
-                                 (tile[cur][r - k][tz + R] + tile[cur][r + k][tz + R]) +
-                                 (tile[cur][r][tz + R - k] + tile[cur][r][tz + R + k]));
+                lap = fmaf(p.w[k], pair2(q[j][R - k], q[j][R + k], c) +
+                                   pair2(tile[cur][r - k][tz + R], tile[cur][r + k][tz + R], c) +
+                                   pair2(tile[cur][r][tz + R - k], tile[cur][r][tz + R + k], c), lap);
             const unsigned o = pa + j * rstep;
-            const float ov = update<ADJ>(p, dx * dx + dyz[j], o == srcb, c, lap, u2v[j], bv[j]);
-            stnt(p.out, o, ov);
-            if (ADJ) stnt(p.g, o, gv[j] - ukv[j] * (ov - 2.0f * c + u2v[j]) * p.inv_dt2);
+            const float inc = increment<ADJ>(p, dx * dx + dyz[j], o == srcb, c, lap, u2v[j], bv[j]);
+            stnt(p.out, o, c + inc);
+            // imaging: out - 2c + u2 = (out - c) - (c - u2)
+            if (ADJ) stnt(p.g, o, gv[j] - ukv[j] * (inc - (c - u2v[j])) * p.inv_dt2);
         }
         if (!nxt) break;
         // ---- advance the queues and stage plane x+1 in the other buffer
@@ -389,16 +397,17 @@ __device__ __forceinline__ void step3d_body_deep(const StepParams &p, int hw, in
             if (!act[j]) continue;
             const int r = ty + 8 * j + R;
             const float c = q[j][R];
-            float lap = 3.0f * p.w[0] * c;
+            float lap = 0.0f;
 #pragma unroll
             for (int k = 1; k <= R; ++k)
-                lap += p.w[k] * ((q[j][R - k] + q[j][R + k]) +
-                                 (tile[cur][r - k][tz + R] + tile[cur][r + k][tz + R]) +
-                                 (tile[cur][r][tz + R - k] + tile[cur][r][tz + R + k]));
+                lap = fmaf(p.w[k], pair2(q[j][R - k], q[j][R + k], c) +
+                                   pair2(tile[cur][r - k][tz + R], tile[cur][r + k][tz + R], c) +
+                                   pair2(tile[cur][r][tz + R - k], tile[cur][r][tz + R + k], c), lap);
             const unsigned o = pa + j * rstep;
-            const float ov = update<ADJ>(p, dx * dx + dyz[j], o == srcb, c, lap, u2v[j], bv[j]);
-            stnt(p.out, o, ov);
-            if (ADJ) stnt(p.g, o, gv[j] - ukv[j] * (ov - 2.0f * c + u2v[j]) * p.inv_dt2);
+            const float inc = increment<ADJ>(p, dx * dx + dyz[j], o == srcb, c, lap, u2v[j], bv[j]);
+            stnt(p.out, o, c + inc);
+            // imaging: out - 2c + u2 = (out - c) - (c - u2)
+            if (ADJ) stnt(p.g, o, gv[j] - ukv[j] * (inc - (c - u2v[j])) * p.inv_dt2);
         }
         if (x + 1 >= xe) break;
         // ---- advance the queues and stage plane x+1 (loads issued one plane ago)
@@ -594,25 +603,28 @@ __device__ __forceinline__ void step3w_body(const StepParams &p, int hw, int ntz
                 zr[2 * m] = v.x;
                 zr[2 * m + 1] = v.y;
             }
-            float la = 3.0f * p.w[0] * c.x, lb = 3.0f * p.w[0] * c.y;
+            float la = 0.0f, lb = 0.0f;
 #pragma unroll
             for (int k = 1; k <= R; ++k) {
                 const f2v ym = *(const f2v *)&tile[cur][r - k][ccol];
                 const f2v yp = *(const f2v *)&tile[cur][r + k][ccol];
-                la += p.w[k] * ((q[j][R - k].x + q[j][R + k].x) + (ym.x + yp.x) + (zr[R - k] + zr[R + k]));
-                lb += p.w[k] * ((q[j][R - k].y + q[j][R + k].y) + (ym.y + yp.y) +
-                                (zr[R + 1 - k] + zr[R + 1 + k]));
+                la = fmaf(p.w[k], pair2(q[j][R - k].x, q[j][R + k].x, c.x) + pair2(ym.x, yp.x, c.x) +
+                                  pair2(zr[R - k], zr[R + k], c.x), la);
+                lb = fmaf(p.w[k], pair2(q[j][R - k].y, q[j][R + k].y, c.y) + pair2(ym.y, yp.y, c.y) +
+                                  pair2(zr[R + 1 - k], zr[R + 1 + k], c.y), lb);
             }
             const unsigned o = pa + j * rstep;
             const int dxy = dx * dx + dya[j];
-            f2v ov;
-            ov.x = update<ADJ>(p, dxy + dza * dza, o == srcb, c.x, la, u2v[j].x, bv[j].x);
-            ov.y = update<ADJ>(p, dxy + dzb * dzb, o + 4u == srcb, c.y, lb, u2v[j].y, bv[j].y);
+            f2v inc, ov;
+            inc.x = increment<ADJ>(p, dxy + dza * dza, o == srcb, c.x, la, u2v[j].x, bv[j].x);
+            inc.y = increment<ADJ>(p, dxy + dzb * dzb, o + 4u == srcb, c.y, lb, u2v[j].y, bv[j].y);
+            ov.x = c.x + inc.x;
+            ov.y = c.y + inc.y;
             st2(p.out, o, ov, both);
             if (ADJ) {
                 f2v gn;
-                gn.x = gv[j].x - ukv[j].x * (ov.x - 2.0f * c.x + u2v[j].x) * p.inv_dt2;
-                gn.y = gv[j].y - ukv[j].y * (ov.y - 2.0f * c.y + u2v[j].y) * p.inv_dt2;
+                gn.x = gv[j].x - ukv[j].x * (inc.x - (c.x - u2v[j].x)) * p.inv_dt2;
+                gn.y = gv[j].y - ukv[j].y * (inc.y - (c.y - u2v[j].y)) * p.inv_dt2;
                 st2(p.g, o, gn, both);
             }
         }
@@ -696,14 +708,15 @@ __device__ __forceinline__ void step2d_body(const StepParams &p, int hw, int ntz
         }
         if (act) {
             const float c = q[R];
-            float lap = 2.0f * p.w[0] * c;
+            float lap = 0.0f;
 #pragma unroll
             for (int k = 1; k <= R; ++k)
-                lap += p.w[k] * ((q[R - k] + q[R + k]) + (row[cur][tz + R - k] + row[cur][tz + R + k]));
+                lap = fmaf(p.w[k], pair2(q[R - k], q[R + k], c) +
+                                   pair2(row[cur][tz + R - k], row[cur][tz + R + k], c), lap);
             const int dx = layer_depth(x, p.nx, p.nbl);
-            const float o = update<ADJ>(p, dx * dx + dz * dz, pa == srcb, c, lap, u2v, bb);
-            st(p.out, pa, o);
-            if (ADJ) st(p.g, pa, gv - ukv * (o - 2.0f * c + u2v) * p.inv_dt2);
+            const float inc = increment<ADJ>(p, dx * dx + dz * dz, pa == srcb, c, lap, u2v, bb);
+            st(p.out, pa, c + inc);
+            if (ADJ) st(p.g, pa, gv - ukv * (inc - (c - u2v)) * p.inv_dt2);
         }
         if (!nxt) break;
 #pragma unroll
@@ -971,9 +984,8 @@ void phi_kernel(const double *partials, int n, double *phi)
     if (threadIdx.x == 0) *phi = 0.5 * red[0];
 }
 
-__global__ void inject_kernel(InjectParams p)
+__device__ __forceinline__ void inject_body(const InjectParams &p, int j)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= p.nnode) return;
     float s = 0.0f;
     for (int r = p.rec_ptr[j]; r < p.rec_ptr[j + 1]; ++r) s += p.res_row[p.rec_idx[r]];
@@ -987,6 +999,17 @@ __global__ void inject_kernel(InjectParams p)
     const float delta = bb * s / (1.0f + e);
     p.lam[pi] += delta;
     if (p.g) p.g[pi] -= p.uk[pi] * delta * p.inv_dt2;
+}
+
+__global__ void inject_kernel(InjectParams p)
+{
+    inject_body(p, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// every shot of a batched step at once: shot blockIdx.y, table on the device
+__global__ void inject_batch_kernel(const InjectParams *__restrict__ tab)
+{
+    inject_body(tab[blockIdx.y], blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 }  // namespace
@@ -1133,6 +1156,12 @@ void launch_inject(const InjectParams &p, hipStream_t st)
 {
     if (p.nnode <= 0) return;
     hipLaunchKernelGGL(inject_kernel, dim3((p.nnode + 127) / 128), dim3(128), 0, st, p);
+}
+
+void launch_inject_batch(const InjectParams *dev_tab, int nshot, int max_nodes, hipStream_t st)
+{
+    if (nshot <= 0 || max_nodes <= 0) return;
+    hipLaunchKernelGGL(inject_batch_kernel, dim3((max_nodes + 127) / 128, nshot), dim3(128), 0, st, dev_tab);
 }
 
 Padded make_padded(int ndim, const int *comp)

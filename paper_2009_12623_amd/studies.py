@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import torch
 
+from . import fwigrad as F
 from .metrics import field_errors
 
 
@@ -44,6 +45,12 @@ def compressibility_over_time(ctx, shot, m, wavelet, atol: float, every: int, st
     return rows
 
 
+def _refused(atol, **kw):
+    """row of a tolerance the codec refuses: the field holds values at or
+    above atol 2^23, where |x - x_hat| <= atol cannot be guaranteed"""
+    return dict({"atol": atol, "refused": "FWI_ERANGE"}, **kw)
+
+
 def lossy_restart(ctx, shot, m, wavelet, k0: int, atols, k1: int | None = None):
     """Advance to step k0, compress both leapfrog levels at each atol, and
     continue to k1 (default nt) from the decompressed state; rows of the
@@ -58,7 +65,13 @@ def lossy_restart(ctx, shot, m, wavelet, k0: int, atols, k1: int | None = None):
     ctx.forward_span(shot, m, wavelet, k0, k1, e1, e0, d_ex)
     rows = []
     for atol in atols:
-        s1, s0 = ctx.compress(u1, atol), ctx.compress(u0, atol)
+        try:
+            s1, s0 = ctx.compress(u1, atol), ctx.compress(u0, atol)
+        except F.FwiError as e:
+            if e.code != F.FWI_ERANGE:
+                raise
+            rows.append(_refused(atol))
+            continue
         cf = 2 * 4.0 * m.numel() / (s1.numel() + s0.numel())
         a1, a0 = ctx.decompress(s1, m.shape), ctx.decompress(s0, m.shape)
         start = field_errors(u1, a1)
@@ -82,7 +95,13 @@ def gradient_error_vs_atol(ctx, shot, m, wavelet, d_obs, atols, nslots: int | No
     g_ex = g_ex.clone()
     rows = []
     for atol in atols:
-        phi, g = ctx.gradient(shot, m, wavelet, d_obs, nslots=s, compress=True, atol=atol)
+        try:
+            phi, g = ctx.gradient(shot, m, wavelet, d_obs, nslots=s, compress=True, atol=atol)
+        except F.FwiError as e:
+            if e.code != F.FWI_ERANGE:
+                raise
+            rows.append(_refused(atol, nslots=s))
+            continue
         st = ctx.stats()
         er = field_errors(g_ex, g)
         rows.append(_round({"atol": atol, "nslots": s,
@@ -101,7 +120,13 @@ def gradient_error_vs_slots(ctx, shot, m, wavelet, d_obs, slots, atols):
     rows = []
     for atol in atols:
         for s in slots:
-            _, g = ctx.gradient(shot, m, wavelet, d_obs, nslots=s, compress=True, atol=atol)
+            try:
+                _, g = ctx.gradient(shot, m, wavelet, d_obs, nslots=s, compress=True, atol=atol)
+            except F.FwiError as e:
+                if e.code != F.FWI_ERANGE:
+                    raise
+                rows.append(_refused(atol, nslots=s))
+                continue
             st = ctx.stats()
             er = field_errors(g_ex, g)
             rows.append(_round({"atol": atol, "nslots": s, "forward_steps": st["n_forward"],
@@ -125,20 +150,46 @@ def subsampling_error(ctx, shot, m, wavelet, d_obs, factors):
     return rows
 
 
-def stacking_error(ctx, shots, models, wavelet, d_obs, atol: float, nslots: int):
-    """Shots sharing one grid: the stack (sum) of the first n lossy
-    gradients against the stack of the first n exact ones, n = 1..len."""
-    _, g_ex = ctx.gradient_batch(shots, models, wavelet, d_obs, nslots=nslots)
-    _, g_lo = ctx.gradient_batch(shots, models, wavelet, d_obs, nslots=nslots, compress=True, atol=atol)
-    se = torch.zeros_like(g_ex[0], dtype=torch.float64)
+def stacking_error(ctx, shots, models, wavelet, d_obs, atol: float, nslots: int, dims=None,
+                   origins=None, group: int | None = None, counts=None):
+    """Stack (sum over shots, Sec. 4 "Stacking") of the first n lossy
+    gradients against the stack of the first n exact ones.  Shots sharing
+    one grid stack their whole gradients; crops of one model (``dims``: the
+    model's physical shape, ``origins``: each crop's physical origin in it)
+    stack their physical parts placed at their origins, as the library's
+    fwi_gradient_stack does.  Exact gradients run ``group`` shots per batched
+    call (bounds the exact checkpoints' memory); ``counts`` (default
+    1..len) lists the n reported."""
+    n = len(shots)
+    group = n if group is None else group
+    g_lo = ctx.gradient_batch(shots, models, wavelet, d_obs, nslots=nslots, compress=True, atol=atol)[1]
+    g_ex = []
+    for i in range(0, n, group):
+        j = min(n, i + group)
+        g_ex += [g.clone() for g in ctx.gradient_batch(shots[i:j], models[i:j], wavelet, d_obs[i:j],
+                                                       nslots=nslots)[1]]
+
+    def place(acc, g, i):
+        if origins is None:
+            acc += g.double()
+            return
+        nb = shots[i].nbl
+        phys = g[tuple(slice(nb, -nb) if nb else slice(None) for _ in range(g.dim()))]
+        sl = tuple(slice(o, o + w) for o, w in zip(origins[i], phys.shape))
+        acc[sl] += phys.double()
+
+    shape = tuple(g_ex[0].shape) if origins is None else tuple(dims)
+    se = torch.zeros(shape, dtype=torch.float64, device=g_ex[0].device)
     sl = torch.zeros_like(se)
+    want = set(range(1, n + 1) if counts is None else counts)
     rows = []
-    for n, (a, b) in enumerate(zip(g_ex, g_lo), 1):
-        se += a.double()
-        sl += b.double()
-        er = field_errors(se, sl)
-        rows.append(_round({"shots": n, "psnr_db": er["psnr_db"], "angle_rad": er["angle_rad"],
-                            "rel_l2": er["rel_l2"]}))
+    for k, (a, b) in enumerate(zip(g_ex, g_lo)):
+        place(se, a, k)
+        place(sl, b, k)
+        if k + 1 in want:
+            er = field_errors(se, sl)
+            rows.append(_round({"shots": k + 1, "psnr_db": er["psnr_db"], "angle_rad": er["angle_rad"],
+                                "rel_l2": er["rel_l2"]}))
     return rows
 
 

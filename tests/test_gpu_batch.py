@@ -192,7 +192,10 @@ def test_stacked_crops_match_oracle_placed_sum(ctx, ndim, widths, depth, so, com
     FP64 oracle's per-crop gradients placed and summed in FP64 match it to
     1e-4 (exact checkpoints; compressed within 1e-3 of exact), and two runs
     are bitwise equal"""
-    full, shots, q32 = crops_with_origins(ndim, widths, depth, so)
+    # 3D: a stronger perturbation and a longer axis keep every crop's
+    # residual above 2 % of its data (FP32 conditioning)
+    full, shots, q32 = (crops_with_origins(ndim, widths, depth, so) if ndim == 2
+                        else crops_with_origins(ndim, widths, depth, so, nt=70, amp=8.0))
     nbl = shots[0][0].nbl
     q = dev(q32)
     d_obs, ref = [], np.zeros(full)

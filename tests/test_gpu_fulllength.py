@@ -5,7 +5,8 @@ overlapped):
 
 * one shot of the 2D survey workload at full size and full length (1001 x
   401 at 10 m, 1081 x 481 with the layer, SO16, 3000 steps): traces, Phi and
-  the exact-checkpoint gradient against the oracle's store-all gradient;
+  the exact-checkpoint gradient against the oracle's store-all gradient
+  (observed data from velocities 3 % above the starting model);
 * a 3D SO8 shot over the 3D workload's 2000 steps (its spacing, time step,
   wavelet and model generator) on a reduced 40^3 grid with a 20-point layer.
 
@@ -66,7 +67,10 @@ def _compare(shot, m0h, mth, q32, tag):
 def test_2d_survey_shot_full_length():
     shot = synth.config5_shots(nt=3000)[7]
     v0 = synth.smooth_2d()
-    vt = synth.blobs_2d(v0)
+    # observed data from velocities 3 % above the starting model: the
+    # survey's blobs change this shot's traces by only 0.1 %, which would
+    # leave the FP32 residual ill-conditioned
+    vt = 1.03 * v0
     m0h = synth.slowness2(synth.extend(v0, shot.nbl)).astype(np.float32)
     mth = synth.slowness2(synth.extend(vt, shot.nbl)).astype(np.float32)
     _compare(shot, m0h, mth, shot.wavelet().astype(np.float32), "2D SO16 1081x481 3000 steps")

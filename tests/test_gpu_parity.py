@@ -214,7 +214,7 @@ def test_compressed_gradient_close_to_exact(ctx, ndim, so):
     dobs = ctx.forward(shot, dev(mt), dev(q))
     _, gexact = ctx.gradient(shot, dev(m0), dev(q), dobs, nslots=5)
     errs = []
-    for atol in (1e-2, 1e-4, 1e-6):
+    for atol in (1e-2, 1e-4, 1e-5):
         _, gc = ctx.gradient(shot, dev(m0), dev(q), dobs, nslots=5, compress=True, atol=atol)
         errs.append(metrics.rel_l2(gc.cpu().numpy(), gexact.cpu().numpy()))
         st = ctx.stats()
@@ -225,14 +225,18 @@ def test_compressed_gradient_close_to_exact(ctx, ndim, so):
 
 
 @pytest.mark.parametrize("ndim,n,so,nt,nslots", [(2, 40, 4, 60, 4), (2, 90, 16, 160, 6),
-                                                (3, 24, 8, 90, 5), (3, 20, 16, 60, 60)])
+                                                (3, 24, 8, 90, 5), (3, 20, 16, 100, 100)])
 def test_compressed_gradient_matches_oracle_compressed(ctx, ndim, n, so, nt, nslots):
     """lossy GPU gradient (atol 1e-4) against the oracle's lossy gradient
     (FP64 states rounded to float32 and compressed, Sec. 3) at the same bar
     as the exact gradient; each side compresses its own states, so the
     streams may differ where a value sits on a quantisation boundary"""
     shot = synth.tiny_shot(ndim, n=n, so=so, nbl=6, nt=nt)
-    m0, mt, q = inputs(shot)
+    v0, vt = synth.tiny_models(shot.shape, seed=3)
+    vt = v0 * (1.0 + 4.0 * (vt / v0 - 1.0))          # a residual of several % of the data
+    m0 = synth.slowness2(synth.extend(v0, shot.nbl)).astype(np.float32)
+    mt = synth.slowness2(synth.extend(vt, shot.nbl)).astype(np.float32)
+    q = shot.wavelet().astype(np.float32)
     p0 = oracle_problem(shot, m0, q)
     dobs = solver.forward(oracle_problem(shot, mt, q))
     st = {}
@@ -475,7 +479,7 @@ def test_gradient_error_paths(ctx):
         small.gradient(shot, dev(m0), dev(q), dobs, nslots=3)
     assert e.value.code == F.FWI_ECAPACITY
     with pytest.raises(F.FwiError) as e:
-        small.gradient(shot, dev(m0), dev(q), dobs, nslots=3, compress=True, atol=1e-6)
+        small.gradient(shot, dev(m0), dev(q), dobs, nslots=3, compress=True, atol=1e-6, pool_bytes=256)
     assert e.value.code == F.FWI_ECAPACITY
     small.close()
 

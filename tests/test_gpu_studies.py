@@ -41,8 +41,8 @@ def test_compressibility_and_restart(ctx):
     rows = studies.compressibility_over_time(ctx, shot, mt, q, 1e-4, every=7)
     assert [r["step"] for r in rows] == [7, 14, 21, 28, 35, 42, 49, 56, 60]
     assert all(r["cf"] > 1 for r in rows)
-    rr = studies.lossy_restart(ctx, shot, mt, q, 30, [1e-2, 1e-4, 1e-6])
-    assert [r["atol"] for r in rr] == [1e-2, 1e-4, 1e-6]
+    rr = studies.lossy_restart(ctx, shot, mt, q, 30, [1e-2, 1e-4, 1e-5])
+    assert [r["atol"] for r in rr] == [1e-2, 1e-4, 1e-5]
     assert rr[0]["final_rel_l2"] > rr[1]["final_rel_l2"] > rr[2]["final_rel_l2"]
     assert rr[0]["cf"] > rr[2]["cf"]
     assert all(r["restart_linf"] <= r["atol"] for r in rr)
@@ -76,16 +76,18 @@ def test_stacking(ctx):
 
 def test_gradient_error_shape_in_atol(ctx):
     """Sec. 4 "Gradient computation": the lossy gradient's error falls as
-    atol falls and flattens once the codec error is below the FP32 floor;
-    the compression factor falls with it"""
+    atol falls, and the compression factor falls with it; a tolerance below
+    what float32 blocks of this wavefield can hold (values at or above
+    atol 2^23 near the source) is refused, not silently missed"""
     shot, m0, mt, q = problem(2, 48, 8, nt=120)
     d = ctx.forward(shot, mt, q)
-    atols = [1e-1, 1e-3, 1e-5, 1e-7, 1e-9]
+    atols = [1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-9]
     rows = studies.gradient_error_vs_atol(ctx, shot, m0, q, d, atols)
+    assert rows[-1] == {"atol": 1e-9, "refused": "FWI_ERANGE", "nslots": shot.nt}
+    rows = rows[:-1]
     err = [r["rel_l2"] for r in rows]
     cf = [r["cf"] for r in rows]
     print("atol", atols, "rel_l2", err, "cf", cf)
     assert all(b <= a * 1.5 for a, b in zip(err, err[1:]))       # no growth as atol falls
     assert err[0] > 100 * err[-1]
-    assert err[-1] <= 2 * err[-2] and err[-2] <= 2 * err[-1] + 1e-12   # flat at the floor
     assert all(b <= a for a, b in zip(cf, cf[1:]))
