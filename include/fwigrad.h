@@ -311,6 +311,19 @@ int ckpt_compress(fwi_ctx *ctx, const float *field, int ndim, const int n[3],
 int ckpt_decompress(fwi_ctx *ctx, const void *stream_bytes, size_t nbytes,
                     float *field, int ndim, const int n[3], hipStream_t stream);
 
+/* ckpt_compress for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no context; the encode workspace (chunk bit strings, lengths, tile sums,
+ * counters, status flags) is a static 32 MiB device array of the library,
+ * one per GPU for the life of the process, so the call allocates nothing.
+ * Same arguments and stream as ckpt_compress on the current device; fields
+ * whose workspace exceeds the array (about 4M values, e.g. 161^3 or 2048^2;
+ * thin fields of many partial blocks fewer) are refused with FWI_EINVAL.
+ * All calls on one GPU share the array: calls that overlap on one GPU race.
+ * Synchronises the stream to return *nbytes and the status. */
+int ckpt_compress_static(const float *field, int ndim, const int n[3], double atol,
+                         void *out, size_t cap, size_t *nbytes, hipStream_t stream);
+
 /* The codec on a field inside a larger array [device]: element (x, y, z)
  * at origin[x*sx + y*sy + z] (2D: origin[x*sx + z]; sy ignored).  The
  * stream is the same as ckpt_compress of the dense field.  padded != 0

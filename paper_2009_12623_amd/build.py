@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfwigrad.so")
-SOURCES = ["stencil.hip", "codec.hip", "runtime.cpp", "revolve.cpp"]
+SOURCES = ["stencil.hip", "codec.hip", "runtime.cpp", "revolve.cpp", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

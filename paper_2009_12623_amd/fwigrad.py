@@ -90,7 +90,7 @@ EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_s
            "ckpt_compress_view", "ckpt_decompress_view", "fwi_forward_ckpt_batch",
            "fwi_backward_batch", "fwi_gradient_subsampled", "fwi_forward_span",
            "fwi_ctx_set_overlap", "fwi_time_shape", "fwi_tape_stream", "fwi_gradient_stack",
-           "fwi_backward_stack"]
+           "fwi_backward_stack", "ckpt_compress_static"]
 
 
 def lib():
@@ -153,6 +153,8 @@ def lib():
                                      ctypes.POINTER(fwi_ckpt_cfg), ctypes.POINTER(fwi_stack), P,
                                      ctypes.POINTER(ctypes.c_double), P]
     L.fwi_backward_stack.argtypes = [P, P, ctypes.POINTER(P), ctypes.POINTER(fwi_stack), P, P]
+    L.ckpt_compress_static.argtypes = [P, I, ctypes.POINTER(ctypes.c_int), ctypes.c_double, P, ctypes.c_size_t,
+                                       ctypes.POINTER(ctypes.c_size_t), P]
     L.fwi_tape_stream.argtypes = [P, I, I, I, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]
     L.fwi_time_shape.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot),
                                  ctypes.POINTER(ctypes.c_int), I, ctypes.POINTER(ctypes.c_double),
@@ -192,6 +194,17 @@ def fwi_bandwidth_probe(srcs, dsts, width=4, grid=8192):
     for t in list(srcs) + list(dsts):
         _ptr(t)
     check(lib().fwi_bandwidth_probe(sp, len(srcs), dp, len(dsts), n, int(width), int(grid), _stream()))
+
+
+def ckpt_compress_static(field: torch.Tensor, atol: float) -> torch.Tensor:
+    """ckpt_compress_static: the codec stream of a field, written with the
+    library's static workspace (no allocation inside the call)"""
+    cap = ckpt_bound(field.shape)
+    out = torch.empty(cap, dtype=torch.uint8, device=field.device)
+    nb = ctypes.c_size_t()
+    check(lib().ckpt_compress_static(_ptr(field), field.dim(), _dims3(field.shape), float(atol), _ptr(out), cap,
+                                     ctypes.byref(nb), _stream()))
+    return out[:nb.value]
 
 
 # ---------------------------------------------------------- host-only calls
