@@ -115,6 +115,8 @@ typedef struct {
     long long ckpt_bytes;     /* sum of stored checkpoint bytes */
     long long ckpt_raw_bytes; /* raw bytes those checkpoints represent */
     long long pool_high;      /* high-water mark of the pool (bytes) */
+    long long graphs_captured; /* schedules captured into a hipGraph by the call */
+    long long graphs_replayed; /* captured schedules the call replayed */
 } fwi_stats;
 
 /* Revolve action (see fwi_revolve_plan). */
@@ -133,12 +135,16 @@ int fwi_ctx_destroy(fwi_ctx *ctx);
 /* Collect per-kernel HIP-event timings in later calls (small overhead). */
 int fwi_ctx_set_timing(fwi_ctx *ctx, int on);
 int fwi_ctx_stats(const fwi_ctx *ctx, fwi_stats *out);
-/* Captured schedules: with on != 0, fwi_gradient and fwi_gradient_batch
- * record the whole checkpoint schedule of a call (every step, codec and
- * receiver launch) into a hipGraph the first time a call signature (grid,
- * shot, pointers, checkpoint config, launch shapes) is seen, and replay it on
- * later calls with the same signature; a graph is re-captured after any of
- * the library's buffers is reallocated.  Results are identical to direct
+/* Captured schedules: with on != 0, fwi_gradient, fwi_gradient_batch,
+ * fwi_gradient_stack and the tape calls (fwi_forward_ckpt(_batch),
+ * fwi_backward(_batch), fwi_backward_stack) record the whole checkpoint
+ * schedule of a call (every step, codec and receiver launch) into a
+ * hipGraph the first time a call signature (grid, shot, pointers, checkpoint
+ * config, launch shapes; for tapes also the tape's buffers) is seen, and
+ * replay it on later calls with the same signature; a graph is re-captured
+ * after any of the library's buffers is reallocated.  A freed tape's buffers
+ * are kept by its context and reused by the next tape of the same sizes, so
+ * the tapes of an iterative loop replay.  Results are identical to direct
  * launches.  Per-kernel timings are not collected during replays; launch
  * counts are.  Off by default; off drops every graph. */
 int fwi_ctx_set_graphs(fwi_ctx *ctx, int on);

@@ -22,6 +22,8 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -162,6 +164,43 @@ struct BatchTables {
 
 enum Kind { K_FWD = 0, K_ADJ = 1, K_ENC = 2, K_DEC = 3, K_NKIND = 4 };
 
+// Device buffers of a freed tape, kept by its context for the next tape of
+// the same sizes: a captured tape schedule embeds buffer addresses, so
+// reusing them (instead of allocating afresh) lets it replay.
+struct TapeStore {
+    std::vector<size_t> sig;                        // bytes of each buffer, in order
+    std::vector<std::pair<void *, size_t>> bufs;    // (pointer, element count)
+    void release()
+    {
+        for (auto &b : bufs)
+            if (b.first) (void)hipFree(b.first);
+        bufs.clear();
+        sig.clear();
+    }
+};
+
+template <class T>
+void store_put(TapeStore &s, DevBuf<T> &b)
+{
+    s.bufs.push_back({(void *)b.p, b.n});
+    s.sig.push_back(b.n * sizeof(T));
+    b.p = nullptr;
+    b.n = 0;
+}
+
+template <class T>
+void store_take(TapeStore &s, size_t i, DevBuf<T> &b)
+{
+    b.p = (T *)s.bufs[i].first;
+    b.n = s.bufs[i].second;
+    s.bufs[i].first = nullptr;
+}
+
+// contexts alive in this process (a tape freed after its context releases
+// its buffers instead of returning them)
+std::mutex g_ctx_mu;
+std::set<const void *> g_live_ctx;
+
 }  // namespace
 
 struct fwi_ctx {
@@ -243,6 +282,29 @@ struct fwi_ctx {
     std::vector<Iv> ivs;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     std::map<std::pair<int, int>, std::vector<fwi_action>> plans;
+    // storage of freed tapes, newest last (at most TAPE_CACHE entries)
+    static constexpr size_t TAPE_CACHE = 4;
+    std::vector<TapeStore> tape_cache;
+    // a cached store whose buffer sizes equal sig (removed from the cache),
+    // or an empty store
+    TapeStore take_store(const std::vector<size_t> &sig)
+    {
+        for (size_t i = tape_cache.size(); i-- > 0;)
+            if (tape_cache[i].sig == sig) {
+                TapeStore s = std::move(tape_cache[i]);
+                tape_cache.erase(tape_cache.begin() + (long)i);
+                return s;
+            }
+        return TapeStore{};
+    }
+    void keep_store(TapeStore &&s)
+    {
+        tape_cache.push_back(std::move(s));
+        while (tape_cache.size() > TAPE_CACHE) {
+            tape_cache.front().release();
+            tape_cache.erase(tape_cache.begin());
+        }
+    }
 
     hipEvent_t ev()
     {
@@ -1084,6 +1146,23 @@ std::vector<char> restart_flags(const std::vector<fwi_action> &acts)
     return both;
 }
 
+// index of the first reverse step and, for the checkpoints the first sweep
+// takes, whether each slot holds the older level (what a forward tape run
+// leaves behind, derived from the action list so that a replayed capture
+// needs no host work)
+size_t first_sweep(const std::vector<fwi_action> &acts, const std::vector<char> &both,
+                   std::vector<char> &slot_both)
+{
+    slot_both.clear();
+    size_t i = 0;
+    for (; i < acts.size() && acts[i].op != FWI_REVERSE; ++i)
+        if (acts[i].op == FWI_TAKESHOT) {
+            if ((int)slot_both.size() <= acts[i].a) slot_both.resize(acts[i].a + 1, 0);
+            slot_both[acts[i].a] = both[i];
+        }
+    return i;
+}
+
 void check_cfg(const fwi_ckpt_cfg *cfg)
 {
     if (!cfg) throw Error{FWI_EINVAL, "checkpoint config is null"};
@@ -1496,7 +1575,9 @@ void run_schedule(fwi_ctx *c, hipStream_t caller, const std::string &key, size_t
         ge.ckpt_raw_bytes = c->stats.ckpt_raw_bytes - before.ckpt_raw_bytes;
         ge.ckpt_bytes_host = c->stats.ckpt_bytes - before.ckpt_bytes;
         it = c->gcache.emplace(key, ge).first;
+        c->stats.graphs_captured += 1;
     } else {
+        c->stats.graphs_replayed += 1;
         const fwi_ctx::GraphEntry &ge = it->second;
         c->stats.n_forward += ge.n_forward;
         c->stats.n_adjoint += ge.n_adjoint;
@@ -1668,6 +1749,10 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         fwi_ctx *c = new fwi_ctx();
         c->device = device;
         c->pool_default = pool_bytes;
+        {
+            std::lock_guard<std::mutex> lock(g_ctx_mu);
+            g_live_ctx.insert(c);
+        }
         if (const char *e = std::getenv("FWI_XCHUNK")) c->xchunk3 = std::atoi(e);
         if (const char *e = std::getenv("FWI_RPL")) c->rpl3 = std::atoi(e) == 4 ? 4 : 2;
         if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::max(0, std::min(std::atoi(e), 2));
@@ -1681,8 +1766,14 @@ int fwi_ctx_destroy(fwi_ctx *c)
 {
     return guarded([&] {
         if (!c) return;
+        {
+            std::lock_guard<std::mutex> lock(g_ctx_mu);
+            g_live_ctx.erase(c);
+        }
         (void)hipSetDevice(c->device);
         (void)hipDeviceSynchronize();
+        for (auto &ts : c->tape_cache) ts.release();
+        c->tape_cache.clear();
         for (auto e : c->evpool) (void)hipEventDestroy(e);
         for (auto e : c->spool) (void)hipEventDestroy(e);
         if (c->cstream) (void)hipStreamDestroy(c->cstream);
@@ -2091,7 +2182,10 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
             const size_t cap = cfg->pool_bytes ? cfg->pool_bytes : c->pool_default;
             double wsum = 0;
             for (auto &S : setups) wsum += (double)S.pad.elems();
+            const size_t nsl = (size_t)std::max(2 * used, 1);
+            std::vector<size_t> sig;
             for (int i = 0; i < nshots; ++i) {
+                ensure_fields(c->batch[i].get(), setups[i]);
                 auto sh = std::make_unique<fwi_tape::Shot>();
                 sh->grid = grids[i];
                 sh->shot = shots[i];
@@ -2099,10 +2193,32 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
                 sh->shot.rec = sh->rec.data();
                 sh->m = models[i];
                 sh->cap = ((size_t)((double)cap * ((double)setups[i].pad.elems() / wsum))) & ~(size_t)255;
-                sh->pool.ensure(sh->cap + 8);
-                sh->slots.ensure((size_t)std::max(2 * used, 1));
-                sh->misc.ensure(4);
+                const size_t pe = c->batch[i]->padded_elems;
+                for (size_t b : {sh->cap + 8, nsl * sizeof(StreamSlot), 4 * sizeof(unsigned long long), pe * 4,
+                                 pe * 4})
+                    sig.push_back(b);
                 t->shots.push_back(std::move(sh));
+            }
+            {
+                // the buffers of an earlier batched tape of the same sizes, if any
+                TapeStore rs = c->take_store(sig);
+                for (int i = 0; i < nshots && !rs.bufs.empty(); ++i) {
+                    fwi_tape::Shot &sh = *t->shots[i];
+                    store_take(rs, 5 * i + 0, sh.pool);
+                    store_take(rs, 5 * i + 1, sh.slots);
+                    store_take(rs, 5 * i + 2, sh.misc);
+                    store_take(rs, 5 * i + 3, sh.xcur);
+                    store_take(rs, 5 * i + 4, sh.xprev);
+                }
+            }
+            for (int i = 0; i < nshots; ++i) {
+                fwi_tape::Shot &sh = *t->shots[i];
+                const size_t pe = c->batch[i]->padded_elems;
+                sh.pool.ensure(sh.cap + 8);
+                sh.slots.ensure(nsl);
+                sh.misc.ensure(4);
+                sh.xcur.ensure(pe);
+                sh.xprev.ensure(pe);
             }
             std::vector<size_t> so, cb, co;
             batch_codec_scratch(c, setups, cfg->compress != 0, so, cb, co);
@@ -2112,7 +2228,6 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
             for (int i = 0; i < nshots; ++i) {
                 fwi_tape::Shot &sh = *t->shots[i];
                 ShotBufs *b = c->batch[i].get();
-                ensure_fields(b, setups[i]);
                 HIPCHK(hipMemsetAsync(sh.misc.p, 0, 4 * sizeof(unsigned long long), st));
                 Exec e{c, setups[i], st, models[i], &sh.shot, b};
                 e.misc = sh.misc.p;
@@ -2126,18 +2241,32 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
                 e.init_fields();
                 ex.push_back(std::move(e));
             }
-            c->btab.ensure(table_bytes_of(t->acts, (size_t)nshots));
-            BatchExec bx{c, st, ex, setups[0].ndim, setups[0].R, c->btab.dev.p, true, {}};
-            t->next = bx.run(t->acts, t->both, 0, true);
+            std::vector<char> sb;
+            t->next = first_sweep(t->acts, t->both, sb);
+            for (auto &sh : t->shots) sh->slot_both = sb;
+            const size_t nbytes_tab = table_bytes_of(t->acts, (size_t)nshots);
+            c->btab.ensure(nbytes_tab);     // before any capture: it may allocate
+            KeyBuilder key;
+            key.add('f').add(nshots).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
             for (int i = 0; i < nshots; ++i) {
-                fwi_tape::Shot &sh = *t->shots[i];
-                const size_t pe = c->batch[i]->padded_elems;
-                sh.slot_both = ex[i].slot_both;
-                sh.xcur.ensure(pe);
-                sh.xprev.ensure(pe);
-                launch_copy(sh.xcur.p, ex[i].cur, pe, st);
-                launch_copy(sh.xprev.p, ex[i].prev, pe, st);
+                const fwi_tape::Shot &sh = *t->shots[i];
+                key_shot(key, c, &grids[i], &shots[i], setups[i]);
+                key.add(models[i]).add(d_sim[i]).add(sh.pool.p).add(sh.slots.p).add(sh.misc.p).add(sh.xcur.p)
+                    .add(sh.xprev.p);
             }
+            run_schedule(c, st, key.s, nbytes_tab, [&](char *gtab, hipStream_t rs) {
+                c->btab.used = 0;
+                for (auto &e : ex) e.st = rs;
+                BatchExec bx{c, rs, ex, setups[0].ndim, setups[0].R, gtab ? gtab : c->btab.dev.p, gtab == nullptr, {}};
+                bx.run(t->acts, t->both, 0, true);
+                for (int i = 0; i < nshots; ++i) {
+                    fwi_tape::Shot &sh = *t->shots[i];
+                    const size_t pe = c->batch[i]->padded_elems;
+                    launch_copy(sh.xcur.p, ex[i].cur, pe, rs);
+                    launch_copy(sh.xprev.p, ex[i].prev, pe, rs);
+                }
+                for (auto &e : ex) e.st = st;
+            });
             HIPCHK(hipGetLastError());
             finish_status(c, st);
             end_call(c, st);
@@ -2194,10 +2323,25 @@ static int backward_batch_impl(fwi_ctx *c, fwi_tape *t, const float *const *dd, 
             e.slot_both = sh.slot_both;
             ex.push_back(std::move(e));
         }
-        c->btab.ensure(table_bytes_of(t->acts, (size_t)nshots));
-        BatchExec bx{c, st, ex, setups[0].ndim, setups[0].R, c->btab.dev.p, true, {}};
-        bx.run(t->acts, t->both, t->next, false);
-        finish_gradients(c, ex, grads, smaps, sk, gstack, st);
+        const size_t nbytes_tab = table_bytes_of(t->acts, (size_t)nshots);
+        c->btab.ensure(nbytes_tab);     // before any capture: it may allocate
+        KeyBuilder key;
+        key.add('b').add(nshots).add(t->cfg.nslots).add(t->cfg.compress).add(t->cfg.atol).add(t->next);
+        for (int i = 0; i < nshots; ++i) {
+            const fwi_tape::Shot &sh = *t->shots[i];
+            key_shot(key, c, &sh.grid, &sh.shot, setups[i]);
+            key.add(sh.m).add(dd[i]).add(grads ? grads[i] : nullptr).add(sh.pool.p).add(sh.slots.p).add(sh.misc.p)
+                .add(sh.xcur.p).add(sh.xprev.p).add(sh.cap);
+        }
+        key_stack(key, sk, nshots, gstack);
+        run_schedule(c, st, key.s, nbytes_tab, [&](char *gtab, hipStream_t rs) {
+            c->btab.used = 0;
+            for (auto &e : ex) e.st = rs;
+            BatchExec bx{c, rs, ex, setups[0].ndim, setups[0].R, gtab ? gtab : c->btab.dev.p, gtab == nullptr, {}};
+            bx.run(t->acts, t->both, t->next, false);
+            finish_gradients(c, ex, grads, smaps, sk, gstack, rs);
+            for (auto &e : ex) e.st = st;
+        });
         HIPCHK(hipGetLastError());
         finish_status(c, st);
         t->used = true;
@@ -2240,21 +2384,40 @@ int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_sh
             FieldView fv = padded_view(ex.S);
             if (cfg->compress) ensure_codec(c, fv, 1);
             const size_t cap = cfg->pool_bytes ? cfg->pool_bytes : c->pool_default;
+            const size_t pe = c->sb.padded_elems;
+            const size_t nsl = (size_t)std::max(2 * used, 1);
+            {
+                // the buffers of an earlier tape of the same sizes, if any
+                TapeStore rs = c->take_store({cap + 8, nsl * sizeof(StreamSlot), pe * 4, pe * 4});
+                if (!rs.bufs.empty()) {
+                    store_take(rs, 0, t->pool);
+                    store_take(rs, 1, t->slots);
+                    store_take(rs, 2, t->xcur);
+                    store_take(rs, 3, t->xprev);
+                }
+            }
             t->pool.ensure(cap + 8);
-            t->slots.ensure((size_t)std::max(2 * used, 1));
+            t->slots.ensure(nsl);
+            t->xcur.ensure(pe);
+            t->xprev.ensure(pe);
             reset_status(c, st);
             setup_ckpt(ex, cfg, t->pool.p, cap, t->slots.p, used);
             ex.dsim = d_sim;
             ex.init_fields();
             t->both = restart_flags(t->acts);
-            t->next = ex.run(t->acts, t->both, 0, true);
-            t->slot_both = ex.slot_both;
-            t->xcur.ensure(c->sb.padded_elems);
-            t->xprev.ensure(c->sb.padded_elems);
-            HIPCHK(hipMemcpyAsync(t->xcur.p, ex.cur, c->sb.padded_elems * sizeof(float),
-                                  hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(t->xprev.p, ex.prev, c->sb.padded_elems * sizeof(float),
-                                  hipMemcpyDeviceToDevice, st));
+            t->next = first_sweep(t->acts, t->both, t->slot_both);
+            KeyBuilder key;
+            key.add('F');
+            key_shot(key, c, g, shot, ex.S);
+            key.add(m).add(d_sim).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
+            key.add(t->pool.p).add(t->slots.p).add(t->xcur.p).add(t->xprev.p);
+            run_schedule(c, st, key.s, 0, [&](char *, hipStream_t rs) {
+                ex.st = rs;
+                ex.run(t->acts, t->both, 0, true);
+                launch_copy(t->xcur.p, ex.cur, pe, rs);
+                launch_copy(t->xprev.p, ex.prev, pe, rs);
+                ex.st = st;
+            });
             HIPCHK(hipGetLastError());
             finish_status(c, st);
             end_call(c, st);
@@ -2291,8 +2454,17 @@ int fwi_backward(fwi_ctx *c, fwi_tape *t, const float *dd, float *grad, hipStrea
         ex.work = t->grid.nt;
         ex.reached = t->grid.nt;
         ex.slot_both = t->slot_both;
-        ex.run(t->acts, t->both, t->next, false);
-        launch_unpad(c->sb.gacc.p, grad, ex.padmap(), st);
+        KeyBuilder key;
+        key.add('U');
+        key_shot(key, c, &t->grid, &t->shot, ex.S);
+        key.add(t->m).add(dd).add(grad).add(t->cfg.nslots).add(t->cfg.compress).add(t->cfg.atol).add(cap);
+        key.add(t->pool.p).add(t->slots.p).add(t->xcur.p).add(t->xprev.p);
+        run_schedule(c, st, key.s, 0, [&](char *, hipStream_t rs) {
+            ex.st = rs;
+            ex.run(t->acts, t->both, t->next, false);
+            launch_unpad(c->sb.gacc.p, grad, ex.padmap(), rs);
+            ex.st = st;
+        });
         HIPCHK(hipGetLastError());
         finish_status(c, st);
         t->used = true;
@@ -2304,8 +2476,30 @@ int fwi_tape_free(fwi_tape *t)
 {
     return guarded([&] {
         if (!t) return;
-        t->pool.release(); t->slots.release(); t->xcur.release(); t->xprev.release();
-        for (auto &sh : t->shots) sh->release();
+        // the buffers go back to the context (for the next tape of the same
+        // sizes) while it lives, else to the device
+        TapeStore rs;
+        if (t->shots.empty()) {
+            store_put(rs, t->pool);
+            store_put(rs, t->slots);
+            store_put(rs, t->xcur);
+            store_put(rs, t->xprev);
+        } else {
+            for (auto &sh : t->shots) {
+                store_put(rs, sh->pool);
+                store_put(rs, sh->slots);
+                store_put(rs, sh->misc);
+                store_put(rs, sh->xcur);
+                store_put(rs, sh->xprev);
+            }
+        }
+        bool alive;
+        {
+            std::lock_guard<std::mutex> lock(g_ctx_mu);
+            alive = g_live_ctx.count(t->ctx) != 0;
+        }
+        if (alive) t->ctx->keep_store(std::move(rs));
+        else rs.release();
         delete t;
     });
 }

@@ -50,7 +50,7 @@ class fwi_stats(ctypes.Structure):
                 ("ms_total", "ms_forward", "ms_adjoint", "ms_encode", "ms_decode")] + \
                [(n, ctypes.c_longlong) for n in
                 ("n_forward", "n_adjoint", "n_encode", "n_decode", "ckpt_bytes",
-                 "ckpt_raw_bytes", "pool_high")]
+                 "ckpt_raw_bytes", "pool_high", "graphs_captured", "graphs_replayed")]
 
 
 class fwi_tune_result(ctypes.Structure):
@@ -456,7 +456,7 @@ class Context:
         return out
 
     def forward_ckpt_batch(self, shots, models, wavelets, nslots=10, compress=False, atol=1e-4,
-                           pool_bytes=0):
+                           pool_bytes=0, d_sim=None):
         """fwi_forward_ckpt_batch: (list of d_sim, batched Tape)"""
         n = len(shots)
         if not isinstance(wavelets, (list, tuple)):
@@ -466,7 +466,7 @@ class Context:
         cshots = (fwi_shot * n)(*[sa.c for sa in sas])
         ms = (ctypes.c_void_p * n)(*[_ptr(m) for m in models])
         ds = [torch.empty((s.nt, sa.nrec), dtype=torch.float32, device=models[0].device)
-              for s, sa in zip(shots, sas)]
+              for s, sa in zip(shots, sas)] if d_sim is None else list(d_sim)
         dp = (ctypes.c_void_p * n)(*[_ptr(d) for d in ds])
         cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), float(atol), int(pool_bytes))
         t = ctypes.c_void_p()
@@ -484,11 +484,11 @@ class Context:
         check(lib().fwi_backward_batch(self.h, tape.handle, dp, gp, _stream()))
         return outs
 
-    def forward_ckpt(self, shot, m, wavelet, nslots=10, compress=False, atol=1e-4, pool_bytes=0):
+    def forward_ckpt(self, shot, m, wavelet, nslots=10, compress=False, atol=1e-4, pool_bytes=0, d_sim=None):
         sa = ShotArgs(shot, wavelet)
         g = grid_of(shot)
         cfg = fwi_ckpt_cfg(int(nslots), int(bool(compress)), float(atol), int(pool_bytes))
-        d = torch.empty((shot.nt, sa.nrec), dtype=torch.float32, device=m.device)
+        d = torch.empty((shot.nt, sa.nrec), dtype=torch.float32, device=m.device) if d_sim is None else d_sim
         t = ctypes.c_void_p()
         check(lib().fwi_forward_ckpt(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c),
                                      ctypes.byref(cfg), _ptr(d), ctypes.byref(t), _stream()))

@@ -100,3 +100,74 @@ def test_graph_on_a_user_stream():
     s.synchronize()
     assert torch.equal(g, g0) and phi == phi0
     c.close()
+
+
+@pytest.mark.parametrize("ndim,compress", [(2, True), (3, False), (3, True)])
+def test_tape_graphs_replay_equal_direct(ndim, compress):
+    """the split (autograd) form: forward tape and backward captured once,
+    then replayed with the tape buffers the context keeps from the freed
+    tape, equal bit for bit to direct launches every time"""
+    c = F.Context(0, pool_bytes=1 << 27)
+    shot, m0, mt, q = problem(ndim, 40 if ndim == 2 else 16, 8, nt=40)
+    d_obs = c.forward(shot, mt, q)
+    d0, tape = c.forward_ckpt(shot, m0, q, nslots=4, compress=compress, atol=1e-4, pool_bytes=1 << 25)
+    dd = (d0 - d_obs).contiguous()
+    g0 = c.backward(tape, dd)
+    tape.free()
+    c.set_graphs(True)
+    d, g = torch.empty_like(d0), torch.empty_like(m0)
+    for i in range(4):
+        d.fill_(float("nan"))
+        g.fill_(float("nan"))
+        _, tape = c.forward_ckpt(shot, m0, q, nslots=4, compress=compress, atol=1e-4, pool_bytes=1 << 25,
+                                 d_sim=d)
+        sf = c.stats()
+        c.backward(tape, dd, grad=g)
+        sb = c.stats()
+        tape.free()
+        assert torch.equal(d, d0) and torch.equal(g, g0), i
+        if i > 0:
+            assert sf["graphs_replayed"] == 1 and sb["graphs_replayed"] == 1, (i, sf, sb)
+        c.forward(shot, mt, q)           # eager work between replays
+        torch.cuda.synchronize()
+    c.close()
+
+
+@pytest.mark.parametrize("compress", [True, False])
+def test_batched_tape_graphs_replay_equal_direct(compress):
+    """the batched autograd op's calls (forward tape, stacked backward) with
+    graphs on: replays equal direct launches bit for bit"""
+    c = F.Context(0, pool_bytes=1 << 28)
+    base, m0, mt, q = problem(2, 44, 8, nt=40)
+    shots = []
+    for x in (6, 20, 37):
+        s = synth.Shot(2, base.shape, base.h, base.so, base.nbl, base.nt, base.dt, base.vmax, base.f0,
+                       (x, 2), base.rec)
+        shots.append(s)
+    d_obs = [c.forward(s, mt, q) for s in shots]
+    ref_ds, tape = c.forward_ckpt_batch(shots, [m0] * 3, q, nslots=4, compress=compress, atol=1e-4,
+                                        pool_bytes=1 << 26)
+    dds = [(a - b).contiguous() for a, b in zip(ref_ds, d_obs)]
+    dims = tuple(m0.shape)
+    g0 = c.backward_stack(tape, dds, dims, 0, [(0, 0)] * 3)
+    tape.free()
+    c.set_graphs(True)
+    ds = [torch.empty_like(x) for x in ref_ds]
+    g = torch.empty_like(m0)
+    for i in range(3):
+        for x in ds:
+            x.fill_(float("nan"))
+        g.fill_(float("nan"))
+        _, tape = c.forward_ckpt_batch(shots, [m0] * 3, q, nslots=4, compress=compress, atol=1e-4,
+                                       pool_bytes=1 << 26, d_sim=ds)
+        sf = c.stats()
+        c.backward_stack(tape, dds, dims, 0, [(0, 0)] * 3, grad=g)
+        sb = c.stats()
+        tape.free()
+        for a, b in zip(ds, ref_ds):
+            assert torch.equal(a, b), i
+        assert torch.equal(g, g0), i
+        if i > 0:
+            assert sf["graphs_replayed"] == 1 and sb["graphs_replayed"] == 1, (i, sf, sb)
+        torch.cuda.synchronize()
+    c.close()
