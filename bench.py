@@ -278,6 +278,22 @@ def run_c2(args, torch, F, dev):
     trend = {}
     for k, u in snaps.items():
         trend[k] = round(4.0 * n / ctx.compress(u, 1e-4).numel(), 3)
+    # One field of the 3D single-shot gradient's size (961 x 961 x 367,
+    # 5.3M blocks: the launch the gradient's codec makes), built by tiling
+    # the snapshot: the codec's own rate at that launch size.
+    big = x.repeat(4, 4, 2)[:961, :961, :367].contiguous()
+    c3_field = []
+    for atol in (1e-2, 1e-4):
+        st, te = timed(lambda: ctx.compress(big, atol), "ms_encode", max(args.steps, 5))
+        y, td = timed(lambda: ctx.decompress(st, big.shape), "ms_decode", max(args.steps, 5))
+        err = (y - big).abs().max().item()
+        assert err <= atol, (atol, err)
+        c3_field.append({"atol": atol, "ratio": round(4.0 * big.numel() / st.numel(), 2),
+                         "compress_ms": round(te, 4), "decompress_ms": round(td, 4),
+                         "compress_GBs": round(4.0 * big.numel() / (te * 1e-3) / 1e9, 1),
+                         "decompress_GBs": round(4.0 * big.numel() / (td * 1e-3) / 1e9, 1)})
+        log("961x961x367 field", c3_field[-1])
+    del big, y
     main = next(r for r in rows if r["atol"] == 1e-4)
     bytes_enc = 4.0 * n * (1 + 1 / main["ratio"])
     achieved = bytes_enc / (main["compress_ms"] * 1e-3) / 1e9
@@ -299,6 +315,7 @@ def run_c2(args, torch, F, dev):
                              "per-lane bit work, not HBM"},
         "sweep": rows,
         "ratio_by_step_atol_1e-4": trend,
+        "field_961x961x367": c3_field,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_codec_baseline(
@@ -354,6 +371,24 @@ def run_c4(args, torch, F, dev):
     torch.cuda.synchronize()
     t_b = (time.time() - t0) / args.steps
     st = ctx.stats()
+    graphs = None
+    if args.graphs:
+        # the same calls with the schedule captured once and replayed
+        ctx.set_graphs(True)
+        gout = [torch.empty_like(m) for m in m0s]
+        ctx.gradient_batch(shots, m0s, q, d_obs, nslots=nslots, compress=True, atol=args.atol, grads=gout)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for i in range(args.steps):
+            ctx.gradient_batch(shots, m0s, q, d_obs, nslots=nslots, compress=True, atol=args.atol, grads=gout)
+        torch.cuda.synchronize()
+        t_g = (time.time() - t0) / args.steps
+        graphs = {"s_per_shot": round(t_g / len(shots), 4), "speedup_vs_direct_launches": round(t_b / t_g, 3),
+                  "replayed_last_call": ctx.stats()["graphs_replayed"],
+                  "equal_to_direct_launches": all(bool(torch.equal(a, b)) for a, b in zip(gout, grads))}
+        log("captured schedule: %s" % graphs)
+        del gout
+        ctx.set_graphs(False)
     # the same shots one at a time (same schedule and codec settings)
     t0 = time.time()
     seq_err = 0.0
@@ -416,6 +451,7 @@ def run_c4(args, torch, F, dev):
         "grad_rel_l2_compressed_vs_exact_first_shots": [float("%.3e" % e) for e in errs],
         "kernel_ms": {k: round(st[k], 1) for k in ("ms_forward", "ms_adjoint", "ms_encode", "ms_decode", "ms_total")},
         "ckpt_compression_factor": round(st["ckpt_raw_bytes"] / max(st["ckpt_bytes"], 1), 2),
+        "captured_schedule": graphs,
         "model_gradient": {"dims": [401, 401, 201], "s": round(t_stack, 3),
                            "l2_norm": float("%.4g" % g_model.double().norm().item()),
                            "nonzero_points": covered,
@@ -457,10 +493,13 @@ def run_c5(args, torch, F, dev):
         loss.backward()
         return float(loss.detach()), m.grad
 
+    last = {}
+
     def batched(compress):
         m = m0.clone().requires_grad_(True)
         ds = F.forward_modelling_batch(ctx, m, shots, q, nslots=nslots, compress=compress,
                                        atol=args.atol)
+        last["forward"] = ctx.stats()
         loss = 0.0
         for d, o in zip(ds, d_obs):
             r = d - o
@@ -485,6 +524,34 @@ def run_c5(args, torch, F, dev):
     t_c = (time.time() - t0) / args.steps
     st = ctx.stats()            # last call: the batched backward
     err = rel_l2(g_c, g_u)
+    # the same iterations with captured schedules (the tapes' buffers are
+    # kept by the context, so every call after the first replays its graph)
+    graphs = None
+    if args.graphs:
+        ctx.set_graphs(True)
+        for _ in range(max(args.warmup, 1)):
+            batched(False)
+            batched(True)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        for i in range(args.steps):
+            _, g_ug = batched(False)
+        torch.cuda.synchronize()
+        t_ug = (time.time() - t0) / args.steps
+        t0 = time.time()
+        for i in range(args.steps):
+            _, g_cg = batched(True)
+        torch.cuda.synchronize()
+        t_cg = (time.time() - t0) / args.steps
+        sg = ctx.stats()
+        graphs = {"s_per_shot": round(t_cg / len(shots), 4),
+                  "uncompressed_s_per_shot": round(t_ug / len(shots), 4),
+                  "speedup_vs_direct_launches": round(t_c / t_cg, 3),
+                  "last_iteration_replayed": {"forward": bool(last["forward"]["graphs_replayed"]),
+                                              "backward": bool(sg["graphs_replayed"])},
+                  "equal_to_direct_launches": bool(torch.equal(g_cg, g_c) and torch.equal(g_ug, g_u))}
+        log("captured schedules: %s" % graphs)
+        ctx.set_graphs(False)
     # the same loss through one autograd node per shot
     op_c = F.FwiOperator(ctx, nslots=nslots, compress=True, atol=args.atol)
     gradient(op_c)
@@ -520,6 +587,7 @@ def run_c5(args, torch, F, dev):
                 "fraction is not the binding bound here",
         "schedule_per_shot": {"forward": nf, "adjoint": nt, "encodes": nenc,
                               "restores_uk": rr, "restores_both": ra},
+        "captured_schedules": graphs,
     }
     if not args.no_cpu_baseline:
         ctx.close()
@@ -665,6 +733,8 @@ def main():
                     help="run the checkpoint codec on the launch stream instead of beside the stencil")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-studies", action="store_true", help="skip the stacking study of the c4 workload")
+    ap.add_argument("--graphs", action="store_true",
+                    help="c4/c5: also time the calls with captured schedules (hipGraph replays)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 1 GiB device copies (HBM counter calibration)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -748,9 +818,15 @@ def main():
     torch.cuda.synchronize()
     t_unc = time.time() - t0
     st_u = ctx.stats()
-    budget = st_u["pool_high"] if st_u["pool_high"] else st_u["ckpt_bytes"]
-    budget = max(budget, 2 * s_unc * 4 * npts)
-    log("uncompressed s=%d: %.2f s, phi %.6e, budget %.1f GB" % (s_unc, t_unc, phi_u, budget / 1e9))
+    # The budget is what the uncompressed schedule's fields take stored
+    # densely (its peak field count x the computational grid in FP32); the
+    # library itself keeps exact checkpoints in the padded layout (so that a
+    # restore can alias the slot), which holds ~30 % more.
+    from paper_2009_12623_amd import costmodel
+    peak_unc = costmodel.schedule_counts(F.fwi_revolve_plan, nt, s_unc).peak_fields
+    budget = float(peak_unc * 4 * npts)
+    log("uncompressed s=%d: %.2f s, phi %.6e, pool high %.1f GB (padded), budget %.1f GB (%d dense fields)"
+        % (s_unc, t_unc, phi_u, st_u["pool_high"] / 1e9, budget / 1e9, peak_unc))
 
     # Pilots, one per tolerance (largest first): store-all where its streams
     # fit the budget, else the uncompressed run's slot count.  Each gives
@@ -898,6 +974,7 @@ def main():
             "nslots_uncompressed": s_unc,
             "codec_overlap": not args.no_overlap,
             "hbm_budget_gb": round(budget / 1e9, 2),
+            "uncompressed_pool_high_gb_padded": round(st_u["pool_high"] / 1e9, 2),
             "stencil_shape": None if tune is None else {
                 "forward": [tune["fwd_xchunk"], tune["fwd_rows_per_lane"], tune["fwd_xcd_order"], tune["fwd_deep"],
                             tune["fwd_vz"]],

@@ -128,7 +128,7 @@ typedef struct { int op; int a; int b; } fwi_action;
  * The 3D stencil's launch shape before any fwi_autotune call may be set
  * from the environment at creation (for experiments and tests):
  * FWI_XCHUNK (x planes per workgroup, default 16), FWI_RPL (rows per lane,
- * 2 or 4), FWI_REMAP (tile order 0/1/2), FWI_DEEP (two planes of loads in
+ * 2 or 4), FWI_REMAP (tile order 0-4), FWI_DEEP (two planes of loads in
  * flight, 0/1), FWI_VZ (z points per lane, 1 or 2; 2 ignores FWI_DEEP). */
 int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes);
 int fwi_ctx_destroy(fwi_ctx *ctx);
@@ -143,10 +143,17 @@ int fwi_ctx_stats(const fwi_ctx *ctx, fwi_stats *out);
  * config, launch shapes; for tapes also the tape's buffers) is seen, and
  * replay it on later calls with the same signature; a graph is re-captured
  * after any of the library's buffers is reallocated.  A freed tape's buffers
- * are kept by its context and reused by the next tape of the same sizes, so
- * the tapes of an iterative loop replay.  Results are identical to direct
- * launches.  Per-kernel timings are not collected during replays; launch
- * counts are.  Off by default; off drops every graph. */
+ * are kept by its context (up to 64 tapes while graphs are on, 4 otherwise)
+ * and reused by the next tape of the same sizes, preferring the buffers last
+ * used for the same shots, so the tapes of an iterative loop replay.  The
+ * tape calls' graphs do not depend on the caller's model, trace, adjoint
+ * source or gradient buffers: the model is read before the replay, traces
+ * are recorded into context buffers and copied to d_sim after it, adjoint
+ * sources are copied in before it and gradients leave the context's
+ * accumulators after it, so autograd loops that allocate new tensors every
+ * iteration replay too.  Results are identical to direct launches.
+ * Per-kernel timings are not collected during replays; launch counts are.
+ * Off by default; off drops every graph. */
 int fwi_ctx_set_graphs(fwi_ctx *ctx, int on);
 /* Codec overlap: with on != 0 (the default), fwi_gradient and the
  * single-shot tapes run the checkpoint codec of compressed schedules on a
@@ -374,7 +381,7 @@ int fwi_revolve_plan(int nsteps, int nslots, fwi_action *out, int cap,
  * working fields are cleared (tapes keep their own state). */
 typedef struct {
     int ncand;
-    int fwd_xchunk, fwd_rows_per_lane, fwd_xcd_order;   /* order: 0 round robin, 1 XCD-contiguous, 2 z columns per XCD */
+    int fwd_xchunk, fwd_rows_per_lane, fwd_xcd_order;   /* order: 0 round robin, 1 XCD-contiguous, 2 z columns per XCD, 3/4 groups of 2/4 columns per XCD */
     int adj_xchunk, adj_rows_per_lane, adj_xcd_order;
     double fwd_ms, adj_ms;
     int fwd_deep, adj_deep;       /* two planes of loads in flight */

@@ -168,6 +168,7 @@ enum Kind { K_FWD = 0, K_ADJ = 1, K_ENC = 2, K_DEC = 3, K_NKIND = 4 };
 // the same sizes: a captured tape schedule embeds buffer addresses, so
 // reusing them (instead of allocating afresh) lets it replay.
 struct TapeStore {
+    std::string tag;                                // the shots the tape was recorded for
     std::vector<size_t> sig;                        // bytes of each buffer, in order
     std::vector<std::pair<void *, size_t>> bufs;    // (pointer, element count)
     void release()
@@ -245,7 +246,8 @@ struct fwi_ctx {
     // stencil launch shape; overridden per grid by fwi_autotune
     int xchunk3 = 0;           // 3D x planes per workgroup (0: default)
     int rpl3 = 2;              // 3D rows per lane
-    int remap3 = 0;            // 3D tile order: 0 round robin, 1 XCD-contiguous, 2 z columns per XCD
+    int remap3 = 0;            // 3D tile order: 0 round robin, 1 XCD-contiguous, 2 z columns per XCD,
+                               // 3 and 4 groups of 2 and 4 columns per XCD
     int deep3 = 0;             // 3D two planes of loads in flight
     int vz3 = 1;               // 3D z points per lane (1: 64-point z tiles, 2: 128-point)
     struct Shape {
@@ -282,25 +284,30 @@ struct fwi_ctx {
     std::vector<Iv> ivs;
     hipEvent_t t0 = nullptr, t1 = nullptr;
     std::map<std::pair<int, int>, std::vector<fwi_action>> plans;
-    // storage of freed tapes, newest last (at most TAPE_CACHE entries)
-    static constexpr size_t TAPE_CACHE = 4;
+    // storage of freed tapes, newest last (at most TAPE_CACHE entries, or
+    // TAPE_CACHE_GRAPHS while schedules are captured: a per-shot autograd
+    // loop keeps one tape per shot alive until its backward)
+    static constexpr size_t TAPE_CACHE = 4, TAPE_CACHE_GRAPHS = 64;
     std::vector<TapeStore> tape_cache;
     // a cached store whose buffer sizes equal sig (removed from the cache),
-    // or an empty store
-    TapeStore take_store(const std::vector<size_t> &sig)
+    // preferring the newest one last used for the same shots (so that a
+    // shot meets the buffers its captured schedule refers to), or an empty
+    // store
+    TapeStore take_store(const std::vector<size_t> &sig, const std::string &tag)
     {
-        for (size_t i = tape_cache.size(); i-- > 0;)
-            if (tape_cache[i].sig == sig) {
-                TapeStore s = std::move(tape_cache[i]);
-                tape_cache.erase(tape_cache.begin() + (long)i);
-                return s;
-            }
+        for (int pass = 0; pass < 2; ++pass)
+            for (size_t i = tape_cache.size(); i-- > 0;)
+                if (tape_cache[i].sig == sig && (pass == 1 || tape_cache[i].tag == tag)) {
+                    TapeStore s = std::move(tape_cache[i]);
+                    tape_cache.erase(tape_cache.begin() + (long)i);
+                    return s;
+                }
         return TapeStore{};
     }
     void keep_store(TapeStore &&s)
     {
         tape_cache.push_back(std::move(s));
-        while (tape_cache.size() > TAPE_CACHE) {
+        while (tape_cache.size() > (graphs ? TAPE_CACHE_GRAPHS : TAPE_CACHE)) {
             tape_cache.front().release();
             tape_cache.erase(tape_cache.begin());
         }
@@ -327,6 +334,7 @@ struct fwi_tape {
     std::vector<fwi_action> acts;
     std::vector<char> both, slot_both;
     size_t next = 0;
+    std::string tag;                 // grids and shots (no addresses); see take_store
     DevBuf<unsigned char> pool;
     DevBuf<StreamSlot> slots;
     DevBuf<float> xcur, xprev;
@@ -1647,7 +1655,7 @@ bool valid_shape(int ndim, const fwi_ctx::Shape &s)
 {
     if (s.xchunk < 1) return false;
     if (ndim == 2) return true;
-    return (s.rpl == 2 || s.rpl == 4) && s.remap >= 0 && s.remap <= 2 && (s.vz == 1 || s.vz == 2) &&
+    return (s.rpl == 2 || s.rpl == 4) && s.remap >= 0 && s.remap <= 4 && (s.vz == 1 || s.vz == 2) &&
            (s.deep == 0 || (s.deep == 1 && s.vz == 1));
 }
 
@@ -1755,7 +1763,7 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         }
         if (const char *e = std::getenv("FWI_XCHUNK")) c->xchunk3 = std::atoi(e);
         if (const char *e = std::getenv("FWI_RPL")) c->rpl3 = std::atoi(e) == 4 ? 4 : 2;
-        if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::max(0, std::min(std::atoi(e), 2));
+        if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::max(0, std::min(std::atoi(e), 4));
         if (const char *e = std::getenv("FWI_DEEP")) c->deep3 = std::atoi(e) != 0;
         if (const char *e = std::getenv("FWI_VZ")) c->vz3 = std::atoi(e) == 2 ? 2 : 1;
         *ctx = c;
@@ -2200,8 +2208,11 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
                 t->shots.push_back(std::move(sh));
             }
             {
+                KeyBuilder tag;
+                for (int i = 0; i < nshots; ++i) key_shot(tag, c, &grids[i], &shots[i], setups[i]);
+                t->tag = tag.s;
                 // the buffers of an earlier batched tape of the same sizes, if any
-                TapeStore rs = c->take_store(sig);
+                TapeStore rs = c->take_store(sig, t->tag);
                 for (int i = 0; i < nshots && !rs.bufs.empty(); ++i) {
                     fwi_tape::Shot &sh = *t->shots[i];
                     store_take(rs, 5 * i + 0, sh.pool);
@@ -2237,7 +2248,14 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
                     e.coff = c->chunk_off.p + co[i];
                 }
                 setup_ckpt(e, cfg, sh.pool.p, sh.cap, sh.slots.p, used);
-                e.dsim = d_sim[i];
+                // captured schedules record into the shot's trace buffer and
+                // copy out after the replay (the graph does not depend on d_sim)
+                const size_t nd = (size_t)shots[i].nrec * (size_t)setups[i].nt;
+                if (c->graphs && nd) {
+                    b->dsim.ensure(nd);
+                    b->res.ensure(nd);      // the backward's, so that it does not allocate
+                }
+                e.dsim = c->graphs && nd ? b->dsim.p : d_sim[i];
                 e.init_fields();
                 ex.push_back(std::move(e));
             }
@@ -2251,8 +2269,7 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
             for (int i = 0; i < nshots; ++i) {
                 const fwi_tape::Shot &sh = *t->shots[i];
                 key_shot(key, c, &grids[i], &shots[i], setups[i]);
-                key.add(models[i]).add(d_sim[i]).add(sh.pool.p).add(sh.slots.p).add(sh.misc.p).add(sh.xcur.p)
-                    .add(sh.xprev.p);
+                key.add(ex[i].dsim).add(sh.pool.p).add(sh.slots.p).add(sh.misc.p).add(sh.xcur.p).add(sh.xprev.p);
             }
             run_schedule(c, st, key.s, nbytes_tab, [&](char *gtab, hipStream_t rs) {
                 c->btab.used = 0;
@@ -2267,6 +2284,11 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
                 }
                 for (auto &e : ex) e.st = st;
             });
+            for (int i = 0; i < nshots; ++i)
+                if (ex[i].dsim != d_sim[i])
+                    HIPCHK(hipMemcpyAsync(d_sim[i], ex[i].dsim,
+                                          (size_t)shots[i].nrec * (size_t)setups[i].nt * sizeof(float),
+                                          hipMemcpyDeviceToDevice, st));
             HIPCHK(hipGetLastError());
             finish_status(c, st);
             end_call(c, st);
@@ -2313,7 +2335,14 @@ static int backward_batch_impl(fwi_ctx *c, fwi_tape *t, const float *const *dd, 
             }
             setup_ckpt(e, &t->cfg, sh.pool.p, sh.cap, sh.slots.p, used);
             e.grad = grads ? grads[i] : gstack;
-            e.adj_src = dd[i];
+            // captured schedules read the adjoint source from the shot's
+            // buffer, filled before the replay (the graph does not depend on dd)
+            const size_t nd = (size_t)sh.shot.nrec * (size_t)setups[i].nt;
+            if (c->graphs && nd) {
+                b->res.ensure(nd);
+                HIPCHK(hipMemcpyAsync(b->res.p, dd[i], nd * sizeof(float), hipMemcpyDeviceToDevice, st));
+            }
+            e.adj_src = c->graphs && nd ? b->res.p : dd[i];
             e.init_fields();
             e.init_adjoint();
             e.cur = sh.xcur.p;
@@ -2330,18 +2359,22 @@ static int backward_batch_impl(fwi_ctx *c, fwi_tape *t, const float *const *dd, 
         for (int i = 0; i < nshots; ++i) {
             const fwi_tape::Shot &sh = *t->shots[i];
             key_shot(key, c, &sh.grid, &sh.shot, setups[i]);
-            key.add(sh.m).add(dd[i]).add(grads ? grads[i] : nullptr).add(sh.pool.p).add(sh.slots.p).add(sh.misc.p)
-                .add(sh.xcur.p).add(sh.xprev.p).add(sh.cap);
+            key.add(ex[i].adj_src).add(sh.pool.p).add(sh.slots.p).add(sh.misc.p).add(sh.xcur.p).add(sh.xprev.p)
+                .add(sh.cap);
         }
-        key_stack(key, sk, nshots, gstack);
+        // the gradients leave the padded accumulators after the schedule;
+        // captured schedules stop at the accumulators, so the graph does not
+        // depend on where the caller wants the gradients
+        key.add(sk ? 'S' : '-');
         run_schedule(c, st, key.s, nbytes_tab, [&](char *gtab, hipStream_t rs) {
             c->btab.used = 0;
             for (auto &e : ex) e.st = rs;
             BatchExec bx{c, rs, ex, setups[0].ndim, setups[0].R, gtab ? gtab : c->btab.dev.p, gtab == nullptr, {}};
             bx.run(t->acts, t->both, t->next, false);
-            finish_gradients(c, ex, grads, smaps, sk, gstack, rs);
+            if (!c->graphs) finish_gradients(c, ex, grads, smaps, sk, gstack, rs);
             for (auto &e : ex) e.st = st;
         });
+        if (c->graphs) finish_gradients(c, ex, grads, smaps, sk, gstack, st);
         HIPCHK(hipGetLastError());
         finish_status(c, st);
         t->used = true;
@@ -2387,8 +2420,11 @@ int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_sh
             const size_t pe = c->sb.padded_elems;
             const size_t nsl = (size_t)std::max(2 * used, 1);
             {
+                KeyBuilder tag;
+                key_shot(tag, c, g, shot, ex.S);
+                t->tag = tag.s;
                 // the buffers of an earlier tape of the same sizes, if any
-                TapeStore rs = c->take_store({cap + 8, nsl * sizeof(StreamSlot), pe * 4, pe * 4});
+                TapeStore rs = c->take_store({cap + 8, nsl * sizeof(StreamSlot), pe * 4, pe * 4}, t->tag);
                 if (!rs.bufs.empty()) {
                     store_take(rs, 0, t->pool);
                     store_take(rs, 1, t->slots);
@@ -2402,14 +2438,21 @@ int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_sh
             t->xprev.ensure(pe);
             reset_status(c, st);
             setup_ckpt(ex, cfg, t->pool.p, cap, t->slots.p, used);
-            ex.dsim = d_sim;
+            // captured schedules record into the context's trace buffer and
+            // copy out after the replay, so they do not depend on d_sim
+            const size_t nd = (size_t)shot->nrec * (size_t)ex.S.nt;
+            if (c->graphs && nd) {
+                c->sb.dsim.ensure(nd);
+                c->sb.res.ensure(nd);       // the backward's, so that it does not allocate
+            }
+            ex.dsim = c->graphs && nd ? c->sb.dsim.p : d_sim;
             ex.init_fields();
             t->both = restart_flags(t->acts);
             t->next = first_sweep(t->acts, t->both, t->slot_both);
             KeyBuilder key;
             key.add('F');
             key_shot(key, c, g, shot, ex.S);
-            key.add(m).add(d_sim).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
+            key.add(ex.dsim).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
             key.add(t->pool.p).add(t->slots.p).add(t->xcur.p).add(t->xprev.p);
             run_schedule(c, st, key.s, 0, [&](char *, hipStream_t rs) {
                 ex.st = rs;
@@ -2418,6 +2461,8 @@ int fwi_forward_ckpt(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_sh
                 launch_copy(t->xprev.p, ex.prev, pe, rs);
                 ex.st = st;
             });
+            if (ex.dsim != d_sim)
+                HIPCHK(hipMemcpyAsync(d_sim, ex.dsim, nd * sizeof(float), hipMemcpyDeviceToDevice, st));
             HIPCHK(hipGetLastError());
             finish_status(c, st);
             end_call(c, st);
@@ -2446,7 +2491,16 @@ int fwi_backward(fwi_ctx *c, fwi_tape *t, const float *dd, float *grad, hipStrea
         reset_status(c, st);
         setup_ckpt(ex, &t->cfg, t->pool.p, cap, t->slots.p, used);
         ex.grad = grad;
-        ex.adj_src = dd;
+        // captured schedules read the adjoint source from the context's
+        // buffer (filled before the replay) and leave the gradient in the
+        // padded accumulator, unpadded after the replay: the graph does not
+        // depend on dd or grad
+        const size_t nd = (size_t)t->shot.nrec * (size_t)ex.S.nt;
+        if (c->graphs && nd) {
+            c->sb.res.ensure(nd);
+            HIPCHK(hipMemcpyAsync(c->sb.res.p, dd, nd * sizeof(float), hipMemcpyDeviceToDevice, st));
+        }
+        ex.adj_src = c->graphs && nd ? c->sb.res.p : dd;
         ex.init_fields();
         ex.init_adjoint();
         ex.cur = t->xcur.p;
@@ -2457,14 +2511,15 @@ int fwi_backward(fwi_ctx *c, fwi_tape *t, const float *dd, float *grad, hipStrea
         KeyBuilder key;
         key.add('U');
         key_shot(key, c, &t->grid, &t->shot, ex.S);
-        key.add(t->m).add(dd).add(grad).add(t->cfg.nslots).add(t->cfg.compress).add(t->cfg.atol).add(cap);
+        key.add(ex.adj_src).add(t->cfg.nslots).add(t->cfg.compress).add(t->cfg.atol).add(cap);
         key.add(t->pool.p).add(t->slots.p).add(t->xcur.p).add(t->xprev.p);
         run_schedule(c, st, key.s, 0, [&](char *, hipStream_t rs) {
             ex.st = rs;
             ex.run(t->acts, t->both, t->next, false);
-            launch_unpad(c->sb.gacc.p, grad, ex.padmap(), rs);
+            if (!c->graphs) launch_unpad(c->sb.gacc.p, grad, ex.padmap(), rs);
             ex.st = st;
         });
+        if (c->graphs) launch_unpad(c->sb.gacc.p, grad, ex.padmap(), st);
         HIPCHK(hipGetLastError());
         finish_status(c, st);
         t->used = true;
@@ -2479,6 +2534,7 @@ int fwi_tape_free(fwi_tape *t)
         // the buffers go back to the context (for the next tape of the same
         // sizes) while it lives, else to the device
         TapeStore rs;
+        rs.tag = t->tag;
         if (t->shots.empty()) {
             store_put(rs, t->pool);
             store_put(rs, t->slots);
@@ -2739,7 +2795,7 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
                     cands.push_back({xc, 4, remap, 0, 1});
                     cands.push_back({xc, 2, remap, 1, 1});
                 }
-                cands.push_back({xc, 2, 2, 0, 1});
+                for (int remap : {2, 3, 4}) cands.push_back({xc, 2, remap, 0, 1});
                 for (int remap : {0, 1, 2}) {
                     cands.push_back({xc, 2, remap, 0, 2});
                     cands.push_back({xc, 4, remap, 0, 2});
@@ -2774,15 +2830,16 @@ int fwi_autotune(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         std::sort(rf.begin(), rf.end());
         std::sort(ra.begin(), ra.end());
         // among shapes within 6 % of the fastest, prefer one plane of loads
-        // in flight, the z-column order (z halos from L2), then round robin
-        // over the XCDs, then the longest x chunk (fewest halo planes
-        // re-read):
+        // in flight, the column orders (z halos, and with groups of columns
+        // y halos, from L2), then round robin over the XCDs, then the
+        // longest x chunk (fewest halo planes re-read), then the larger
+        // column group:
         // that pays when the codec shares the memory system with the step
         // (the sweeps run it beside them)
         auto pick = [&](const std::vector<std::pair<double, size_t>> &r) {
             auto key = [&](size_t j) {
                 const fwi_ctx::Shape &h = cands[r[j].second];
-                return std::make_tuple(h.deep == 0, h.vz == 2, h.remap == 2, h.remap != 1, h.xchunk);
+                return std::make_tuple(h.deep == 0, h.vz == 2, h.remap >= 2, h.remap != 1, h.xchunk, h.remap);
             };
             size_t k = 0;
             for (size_t j = 1; j < r.size(); ++j)

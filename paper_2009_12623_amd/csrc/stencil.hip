@@ -98,7 +98,10 @@ __device__ __forceinline__ void gather_block(const StepParams &p, int blk)
 // out tiles so that each XCD works on one contiguous range, `remap` 2 so
 // that the z tiles of one (y, x chunk) column go to one XCD in a row (their
 // z halos are then read from that XCD's L2) while columns still go round
-// robin.  Read-once streams (u2, b, u^k, g) use non-temporal loads.
+// robin; `remap` 3 and 4 hand each XCD groups of G = 2 or 4 consecutive
+// columns (y neighbours of one x chunk) in a row, so that the y halos inside
+// a group are read from that XCD's L2 too.  Read-once streams (u2, b, u^k,
+// g) use non-temporal loads.
 __device__ __forceinline__ void tile_coords(int hw, int nwg, int ntz, int nty, int remap, int &tzi,
                                             int &tyi, int &txi, bool &valid)
 {
@@ -106,10 +109,14 @@ __device__ __forceinline__ void tile_coords(int hw, int nwg, int ntz, int nty, i
     if (remap == 1) {
         const int per = (nwg + 7) >> 3;
         logical = (hw & 7) * per + (hw >> 3);
-    } else if (remap == 2) {
-        // a bijection of [0, launched) when launched is a multiple of 8 ntz
-        const int k = hw >> 3;
-        logical = ((k / ntz) * 8 + (hw & 7)) * ntz + k % ntz;
+    } else if (remap >= 2) {
+        // a bijection of [0, launched) when launched is a multiple of
+        // 8 G ntz: the XCD's k-th workgroup takes z tile k % ntz of its
+        // (k / ntz)-th column, columns in groups of G per XCD
+        const int lg = remap - 2;
+        const int k = hw >> 3, cx = k / ntz;
+        const int col = ((((cx >> lg) << 3) + (hw & 7)) << lg) + (cx & ((1 << lg) - 1));
+        logical = col * ntz + k % ntz;
     }
     valid = logical < nwg;
     tzi = logical % ntz;
@@ -1025,7 +1032,7 @@ int step_geometry(BatchEntry &e, int ndim, bool adjoint)
         e.ntz = (p.nz + tzw - 1) / tzw;
         e.nty = (p.ny + rows - 1) / rows;
         e.nwg = e.ntz * e.nty * nchunk;
-        const int unit = p.remap == 2 ? 8 * e.ntz : 8;
+        const int unit = p.remap >= 2 ? (8 << (p.remap - 2)) * e.ntz : 8;
         e.launched = ((e.nwg + unit - 1) / unit) * unit;
         const int ng = gather ? (p.nrec + 511) / 512 : 0;
         return e.launched + ng;

@@ -133,7 +133,7 @@ def test_batch_pool_overflow_is_reported(ctx):
     assert all(np.isfinite(phis))
 
 
-@pytest.mark.parametrize("xchunk,remap", [(16, 2), (7, 2), (8, 1)])
+@pytest.mark.parametrize("xchunk,remap", [(16, 2), (7, 2), (8, 1), (16, 3), (5, 4)])
 def test_batch_tile_orders(xchunk, remap, monkeypatch):
     """the batched kernel in every tile order (the tuner may pick any per
     shot): each shot equals its single-shot gradient bit for bit and the
