@@ -980,7 +980,7 @@ def main():
                             tune["fwd_vz"]],
                 "adjoint": [tune["adj_xchunk"], tune["adj_rows_per_lane"], tune["adj_xcd_order"], tune["adj_deep"],
                             tune["adj_vz"]],
-                "fields": ["x_planes_per_workgroup", "rows_per_lane", "tile_order_0rr_1contig_2zcol", "planes_in_flight_2",
+                "fields": ["x_planes_per_workgroup", "rows_per_lane", "tile_order_0rr_1contig_2zcol_3col2_4col4", "planes_in_flight_2",
                            "z_points_per_lane"]},
         },
         "roofline": roof,
