@@ -143,15 +143,16 @@ int fwi_ctx_stats(const fwi_ctx *ctx, fwi_stats *out);
  * config, launch shapes; for tapes also the tape's buffers) is seen, and
  * replay it on later calls with the same signature; a graph is re-captured
  * after any of the library's buffers is reallocated.  A freed tape's buffers
- * are kept by its context (up to 64 tapes while graphs are on, 4 otherwise)
- * and reused by the next tape of the same sizes, preferring the buffers last
- * used for the same shots, so the tapes of an iterative loop replay.  The
- * tape calls' graphs do not depend on the caller's model, trace, adjoint
- * source or gradient buffers: the model is read before the replay, traces
- * are recorded into context buffers and copied to d_sim after it, adjoint
- * sources are copied in before it and gradients leave the context's
- * accumulators after it, so autograd loops that allocate new tensors every
- * iteration replay too.  Results are identical to direct launches.
+ * are kept by its context (up to 64 tapes while graphs are on, 4 otherwise,
+ * and beyond the newest one at most 16 GiB) and reused by the next tape of
+ * the same sizes, preferring the buffers last
+ * used for the same shots, so the tapes of an iterative loop replay.  No
+ * graph depends on the caller's model, observed data, trace, adjoint source
+ * or gradient buffers: the model is read before the replay, observed data
+ * and adjoint sources are copied into context buffers before it, traces are
+ * recorded into context buffers and copied to d_sim after it, and gradients
+ * leave the context's accumulators after it, so loops that allocate new
+ * tensors every iteration (autograd) replay too.  Results are identical to direct launches.
  * Per-kernel timings are not collected during replays; launch counts are.
  * Off by default; off drops every graph. */
 int fwi_ctx_set_graphs(fwi_ctx *ctx, int on);

@@ -108,7 +108,7 @@ struct ShotBufs {
     FieldPtr fa, fb, la, lb, coef, gacc;
     DevBuf<int> rec_off, node_pad;
     DevBuf<int> node_xyz, rec_ptr, rec_idx;
-    DevBuf<float> dsim, res;
+    DevBuf<float> dsim, res, obs;        // traces, residuals, observed data staged for graphs
     DevBuf<double> partials, phi;
     DevBuf<unsigned long long> misc;     // stream bytes, pool high-water, total bytes
     DevBuf<StreamSlot> slots;
@@ -119,7 +119,7 @@ struct ShotBufs {
         arena.release();
         padded_elems = 0;
         rec_off.release(); node_pad.release(); node_xyz.release(); rec_ptr.release();
-        rec_idx.release(); dsim.release(); res.release(); partials.release(); phi.release();
+        rec_idx.release(); dsim.release(); res.release(); obs.release(); partials.release(); phi.release();
         misc.release(); slots.release();
     }
 };
@@ -304,10 +304,20 @@ struct fwi_ctx {
                 }
         return TapeStore{};
     }
+    // the oldest stores go first once there are too many or they hold more
+    // than TAPE_CACHE_BYTES (the newest is always kept)
+    static constexpr size_t TAPE_CACHE_BYTES = size_t(16) << 30;
     void keep_store(TapeStore &&s)
     {
         tape_cache.push_back(std::move(s));
-        while (tape_cache.size() > (graphs ? TAPE_CACHE_GRAPHS : TAPE_CACHE)) {
+        auto held = [&] {
+            size_t b = 0;
+            for (const TapeStore &t : tape_cache)
+                for (size_t n : t.sig) b += n;
+            return b;
+        };
+        while (tape_cache.size() > (graphs ? TAPE_CACHE_GRAPHS : TAPE_CACHE) ||
+               (tape_cache.size() > 1 && held() > TAPE_CACHE_BYTES)) {
             tape_cache.front().release();
             tape_cache.erase(tape_cache.begin());
         }
@@ -1728,16 +1738,6 @@ void finish_gradients(fwi_ctx *c, std::vector<Exec> &ex, float *const *grads, co
     for (size_t i = 0; i < n; ++i) launch_stack_add(c->batch[i]->gacc.p, gstack, smaps[i], st);
 }
 
-void key_stack(KeyBuilder &k, const fwi_stack *sk, int nshots, const float *grad)
-{
-    if (!sk) {
-        k.add('-');
-        return;
-    }
-    k.add('S').add(sk->ndim).add(sk->n).add(sk->region).add(grad);
-    k.bytes(sk->origin, sizeof(int) * (size_t)nshots * (size_t)sk->ndim);
-}
-
 }  // namespace
 
 void fwi::set_last_error(const char *msg) { g_err = msg; }
@@ -1898,20 +1898,28 @@ int fwi_gradient(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot *
         c->sb.phi.ensure(1);
         HIPCHK(hipMemsetAsync(c->sb.phi.p, 0, sizeof(double), st));
         ex.dsim = c->sb.dsim.p;
-        ex.d_obs = d_obs;
+        // captured schedules read the observed data from the context's copy
+        // and leave the gradient in the padded accumulator (unpadded after the
+        // replay): the graph does not depend on the caller's buffers
+        if (c->graphs && nd) {
+            c->sb.obs.ensure(nd);
+            HIPCHK(hipMemcpyAsync(c->sb.obs.p, d_obs, nd * sizeof(float), hipMemcpyDeviceToDevice, st));
+        }
+        ex.d_obs = c->graphs && nd ? c->sb.obs.p : d_obs;
         ex.grad = grad;
         ex.init_fields();
         ex.init_adjoint();
         KeyBuilder key;
         key.add('G');
         key_shot(key, c, g, shot, ex.S);
-        key.add(m).add(d_obs).add(grad).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
+        key.add(ex.d_obs).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
         run_schedule(c, st, key.s, 0, [&](char *, hipStream_t rs) {
             ex.st = rs;
             ex.run(acts, restart_flags(acts), 0, false);
-            launch_unpad(c->sb.gacc.p, grad, ex.padmap(), rs);
+            if (!c->graphs) launch_unpad(c->sb.gacc.p, grad, ex.padmap(), rs);
             ex.st = st;
         });
+        if (c->graphs) launch_unpad(c->sb.gacc.p, grad, ex.padmap(), st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(phi, c->sb.phi.p, sizeof(double), hipMemcpyDeviceToHost, st));
         finish_status(c, st);
@@ -2067,7 +2075,13 @@ static int gradient_batch_impl(fwi_ctx *c, int nshots, const fwi_grid *grids, co
             b->phi.ensure(1);
             HIPCHK(hipMemsetAsync(b->phi.p, 0, sizeof(double), st));
             e.dsim = b->dsim.p;
-            e.d_obs = d_obs[i];
+            // captured schedules read the shot's copy of the observed data
+            // (the graph does not depend on the caller's buffers)
+            if (c->graphs && nd) {
+                b->obs.ensure(nd);
+                HIPCHK(hipMemcpyAsync(b->obs.p, d_obs[i], nd * sizeof(float), hipMemcpyDeviceToDevice, st));
+            }
+            e.d_obs = c->graphs && nd ? b->obs.p : d_obs[i];
             e.grad = grads ? grads[i] : gstack;
             e.init_fields();
             e.init_adjoint();
@@ -2078,18 +2092,20 @@ static int gradient_batch_impl(fwi_ctx *c, int nshots, const fwi_grid *grids, co
         key.add('B').add(nshots).add(cfg->nslots).add(cfg->compress).add(cfg->atol).add(cap);
         for (int i = 0; i < nshots; ++i) {
             key_shot(key, c, &grids[i], &shots[i], setups[i]);
-            key.add(models[i]).add(d_obs[i]).add(grads ? grads[i] : nullptr);
+            key.add(ex[i].d_obs);
         }
-        key_stack(key, sk, nshots, gstack);
         c->btab.ensure(nbytes_tab);     // before any capture: it may allocate
+        // the gradients leave the padded accumulators after the schedule
+        // (captured schedules stop at the accumulators)
         run_schedule(c, st, key.s, nbytes_tab, [&](char *gtab, hipStream_t rs) {
             c->btab.used = 0;
             for (auto &e : ex) e.st = rs;
             BatchExec bx{c, rs, ex, setups[0].ndim, setups[0].R, gtab ? gtab : c->btab.dev.p, gtab == nullptr, {}};
             bx.run(acts, both);
-            finish_gradients(c, ex, grads, smaps, sk, gstack, rs);
+            if (!c->graphs) finish_gradients(c, ex, grads, smaps, sk, gstack, rs);
             for (auto &e : ex) e.st = st;
         });
+        if (c->graphs) finish_gradients(c, ex, grads, smaps, sk, gstack, st);
         std::vector<double> ph(nshots, 0.0);
         std::vector<unsigned long long> mc(4 * (size_t)nshots, 0);
         for (int i = 0; i < nshots; ++i) {

@@ -94,3 +94,13 @@ def test_ckpt_pool_bytes():
     bad = synth.Shot(2, (0, 10), 10.0, 8, 6, 40, 1e-3, 2500.0, 10.0, (0, 0), shot.rec)
     with pytest.raises(F.FwiError):
         F.ckpt_pool_bytes(bad, 3, False)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """no CPU fallback: without the built library every call path raises"""
+    monkeypatch.setattr(F, "_lib", None)
+    monkeypatch.setattr(F, "LIB_PATH", str(tmp_path / "libfwigrad.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        F.lib()
+    with pytest.raises(RuntimeError, match="not built"):
+        F.fwi_revolve_plan(10, 2)
