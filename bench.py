@@ -173,6 +173,16 @@ def stencil_source_hash():
                     for f in ("stencil.hip", "internal.hpp"))
 
 
+def timed_region_hbm(st, npts, cf, seconds):
+    """algorithmic HBM bytes of all launches of one gradient (counts from
+    fwi_stats) and the rate they imply over its wall time"""
+    field = 4.0 * npts
+    total = (st["n_forward"] * 16.0 * npts + st["n_adjoint"] * 28.0 * npts
+             + (st["n_encode"] + st["n_decode"]) * field * (1.0 + 1.0 / cf))
+    rate = total / seconds / 1e9
+    return {"bytes": total, "GBs": round(rate, 1), "frac_of_peak": round(rate / HBM_PEAK_GBS, 4)}
+
+
 def counted_traffic(kernel, shape):
     """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE summary,
     scaled by the copy-kernel calibration; None unless the kernel, its launch
@@ -1020,6 +1030,10 @@ def main():
             "decode": round(st["n_decode"] * 4.0 * npts / (st["ms_decode"] * 1e-3) / 1e9, 1) if st["n_decode"] else None,
             "compression_factor": round(cf, 2),
         },
+        # every launch of one timed gradient together: algorithmic bytes of
+        # the stencil steps (16 / 28 B per point) and of the codec (4 B per
+        # value plus the stream) over the wall time of the gradient
+        "timed_region_hbm": timed_region_hbm(st, npts, cf, s_per_shot),
         "uncompressed_revolve": {"s_per_shot": round(t_unc, 3), "nslots": s_unc},
         "speedup_vs_uncompressed": round(t_unc / s_per_shot, 3),
         "grad_rel_l2_vs_uncompressed": float("%.3e" % err),
