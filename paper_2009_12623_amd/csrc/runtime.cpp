@@ -1338,7 +1338,12 @@ struct BatchExec {
             h[i].p.rpl = 2;             // the batched 3D kernel uses 2 rows per lane, one z point each
             h[i].p.vz = 1;
             h[i].first = first;
-            first += step_geometry(h[i], ndim, adj);
+            // every shot starts on a multiple of 8 workgroups, so that its
+            // tile order sees the XCD a workgroup runs on (hardware deals
+            // workgroups to the 8 XCDs round robin); the padding is receiver
+            // sampling blocks past the last receiver, which do nothing
+            const int g = step_geometry(h[i], ndim, adj);
+            first += ndim == 3 ? (g + 7) & ~7 : g;
         }
         BatchEntry *d = (BatchEntry *)(dev_base + off);
         if (upload) HIPCHK(hipMemcpyAsync(d, h, (size_t)n * sizeof(BatchEntry), hipMemcpyHostToDevice, st));

@@ -36,27 +36,33 @@ __device__ __forceinline__ int layer_depth(int i, int n, int nbl)
     return d > 0 ? d : 0;
 }
 
-// load/store through a base pointer and an unsigned byte offset
+// load/store through a base pointer and an unsigned byte offset.  Every
+// base is a device (global) array; the accesses say so, so that kernels
+// whose pointers come from a table in memory (the batched ones) get global
+// rather than flat instructions: a flat access also counts against the LDS
+// wait counter, so every wait for an LDS read would wait for it as well.
+typedef __attribute__((address_space(1))) float gfloat;
+
 __device__ __forceinline__ float ld(const float *base, unsigned off)
 {
-    return *(const float *)((const char *)base + off);
+    return *(const gfloat *)((const char *)base + off);
 }
 
 __device__ __forceinline__ float ldnt(const float *base, unsigned off)
 {
-    return __builtin_nontemporal_load((const float *)((const char *)base + off));
+    return __builtin_nontemporal_load((const gfloat *)((const char *)base + off));
 }
 
 __device__ __forceinline__ void st(float *base, unsigned off, float v)
 {
-    *(float *)((char *)base + off) = v;
+    *(gfloat *)((char *)base + off) = v;
 }
 
 // streaming store: the 3D levels and gradient are far larger than the
 // caches and are next read a whole step later
 __device__ __forceinline__ void stnt(float *base, unsigned off, float v)
 {
-    __builtin_nontemporal_store(v, (float *)((char *)base + off));
+    __builtin_nontemporal_store(v, (gfloat *)((char *)base + off));
 }
 
 // Increment out - c of the new level.  The recurrence row is written around
