@@ -135,9 +135,10 @@ def test_batch_pool_overflow_is_reported(ctx):
 
 @pytest.mark.parametrize("xchunk,remap", [(16, 2), (7, 2), (8, 1), (16, 3), (5, 4)])
 def test_batch_tile_orders(xchunk, remap, monkeypatch):
-    """the batched kernel in every tile order (the tuner may pick any per
-    shot): each shot equals its single-shot gradient bit for bit and the
-    oracle's to 1e-4"""
+    """single-shot calls in every tile order (the batched kernel deals its
+    tiles round robin whatever the shot's tuned order): each shot of the
+    batch equals its single-shot gradient bit for bit and the oracle's to
+    1e-4"""
     monkeypatch.setenv("FWI_XCHUNK", str(xchunk))
     monkeypatch.setenv("FWI_REMAP", str(remap))
     c = F.Context(0, pool_bytes=1 << 28)
