@@ -37,6 +37,19 @@ namespace {
 constexpr int QB = 24;
 typedef float f4v __attribute__((ext_vector_type(4)));
 
+// Every array the codec touches is device (global) memory.  The batched
+// kernels take their arguments from job tables in memory, whose pointers the
+// compiler cannot tell apart from LDS ones, so it would emit flat accesses;
+// on gfx950 those count against the LDS wait counter too, and every wait for
+// an LDS read (the scan and pack kernels) would wait for the global loads in
+// flight as well.  Accesses made through gp() are global ones.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL_AS T *gp(T *p)
+{
+    return (GLOBAL_AS T *)p;
+}
+
 // ------------------------------------------------------- sequency tables
 template <int D>
 struct Seq {
@@ -176,7 +189,7 @@ __host__ __device__ __forceinline__ long scratch_word(long c, long w, long chunk
 struct BitWriter {
     unsigned long long acc;
     int fill;
-    unsigned long long *out;        // word 0 of this lane; word w at out[64 w]
+    GLOBAL_AS unsigned long long *out;   // word 0 of this lane; word w at out[64 w]
     long w;
     __device__ __forceinline__ void put(uint32_t v, int n)    // v < 2^n, n <= 32
     {
@@ -201,7 +214,7 @@ struct BitWriter {
 };
 
 struct BitReader {
-    const unsigned long long *w;
+    const GLOBAL_AS unsigned long long *w;
     long nw;
     long idx;                       // word index of lo
     unsigned long long lo, hi;
@@ -302,7 +315,7 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
     constexpr int SZ = GC::SZ;
     constexpr Seq<D> seq{};
     const FieldView &f = k.f;
-    const float *src = k.src;
+    const GLOBAL_AS float *src = gp(k.src);
     const long nb0 = k.nb0, nb1 = k.nb1, nb2 = k.nb2, nblocks = k.nblocks, nchunks = k.nchunks;
     const int kblk = k.kblk, minexp = k.minexp, vec = k.vec;
     unsigned long long *scratch = k.scratch;
@@ -312,7 +325,7 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
     const long c = blk * 64 + threadIdx.x;
     if (c >= nchunks) return;
     const long nb[3] = {nb0, nb1, nb2};
-    BitWriter bw{0ull, 0, scratch + scratch_word(c, 0, chunk_words), 0};
+    BitWriter bw{0ull, 0, gp(scratch) + scratch_word(c, 0, chunk_words), 0};
     bool nonfinite = false, outrange = false;
     // padded fields: the rows of the next block are loaded while the current
     // one is coded
@@ -327,7 +340,7 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
             long x = 4 * qx + ix, y = 4 * qy + iy;
             x = x < f.n[0] ? x : f.n[0] - 1;
             y = y < f.n[1] ? y : f.n[1] - 1;
-            pf[r] = __builtin_nontemporal_load((const f4v *)(src + x * f.sx + y * f.sy + 4 * qz));
+            pf[r] = __builtin_nontemporal_load((const GLOBAL_AS f4v *)(src + x * f.sx + y * f.sy + 4 * qz));
         }
     };
     if (vec == 2) {
@@ -368,8 +381,8 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
             for (int r = 0; r < SZ / 4; ++r) {
                 const int ix = D == 3 ? (r >> 2) : r;
                 const int iy = D == 3 ? (r & 3) : 0;
-                            const f4v v = __builtin_nontemporal_load(
-                    (const f4v *)(src + (4 * bx + ix) * f.sx + (4 * by + iy) * f.sy + 4 * bz));
+                const f4v v = __builtin_nontemporal_load(
+                    (const GLOBAL_AS f4v *)(src + (4 * bx + ix) * f.sx + (4 * by + iy) * f.sy + 4 * bz));
                 w[4 * r + 0] = __float_as_uint(v.x);
                 w[4 * r + 1] = __float_as_uint(v.y);
                 w[4 * r + 2] = __float_as_uint(v.z);
@@ -457,7 +470,7 @@ __device__ __forceinline__ void encode_body(const EncodeK &k, long blk)
         }
     }
     if (bw.fill) bw.out[64 * bw.w] = bw.acc;
-    chunk_bits[c] = (unsigned long long)bw.w * 64ull + (unsigned long long)bw.fill;
+    gp(chunk_bits)[c] = (unsigned long long)bw.w * 64ull + (unsigned long long)bw.fill;
     if (nonfinite) atomicOr(flags, 1u);
     if (outrange) atomicOr(flags, 8u);
 }
@@ -470,13 +483,13 @@ __device__ __forceinline__ void tile_sum_body(const unsigned long long *chunk_bi
 {
     __shared__ unsigned long long red[TILE];
     const long c = blk * TILE + threadIdx.x;
-    red[threadIdx.x] = c < nchunks ? chunk_bits[c] : 0ull;
+    red[threadIdx.x] = c < nchunks ? gp(chunk_bits)[c] : 0ull;
     __syncthreads();
     for (int s = TILE / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) tile_sum[blk] = red[0];
+    if (threadIdx.x == 0) gp(tile_sum)[blk] = red[0];
 }
 
 struct PlanArgs {
@@ -503,12 +516,12 @@ struct PlanArgs {
 
 __device__ __forceinline__ void st64(unsigned char *p, unsigned long long v)
 {
-    for (int i = 0; i < 8; ++i) p[i] = (unsigned char)(v >> (8 * i));
+    for (int i = 0; i < 8; ++i) gp(p)[i] = (unsigned char)(v >> (8 * i));
 }
 
 __device__ __forceinline__ void st32(unsigned char *p, unsigned int v)
 {
-    for (int i = 0; i < 4; ++i) p[i] = (unsigned char)(v >> (8 * i));
+    for (int i = 0; i < 4; ++i) gp(p)[i] = (unsigned char)(v >> (8 * i));
 }
 
 __device__ __forceinline__ void plan_body(const PlanArgs &a)
@@ -600,10 +613,13 @@ struct PackArgs {
 __device__ __forceinline__ void pack_body(const PackArgs &a, long blk)
 {
     __shared__ unsigned long long sc[TILE];
-    if (*a.flags & 2u) return;
-    unsigned char *dst = a.dst ? a.dst : a.pool + *a.dst_offset;
+    if (*gp(a.flags) & 2u) return;
+    unsigned char *dst = a.dst ? a.dst : a.pool + *gp(a.dst_offset);
+    const GLOBAL_AS unsigned long long *chunk_bits = gp(a.chunk_bits);
+    const GLOBAL_AS unsigned long long *scratch = gp(a.scratch);
+    const GLOBAL_AS unsigned long long *tile_prefix = gp(a.tile_prefix);
     const long c = blk * TILE + threadIdx.x;
-    const unsigned long long len = c < a.nchunks ? a.chunk_bits[c] : 0ull;
+    const unsigned long long len = c < a.nchunks ? chunk_bits[c] : 0ull;
     sc[threadIdx.x] = len;
     __syncthreads();
     for (int s = 1; s < TILE; s <<= 1) {
@@ -613,12 +629,12 @@ __device__ __forceinline__ void pack_body(const PackArgs &a, long blk)
         __syncthreads();
     }
     if (c < a.nchunks) {
-        const unsigned long long off = a.tile_prefix[blk] + sc[threadIdx.x] - len;
+        const unsigned long long off = tile_prefix[blk] + sc[threadIdx.x] - len;
         // tables: super-chunk base (the first chunk of each super-chunk) and
         // relative chunk offsets (a super-chunk of 256 lies inside one tile)
         unsigned char *tab = dst + 64;
         const long sup0 = (c / 256) * 256 - blk * TILE;   // in-tile index of the super-chunk head
-        const unsigned long long head = a.tile_prefix[blk] + (sup0 > 0 ? sc[sup0 - 1] : 0ull);
+        const unsigned long long head = tile_prefix[blk] + (sup0 > 0 ? sc[sup0 - 1] : 0ull);
         if ((c & 255) == 0) st64(tab + 8 * (c / 256), off);
         st32(tab + 8 * a.nsuper + 4 * c, (unsigned int)(off - head));
     }
@@ -627,8 +643,8 @@ __device__ __forceinline__ void pack_body(const PackArgs &a, long blk)
     // the chunk scratch and coalesced writes), finding the chunk that holds
     // the word's first bit by binary search over the tile's prefix sums
     __syncthreads();
-    unsigned long long *out = (unsigned long long *)(dst + 64 + a.table_bytes);
-    const unsigned long long base = a.tile_prefix[blk];
+    GLOBAL_AS unsigned long long *out = gp((unsigned long long *)(dst + 64 + a.table_bytes));
+    const unsigned long long base = tile_prefix[blk];
     const unsigned long long tile_end = base + sc[TILE - 1];
     const long c0 = blk * TILE;
     for (unsigned long long w = ((base + 63ull) >> 6) + threadIdx.x; (w << 6) < tile_end; w += TILE) {
@@ -650,12 +666,12 @@ __device__ __forceinline__ void pack_body(const PackArgs &a, long blk)
                 ++cc;
                 if (cc >= a.nchunks) break;
                 cstart += clen;
-                clen = a.chunk_bits[cc];
+                clen = chunk_bits[cc];
                 continue;
             }
             const unsigned long long lb = pos - cstart;       // local bit in chunk cc
             const int sh = (int)(lb & 63);
-            unsigned long long v = a.scratch[scratch_word(cc, (long)(lb >> 6), a.chunk_words)] >> sh;
+            unsigned long long v = scratch[scratch_word(cc, (long)(lb >> 6), a.chunk_words)] >> sh;
             int avail = 64 - sh;
             if ((unsigned long long)avail > clen - lb) avail = (int)(clen - lb);
             const int take = avail < 64 - got ? avail : 64 - got;
@@ -670,7 +686,7 @@ __device__ __forceinline__ void pack_body(const PackArgs &a, long blk)
 
 // ------------------------------------------------------------------ decode
 // absolute payload bit where chunk c starts (super-chunk base + relative offset)
-__device__ __forceinline__ unsigned long long chunk_start(const unsigned char *s, long nsuper, long c)
+__device__ __forceinline__ unsigned long long chunk_start(const GLOBAL_AS unsigned char *s, long nsuper, long c)
 {
     unsigned long long sup = 0;
     unsigned int rel = 0;
@@ -697,11 +713,11 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
     const int vec = k.vec;
     const long c = blk * 64 + threadIdx.x;
     if (c >= nchunks) return;
-    const unsigned char *s = stream;
-    if (!s) {
-        const StreamSlot sl = slots[slot_index];
-        if (!sl.valid) return;
-        s = pool + sl.offset;
+    const GLOBAL_AS unsigned char *s = gp(stream);
+    if (!stream) {
+        const GLOBAL_AS StreamSlot *sl = gp(slots) + slot_index;
+        if (!sl->valid) return;
+        s = gp(pool) + sl->offset;
     }
     const long nb[3] = {nb0, nb1, nb2};
     unsigned long long pbits = 0;
@@ -710,7 +726,7 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
     const int minexp = (int)((unsigned int)s[32] | ((unsigned int)s[33] << 8) |
                              ((unsigned int)s[34] << 16) | ((unsigned int)s[35] << 24));
     BitReader br;
-    br.w = (const unsigned long long *)(s + 64 + table_bytes);
+    br.w = (const GLOBAL_AS unsigned long long *)(s + 64 + table_bytes);
     br.nw = (long)((pbits + 63) / 64);
     br.seek(start);
     for (int j = 0; j < kblk; ++j) {
@@ -790,8 +806,8 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
                 v.w = row && zl >= 3 ? val(4 * r + 3) : 0.0f;
                 // 3D working fields are far larger than the caches and are
                 // read by the next stencil step: stream them out
-                if (D == 3) __builtin_nontemporal_store(v, (f4v *)(dst + x * f.sx + y * f.sy + 4 * bz));
-                else *(f4v *)(dst + x * f.sx + y * f.sy + 4 * bz) = v;
+                if (D == 3) __builtin_nontemporal_store(v, (GLOBAL_AS f4v *)(gp(dst) + x * f.sx + y * f.sy + 4 * bz));
+                else *(GLOBAL_AS f4v *)(gp(dst) + x * f.sx + y * f.sy + 4 * bz) = v;
             }
         } else if (vec && 4 * bx + 3 < f.n[0] && (D == 2 || 4 * by + 3 < f.n[1]) && 4 * bz + 3 < f.n[2]) {
             // whole block inside: one 16-byte store per (x, y) row
@@ -799,8 +815,12 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
             for (int r = 0; r < SZ / 4; ++r) {
                 const int ix = D == 3 ? (r >> 2) : r;
                 const int iy = D == 3 ? (r & 3) : 0;
-                *(float4 *)(dst + (4 * bx + ix) * f.sx + (4 * by + iy) * f.sy + 4 * bz) =
-                    make_float4(val(4 * r), val(4 * r + 1), val(4 * r + 2), val(4 * r + 3));
+                f4v v;
+                v.x = val(4 * r);
+                v.y = val(4 * r + 1);
+                v.z = val(4 * r + 2);
+                v.w = val(4 * r + 3);
+                *(GLOBAL_AS f4v *)(gp(dst) + (4 * bx + ix) * f.sx + (4 * by + iy) * f.sy + 4 * bz) = v;
             }
         } else {
 #pragma unroll
@@ -809,7 +829,7 @@ __device__ __forceinline__ void decode_body(const DecodeK &k, long blk)
                 const int iy = D == 3 ? ((li >> 2) & 3) : 0;
                 const int iz = li & 3;
                 const long x = 4 * bx + ix, y = 4 * by + iy, z = 4 * bz + iz;
-                if (x < f.n[0] && y < f.n[1] && z < f.n[2]) dst[x * f.sx + y * f.sy + z] = val(li);
+                if (x < f.n[0] && y < f.n[1] && z < f.n[2]) gp(dst)[x * f.sx + y * f.sy + z] = val(li);
             }
         }
     }
