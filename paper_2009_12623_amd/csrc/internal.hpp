@@ -173,6 +173,7 @@ struct StreamSlot {
 struct EncodeArgs {
     FieldView f;
     const float *src;            // field origin
+    int max_waves = 0;           // > 0: at most this many waves, looping over the chunk groups
     double atol;
     unsigned long long *scratch;
     unsigned long long *chunk_bits;
@@ -197,6 +198,7 @@ void set_last_error(const char *msg);
 struct DecodeArgs {
     FieldView f;
     float *dst;                  // field origin
+    int max_waves = 0;           // > 0: at most this many waves, looping over the chunk groups
     const unsigned char *stream; // fixed stream, or nullptr: pool slot
     const unsigned char *pool;
     const StreamSlot *slots;
@@ -205,6 +207,9 @@ struct DecodeArgs {
     unsigned int *flags;         // bit2: corrupt
 };
 void codec_decode(const DecodeArgs &a, hipStream_t st);
+// waves of the single-field encode or decode kernel the device holds at
+// once (its occupancy x the compute units); 0 if it cannot be queried
+int codec_resident_waves(int ndim, bool encode);
 
 // Several fields in one launch per pipeline stage (fields of one ndim; each
 // with its own scratch, tables and destination).  host_jobs / dev_jobs:

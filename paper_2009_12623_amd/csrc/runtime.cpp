@@ -250,6 +250,14 @@ struct fwi_ctx {
                                // 3 and 4 groups of 2 and 4 columns per XCD
     int deep3 = 0;             // 3D two planes of loads in flight
     int vz3 = 1;               // 3D z points per lane (1: 64-point z tiles, 2: 128-point)
+    // wave caps of the sweeps' single-field codec launches: one resident
+    // round of the kernel (queried at creation), or FWI_CODEC_WAVES; 0 = none
+    int codec_waves = -1;      // from the environment; -1: resident round
+    int resident[2][2] = {{0, 0}, {0, 0}};   // [ndim == 3][encode]
+    int codec_cap(int ndim, bool encode) const
+    {
+        return codec_waves >= 0 ? codec_waves : resident[ndim == 3][encode];
+    }
     struct Shape {
         int xchunk, rpl, remap, deep, vz;
     };
@@ -884,6 +892,7 @@ struct Exec {
         EncodeArgs e{};
         e.f = padded_view(S);
         e.src = at_origin(lev == 0 ? cur : prev);
+        e.max_waves = c->codec_cap(S.ndim, true);
         e.atol = atol;
         e.scratch = scr ? scr : c->scratch.p;
         e.chunk_bits = cbits ? cbits : c->chunk_bits.p;
@@ -933,6 +942,7 @@ struct Exec {
         DecodeArgs d{};
         d.f = padded_view(S);
         d.dst = at_origin(target ? target : (lev == 0 ? W0() : W1()));
+        d.max_waves = c->codec_cap(S.ndim, false);
         d.stream = nullptr;
         d.pool = pool;
         d.slots = slots;
@@ -1765,7 +1775,12 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         int n = 0;
         HIPCHK(hipGetDeviceCount(&n));
         if (device < 0 || device >= n) throw Error{FWI_EINVAL, "no such device"};
+        HIPCHK(hipSetDevice(device));
+        int resident[2][2];
+        for (int d3 = 0; d3 < 2; ++d3)
+            for (int enc = 0; enc < 2; ++enc) resident[d3][enc] = codec_resident_waves(d3 ? 3 : 2, enc != 0);
         fwi_ctx *c = new fwi_ctx();
+        std::memcpy(c->resident, resident, sizeof resident);
         c->device = device;
         c->pool_default = pool_bytes;
         {
@@ -1777,6 +1792,7 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::max(0, std::min(std::atoi(e), 4));
         if (const char *e = std::getenv("FWI_DEEP")) c->deep3 = std::atoi(e) != 0;
         if (const char *e = std::getenv("FWI_VZ")) c->vz3 = std::atoi(e) == 2 ? 2 : 1;
+        if (const char *e = std::getenv("FWI_CODEC_WAVES")) c->codec_waves = std::max(0, std::atoi(e));
         *ctx = c;
     });
 }

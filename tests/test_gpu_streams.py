@@ -62,13 +62,17 @@ def gpu_states(ctx, shot, m, q, k):
     return u.cpu().numpy(), v.cpu().numpy()
 
 
-@pytest.mark.parametrize("ndim,n,so,nt,nslots,atol", [
-    (2, 60, 8, 40, 40, 1e-4),       # store-all: every step a checkpoint
-    (2, 60, 16, 50, 4, 1e-3),       # recomputing: some checkpoints hold both levels
-    (3, 22, 8, 24, 24, 1e-4),
-    (3, 22, 4, 30, 3, 1e-2),
+@pytest.mark.parametrize("ndim,n,so,nt,nslots,atol,waves", [
+    (2, 60, 8, 40, 40, 1e-4, 0),       # store-all: every step a checkpoint
+    (2, 60, 16, 50, 4, 1e-3, 0),       # recomputing: some checkpoints hold both levels
+    (3, 22, 8, 24, 24, 1e-4, 0),
+    (3, 22, 4, 30, 3, 1e-2, 0),
+    (3, 22, 8, 24, 24, 1e-4, 1),       # codec launches capped at 1 or 3 waves, each looping
+    (3, 22, 4, 30, 3, 1e-2, 3),        # over the chunk groups: same streams
 ])
-def test_tape_streams_equal_oracle_compression(ndim, n, so, nt, nslots, atol):
+def test_tape_streams_equal_oracle_compression(ndim, n, so, nt, nslots, atol, waves, monkeypatch):
+    if waves:
+        monkeypatch.setenv("FWI_CODEC_WAVES", str(waves))
     ctx = F.Context(0, pool_bytes=1 << 27)
     shot = synth.tiny_shot(ndim, n=n, so=so, nbl=5, nt=nt)
     m0, q = inputs(shot)
