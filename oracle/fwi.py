@@ -3,8 +3,8 @@
 The paper's inversion experiment (Sec. 4 "Convergence"; gradients scaled as
 in Sec. 3's setup) runs gradient descent on the squared slowness with the
 objective of Eq. (3) summed over shots and the gradient of Eq. (4).  Its step
-rule is not stated; this build's reading, written out here independently of
-the GPU loop:
+rule is not stated; the reading followed here (written independently of the
+GPU loop):
 
 1. the gradient is multiplied by a mask (zero in the absorbing layer and
    the rows next to the acquisition) and divided by the norm of the first

@@ -1,6 +1,6 @@
 """Pin of the oracle's absorbing layer (paper Sec. 3 "Reference Problem":
-a 40-point absorbing boundary layer on every side; its form is this build's
-reading: a damping term eta u_t with eta = sigma / vmax^2,
+a 40-point absorbing boundary layer on every side; its form is the reading
+taken here: a damping term eta u_t with eta = sigma / vmax^2,
 sigma = sigma_max (d / nbl)^2 per axis, sigma_max = 3 vmax ln(1000)/(2 nbl h)).
 
 The layer is pinned by what wave physics fixes for it, not by its formula:

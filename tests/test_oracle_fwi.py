@@ -1,5 +1,5 @@
 """Pins of the oracle's FWI loop (paper Sec. 4 "Convergence"; the step rule
-is this build's reading, see oracle/fwi.py).  The descent is driven by an
+is the reading taken in oracle/fwi.py).  The descent is driven by an
 analytic quadratic objective whose iterates follow in closed form, then run
 on a tiny 2D survey with the FP64 wave solver for the properties the rule
 guarantees (decrease, mask, bounds, size of the first update)."""
