@@ -130,10 +130,11 @@ typedef struct { int op; int a; int b; } fwi_action;
  * FWI_XCHUNK (x planes per workgroup, default 16), FWI_RPL (rows per lane,
  * 2 or 4), FWI_REMAP (tile order 0-4), FWI_DEEP (two planes of loads in
  * flight, 0/1), FWI_VZ (z points per lane, 1 or 2; 2 ignores FWI_DEEP);
- * FWI_CODEC_WAVES sets the wave cap of the sweeps' checkpoint codec
- * launches (each wave loops over several 64-chunk groups; the streams are
- * the same): unset, one resident round of the codec kernel (its occupancy
- * x the compute units); 0, one wave per group. */
+ * FWI_CODEC_WAVES caps the waves of the sweeps' checkpoint codec launches
+ * (each wave then loops over several 64-chunk groups; the streams are the
+ * same): a positive count, or a negative value for one resident round of
+ * the codec kernel (its occupancy x the compute units); 0 or unset: one
+ * wave per group. */
 int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes);
 int fwi_ctx_destroy(fwi_ctx *ctx);
 /* Collect per-kernel HIP-event timings in later calls (small overhead). */

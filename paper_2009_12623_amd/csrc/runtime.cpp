@@ -250,9 +250,10 @@ struct fwi_ctx {
                                // 3 and 4 groups of 2 and 4 columns per XCD
     int deep3 = 0;             // 3D two planes of loads in flight
     int vz3 = 1;               // 3D z points per lane (1: 64-point z tiles, 2: 128-point)
-    // wave caps of the sweeps' single-field codec launches: one resident
-    // round of the kernel (queried at creation), or FWI_CODEC_WAVES; 0 = none
-    int codec_waves = -1;      // from the environment; -1: resident round
+    // wave caps of the sweeps' single-field codec launches: FWI_CODEC_WAVES
+    // (0 or unset: a wave per chunk group; a negative value: one resident
+    // round of the kernel, queried at creation)
+    int codec_waves = 0;
     int resident[2][2] = {{0, 0}, {0, 0}};   // [ndim == 3][encode]
     int codec_cap(int ndim, bool encode) const
     {
@@ -1792,7 +1793,7 @@ int fwi_ctx_create(fwi_ctx **ctx, int device, size_t pool_bytes)
         if (const char *e = std::getenv("FWI_REMAP")) c->remap3 = std::max(0, std::min(std::atoi(e), 4));
         if (const char *e = std::getenv("FWI_DEEP")) c->deep3 = std::atoi(e) != 0;
         if (const char *e = std::getenv("FWI_VZ")) c->vz3 = std::atoi(e) == 2 ? 2 : 1;
-        if (const char *e = std::getenv("FWI_CODEC_WAVES")) c->codec_waves = std::max(0, std::atoi(e));
+        if (const char *e = std::getenv("FWI_CODEC_WAVES")) c->codec_waves = std::atoi(e);
         *ctx = c;
     });
 }
