@@ -993,12 +993,15 @@ static DecJob make_dec_job(const DecodeArgs &d)
 }
 
 // ---- single-field kernels
-// Single-field kernels loop over the field's 64-chunk groups, so a launch
-// may use fewer waves than groups (beside the stencil, a codec launch that
-// leaves CU slots free slows the step it overlaps less); the streams do
-// not depend on the grid.
+// One wave per 64-chunk group; the _loop variants let a capped number of
+// waves loop over the groups instead (same streams; a separate kernel,
+// because the loop around the inlined body costs the one-pass kernel
+// registers and speed).
 template <int D>
-__global__ __launch_bounds__(64) void encode_kernel(EncodeK k, long ngroups)
+__global__ __launch_bounds__(64) void encode_kernel(EncodeK k) { encode_body<D>(k, blockIdx.x); }
+
+template <int D>
+__global__ __launch_bounds__(64) void encode_loop_kernel(EncodeK k, long ngroups)
 {
     for (long b = blockIdx.x; b < ngroups; b += gridDim.x) encode_body<D>(k, b);
 }
@@ -1014,7 +1017,10 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanArgs a) { plan_body(a); }
 __global__ __launch_bounds__(TILE) void pack_kernel(PackArgs a) { pack_body(a, blockIdx.x); }
 
 template <int D>
-__global__ __launch_bounds__(64) void decode_kernel(DecodeK k, long ngroups)
+__global__ __launch_bounds__(64) void decode_kernel(DecodeK k) { decode_body<D>(k, blockIdx.x); }
+
+template <int D>
+__global__ __launch_bounds__(64) void decode_loop_kernel(DecodeK k, long ngroups)
 {
     for (long b = blockIdx.x; b < ngroups; b += gridDim.x) decode_body<D>(k, b);
 }
@@ -1069,9 +1075,14 @@ void codec_encode(const EncodeArgs &e, hipStream_t st)
 {
     const EncJob j = make_enc_job(e);
     const long ngroups = j.enc.nchunks / 64;
-    const int nwaves = (int)(e.max_waves > 0 && e.max_waves < ngroups ? e.max_waves : ngroups);
-    if (e.f.ndim == 3) hipLaunchKernelGGL(encode_kernel<3>, dim3(nwaves), dim3(64), 0, st, j.enc, ngroups);
-    else hipLaunchKernelGGL(encode_kernel<2>, dim3(nwaves), dim3(64), 0, st, j.enc, ngroups);
+    if (e.max_waves > 0 && e.max_waves < ngroups) {
+        if (e.f.ndim == 3) hipLaunchKernelGGL(encode_loop_kernel<3>, dim3(e.max_waves), dim3(64), 0, st, j.enc, ngroups);
+        else hipLaunchKernelGGL(encode_loop_kernel<2>, dim3(e.max_waves), dim3(64), 0, st, j.enc, ngroups);
+    } else if (e.f.ndim == 3) {
+        hipLaunchKernelGGL(encode_kernel<3>, dim3((unsigned)ngroups), dim3(64), 0, st, j.enc);
+    } else {
+        hipLaunchKernelGGL(encode_kernel<2>, dim3((unsigned)ngroups), dim3(64), 0, st, j.enc);
+    }
     hipLaunchKernelGGL(tile_sum_kernel, dim3(j.plan.ntiles), dim3(TILE), 0, st, j.enc.chunk_bits,
                        j.enc.nchunks, j.plan.tile_sum);
     hipLaunchKernelGGL(plan_kernel, dim3(1), dim3(256), 0, st, j.plan);
@@ -1082,9 +1093,14 @@ void codec_decode(const DecodeArgs &d, hipStream_t st)
 {
     const DecJob j = make_dec_job(d);
     const long ngroups = j.dec.nchunks / 64;
-    const int nwaves = (int)(d.max_waves > 0 && d.max_waves < ngroups ? d.max_waves : ngroups);
-    if (d.f.ndim == 3) hipLaunchKernelGGL(decode_kernel<3>, dim3(nwaves), dim3(64), 0, st, j.dec, ngroups);
-    else hipLaunchKernelGGL(decode_kernel<2>, dim3(nwaves), dim3(64), 0, st, j.dec, ngroups);
+    if (d.max_waves > 0 && d.max_waves < ngroups) {
+        if (d.f.ndim == 3) hipLaunchKernelGGL(decode_loop_kernel<3>, dim3(d.max_waves), dim3(64), 0, st, j.dec, ngroups);
+        else hipLaunchKernelGGL(decode_loop_kernel<2>, dim3(d.max_waves), dim3(64), 0, st, j.dec, ngroups);
+    } else if (d.f.ndim == 3) {
+        hipLaunchKernelGGL(decode_kernel<3>, dim3((unsigned)ngroups), dim3(64), 0, st, j.dec);
+    } else {
+        hipLaunchKernelGGL(decode_kernel<2>, dim3((unsigned)ngroups), dim3(64), 0, st, j.dec);
+    }
 }
 
 size_t codec_job_bytes(bool encode) { return encode ? sizeof(EncJob) : sizeof(DecJob); }
@@ -1097,11 +1113,11 @@ int codec_resident_waves(int ndim, bool encode)
         return 0;
     hipError_t e;
     if (encode)
-        e = ndim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, encode_kernel<3>, 64, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, encode_kernel<2>, 64, 0);
+        e = ndim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, encode_loop_kernel<3>, 64, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, encode_loop_kernel<2>, 64, 0);
     else
-        e = ndim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_kernel<3>, 64, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_kernel<2>, 64, 0);
+        e = ndim == 3 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_loop_kernel<3>, 64, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, decode_loop_kernel<2>, 64, 0);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return 0;
