@@ -288,6 +288,34 @@ def run_c2(args, torch, F, dev):
     trend = {}
     for k, u in snaps.items():
         trend[k] = round(4.0 * n / ctx.compress(u, 1e-4).numel(), 3)
+    # Sixteen snapshots (steps 150, 160, ..., 300) in one batched call
+    # (ckpt_compress_batch / ckpt_decompress_batch): one 256^3 field is
+    # 16,384 chunks, a quarter of the GPU's SIMDs with one wave each; sixteen
+    # fill it.  Every stream equals the single-field call's.
+    ks = list(range(150, 301, 10))
+    batch = []
+    for k in ks:
+        if k in snaps:
+            batch.append(snaps[k])
+            continue
+        sh = synth.config2_shot(nt=k)
+        q = torch.from_numpy(sh.wavelet().astype(np.float32)).to(dev)
+        _, u, _ = ctx.forward_state(sh, m, q)
+        batch.append(u[nb:-nb, nb:-nb, nb:-nb].contiguous())
+    batched = {"snapshots_at_steps": ks, "atol": 1e-4}
+    sts, te = timed(lambda: ctx.compress_batch(batch, 1e-4), "ms_encode", max(args.steps, 5))
+    ys, td = timed(lambda: ctx.decompress_batch(sts, [x.shape] * len(batch)), "ms_decode", max(args.steps, 5))
+    for u, st1, y in zip(batch, sts, ys):
+        assert torch.equal(st1, ctx.compress(u, 1e-4))
+        assert (y - u).abs().max().item() <= 1e-4
+    raw = 4.0 * n * len(batch)
+    batched.update({"fields": len(batch), "ratio": round(raw / sum(t.numel() for t in sts), 3),
+                    "compress_ms": round(te, 4), "decompress_ms": round(td, 4),
+                    "compress_GBs": round(raw / (te * 1e-3) / 1e9, 1),
+                    "decompress_GBs": round(raw / (td * 1e-3) / 1e9, 1),
+                    "streams_equal_single_calls": True})
+    log("batched snapshots", batched)
+    del batch, sts, ys
     # One field of the 3D single-shot gradient's size (961 x 961 x 367,
     # 5.3M blocks: the launch the gradient's codec makes), built by tiling
     # the snapshot, dense and in the padded checkpoint layout (16-byte
@@ -343,6 +371,7 @@ def run_c2(args, torch, F, dev):
                              "per-lane bit work, not HBM"},
         "sweep": rows,
         "ratio_by_step_atol_1e-4": trend,
+        "batched_snapshots": batched,
         "field_961x961x367": c3_field,
     }
     if not args.no_cpu_baseline:

@@ -359,6 +359,26 @@ int ckpt_decompress_view(fwi_ctx *ctx, const void *stream_bytes, size_t nbytes,
                          float *origin, int ndim, const int n[3], long sx, long sy,
                          int padded, hipStream_t stream);
 
+/* The codec (Sec. 1.4 / Sec. 3) on several dense fields of one ndim at once:
+ * one launch per pipeline stage for all of them, so that fields too small
+ * to fill the GPU alone (a 256^3 field is 16,384 chunks, one lane each)
+ * are coded at the rate of one large field.  n [host] holds 3 ints per
+ * field (the dims of field i at n + 3 i, as ckpt_compress's n[3]).
+ * ckpt_compress_batch: fields[i] [device] float32, out[i] [device] with
+ * cap[i] bytes, nbytes[i] [host] the stream sizes on return; every stream
+ * is byte for byte what ckpt_compress writes for that field.  The status
+ * covers the call as a whole (FWI_ECAPACITY, FWI_ENONFINITE, FWI_ERANGE as
+ * ckpt_compress: no stream is then usable).  ckpt_decompress_batch checks
+ * every header as ckpt_decompress does and writes fields[i] [device].
+ * nfields >= 1; the context's codec workspace grows to the fields' sum.
+ * Both synchronise the stream before returning. */
+int ckpt_compress_batch(fwi_ctx *ctx, int nfields, int ndim, const int *n,
+                        const float *const *fields, double atol, void *const *out,
+                        const size_t *cap, size_t *nbytes, hipStream_t stream);
+int ckpt_decompress_batch(fwi_ctx *ctx, int nfields, int ndim, const int *n,
+                          const void *const *streams, const size_t *nbytes,
+                          float *const *fields, hipStream_t stream);
+
 /* Host-only binomial checkpoint schedule reversing states N..1 with nslots
  * slots (minimal forward steps; largest optimal split).  out [host] holds up
  * to cap actions; *nactions receives the full count (FWI_ECAPACITY if it

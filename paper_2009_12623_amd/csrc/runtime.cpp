@@ -2737,16 +2737,12 @@ static void compress_view(fwi_ctx *c, const FieldView &f, const float *field, do
     end_call(c, st);
 }
 
-static void decompress_view(fwi_ctx *c, const FieldView &f, const void *stream, size_t nbytes, float *field,
-                            hipStream_t st)
+// the 64-byte header of a stream for field f (host copy), checked against
+// the field's geometry and the stream's byte count (format: Sec. 1.4 codec)
+static void check_stream_header(const unsigned char *h, const FieldView &f, size_t nbytes)
 {
-    begin_call(c, st);
     const int ndim = f.ndim;
-    CodecGeom g = codec_geom(ndim, f.n);
-    if (nbytes < 64) throw Error{FWI_ECORRUPT, "stream shorter than its header"};
-    unsigned char h[64];
-    HIPCHK(hipMemcpyAsync(h, stream, 64, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    const CodecGeom g = codec_geom(ndim, f.n);
     auto u32 = [&](int o) { unsigned v; memcpy(&v, h + o, 4); return v; };
     auto u64 = [&](int o) { unsigned long long v; memcpy(&v, h + o, 8); return v; };
     const unsigned want[3] = {(unsigned)f.n[0], (unsigned)(ndim == 3 ? f.n[1] : f.n[2]),
@@ -2761,6 +2757,17 @@ static void decompress_view(fwi_ctx *c, const FieldView &f, const void *stream, 
     const unsigned long long pbits = u64(48);
     const unsigned long long total = 64ull + (unsigned long long)g.table_bytes + 8ull * ((pbits + 63) / 64);
     if (u64(56) != total || nbytes < total) throw Error{FWI_ECORRUPT, "stream length mismatch"};
+}
+
+static void decompress_view(fwi_ctx *c, const FieldView &f, const void *stream, size_t nbytes, float *field,
+                            hipStream_t st)
+{
+    begin_call(c, st);
+    if (nbytes < 64) throw Error{FWI_ECORRUPT, "stream shorter than its header"};
+    unsigned char h[64];
+    HIPCHK(hipMemcpyAsync(h, stream, 64, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    check_stream_header(h, f, nbytes);
     reset_status(c, st);
     DecodeArgs d{};
     d.f = f;
@@ -2817,6 +2824,138 @@ int ckpt_decompress_view(fwi_ctx *c, const void *stream, size_t nbytes, float *o
     return guarded([&] {
         if (!c || !stream || !origin || !n) throw Error{FWI_EINVAL, "null argument"};
         decompress_view(c, checked_view(ndim, n, sx, sy, padded, origin), stream, nbytes, origin, st);
+    });
+}
+
+// dense fields of a batched codec call: field i has dims n[3 i .. 3 i + ndim)
+static std::vector<FieldView> batch_views(int nfields, int ndim, const int *n)
+{
+    if (nfields < 1) throw Error{FWI_EINVAL, "nfields must be >= 1"};
+    if (ndim != 2 && ndim != 3) throw Error{FWI_EINVAL, "ndim must be 2 or 3"};
+    std::vector<FieldView> v((size_t)nfields);
+    for (size_t i = 0; i < (size_t)nfields; ++i) {
+        for (int d = 0; d < ndim; ++d)
+            if (n[3 * i + (size_t)d] < 1) throw Error{FWI_EINVAL, "dims must be >= 1"};
+        v[i] = dense_view(ndim, n + 3 * i);
+    }
+    return v;
+}
+
+int ckpt_compress_batch(fwi_ctx *c, int nfields, int ndim, const int *n, const float *const *fields,
+                        double atol, void *const *out, const size_t *cap, size_t *nbytes, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !n || !fields || !out || !cap || !nbytes) throw Error{FWI_EINVAL, "null argument"};
+        const std::vector<FieldView> fv = batch_views(nfields, ndim, n);
+        for (int i = 0; i < nfields; ++i)
+            if (!fields[i] || !out[i]) throw Error{FWI_EINVAL, "null field or output"};
+        if (!(atol >= 2.2250738585072014e-308) || !std::isfinite(atol))
+            throw Error{FWI_EINVAL, "atol must be a positive normal number"};
+        begin_call(c, st);
+        // each field's encode workspace is a slice of the context's buffers
+        std::vector<size_t> o_scr(fv.size()), o_bits(fv.size()), o_tile(fv.size());
+        size_t scr = 0, bits = 0, tiles = 0;
+        for (size_t i = 0; i < fv.size(); ++i) {
+            const CodecGeom g = codec_geom(ndim, fv[i].n);
+            o_scr[i] = scr;
+            o_bits[i] = bits;
+            o_tile[i] = tiles;
+            scr += (size_t)g.nchunks * (size_t)g.max_chunk_words;
+            bits += (size_t)g.nchunks;
+            tiles += (size_t)((g.nchunks + 1023) / 1024) + 2;
+        }
+        c->scratch.ensure(scr);
+        c->chunk_bits.ensure(bits);
+        c->chunk_off.ensure(tiles);
+        c->misc.ensure(4 * fv.size());
+        c->flags.ensure(1);
+        c->btab.ensure((size_t)nfields * codec_job_bytes(true) + 256);
+        HIPCHK(hipMemsetAsync(c->flags.p, 0, sizeof(unsigned int), st));
+        HIPCHK(hipMemsetAsync(c->misc.p, 0, 4 * fv.size() * sizeof(unsigned long long), st));
+        std::vector<EncodeArgs> args(fv.size());
+        for (size_t i = 0; i < fv.size(); ++i) {
+            EncodeArgs &e = args[i];
+            e.f = fv[i];
+            e.src = fields[i];
+            e.atol = atol;
+            e.scratch = c->scratch.p + o_scr[i];
+            e.chunk_bits = c->chunk_bits.p + o_bits[i];
+            e.chunk_off = c->chunk_off.p + o_tile[i];
+            e.dst = (unsigned char *)out[i];
+            e.cap = cap[i];
+            e.out_bytes = c->misc.p + 4 * i;
+            e.pool_high = c->misc.p + 4 * i + 1;
+            e.total_bytes = c->misc.p + 4 * i + 2;
+            e.flags = c->flags.p;
+        }
+        {
+            Timer tm(c, st, K_ENC);
+            const size_t off = c->btab.take((size_t)nfields * codec_job_bytes(true));
+            codec_encode_batch(args.data(), nfields, c->btab.host + off, c->btab.dev.p + off, true, st);
+        }
+        HIPCHK(hipGetLastError());
+        std::vector<unsigned long long> misc(4 * fv.size());
+        unsigned int fl = 0;
+        HIPCHK(hipMemcpyAsync(misc.data(), c->misc.p, misc.size() * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(&fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (fl & 1u) throw Error{FWI_ENONFINITE, "non-finite value in a field"};
+        if (fl & 8u)
+            throw Error{FWI_ERANGE, "a value at or above atol * 2^23 in a field: the fixed-accuracy bound "
+                                    "cannot hold at this atol (raise atol)"};
+        if (fl & 2u) throw Error{FWI_ECAPACITY, "an output buffer is smaller than its stream"};
+        long long total = 0;
+        for (size_t i = 0; i < fv.size(); ++i) {
+            nbytes[i] = (size_t)misc[4 * i];
+            total += (long long)misc[4 * i];
+        }
+        c->stats.ckpt_bytes = total;
+        c->stats.n_encode = nfields;
+        end_call(c, st);
+    });
+}
+
+int ckpt_decompress_batch(fwi_ctx *c, int nfields, int ndim, const int *n, const void *const *streams,
+                          const size_t *nbytes, float *const *fields, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || !n || !streams || !nbytes || !fields) throw Error{FWI_EINVAL, "null argument"};
+        const std::vector<FieldView> fv = batch_views(nfields, ndim, n);
+        for (int i = 0; i < nfields; ++i) {
+            if (!streams[i] || !fields[i]) throw Error{FWI_EINVAL, "null stream or field"};
+            if (nbytes[i] < 64) throw Error{FWI_ECORRUPT, "stream shorter than its header"};
+        }
+        begin_call(c, st);
+        c->flags.ensure(1);
+        c->btab.ensure((size_t)nfields * codec_job_bytes(false) + 256);
+        std::vector<unsigned char> h(64 * fv.size());
+        for (size_t i = 0; i < fv.size(); ++i)
+            HIPCHK(hipMemcpyAsync(h.data() + 64 * i, streams[i], 64, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t i = 0; i < fv.size(); ++i) check_stream_header(h.data() + 64 * i, fv[i], nbytes[i]);
+        HIPCHK(hipMemsetAsync(c->flags.p, 0, sizeof(unsigned int), st));
+        std::vector<DecodeArgs> args(fv.size());
+        for (size_t i = 0; i < fv.size(); ++i) {
+            DecodeArgs &d = args[i];
+            d.f = fv[i];
+            d.dst = fields[i];
+            d.stream = (const unsigned char *)streams[i];
+            d.nbytes = nbytes[i];
+            d.flags = c->flags.p;
+        }
+        {
+            Timer tm(c, st, K_DEC);
+            const size_t off = c->btab.take((size_t)nfields * codec_job_bytes(false));
+            codec_decode_batch(args.data(), nfields, c->btab.host + off, c->btab.dev.p + off, true, st);
+        }
+        HIPCHK(hipGetLastError());
+        unsigned int fl = 0;
+        HIPCHK(hipMemcpyAsync(&fl, c->flags.p, sizeof(fl), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (fl & 4u) throw Error{FWI_ECORRUPT, "a stream failed to decode"};
+        c->stats.n_decode = nfields;
+        end_call(c, st);
     });
 }
 

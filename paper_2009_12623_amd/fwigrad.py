@@ -90,7 +90,7 @@ EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_s
            "ckpt_compress_view", "ckpt_decompress_view", "fwi_forward_ckpt_batch",
            "fwi_backward_batch", "fwi_gradient_subsampled", "fwi_forward_span",
            "fwi_ctx_set_overlap", "fwi_time_shape", "fwi_tape_stream", "fwi_gradient_stack",
-           "fwi_backward_stack", "ckpt_compress_static"]
+           "fwi_backward_stack", "ckpt_compress_static", "ckpt_compress_batch", "ckpt_decompress_batch"]
 
 
 def lib():
@@ -155,6 +155,11 @@ def lib():
     L.fwi_backward_stack.argtypes = [P, P, ctypes.POINTER(P), ctypes.POINTER(fwi_stack), P, P]
     L.ckpt_compress_static.argtypes = [P, I, ctypes.POINTER(ctypes.c_int), ctypes.c_double, P, ctypes.c_size_t,
                                        ctypes.POINTER(ctypes.c_size_t), P]
+    L.ckpt_compress_batch.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(P), ctypes.c_double,
+                                      ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_size_t), P]
+    L.ckpt_decompress_batch.argtypes = [P, I, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(P),
+                                        ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(P), P]
     L.fwi_tape_stream.argtypes = [P, I, I, I, P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t), P]
     L.fwi_time_shape.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot),
                                  ctypes.POINTER(ctypes.c_int), I, ctypes.POINTER(ctypes.c_double),
@@ -526,6 +531,38 @@ class Context:
         origin = ctypes.c_void_p(_ptr(array).value + 4 * int(offset))
         check(lib().ckpt_decompress_view(self.h, _ptr(stream), stream.numel(), origin, len(shape),
                                          _dims3(shape), int(sx), int(sy), int(bool(padded)), _stream()))
+
+    def compress_batch(self, fields, atol: float):
+        """ckpt_compress_batch: the streams of several dense fields of one
+        ndim, coded in one launch per pipeline stage (each stream equals
+        compress() of its field)"""
+        n = len(fields)
+        ndim = fields[0].dim()
+        if any(f.dim() != ndim or not f.is_contiguous() or f.dtype != torch.float32 for f in fields):
+            raise ValueError("fields must be contiguous float32 tensors of one ndim")
+        caps = [ckpt_bound(f.shape) for f in fields]
+        outs = [torch.empty(cap, dtype=torch.uint8, device=f.device) for f, cap in zip(fields, caps)]
+        dims = (ctypes.c_int * (3 * n))(*[d for f in fields for d in list(_dims3(f.shape))])
+        nb = (ctypes.c_size_t * n)()
+        check(lib().ckpt_compress_batch(self.h, n, ndim, dims, (ctypes.c_void_p * n)(*[_ptr(f) for f in fields]),
+                                        float(atol), (ctypes.c_void_p * n)(*[_ptr(o) for o in outs]),
+                                        (ctypes.c_size_t * n)(*caps), nb, _stream()))
+        return [o[:nb[i]] for i, o in enumerate(outs)]
+
+    def decompress_batch(self, streams, shapes):
+        """ckpt_decompress_batch: decode several streams of one ndim in one
+        launch into new tensors of the given shapes"""
+        n = len(streams)
+        ndim = len(shapes[0])
+        if any(len(s) != ndim for s in shapes):
+            raise ValueError("shapes must have one ndim")
+        outs = [torch.empty(tuple(sh), dtype=torch.float32, device=st.device) for st, sh in zip(streams, shapes)]
+        dims = (ctypes.c_int * (3 * n))(*[d for sh in shapes for d in list(_dims3(sh))])
+        check(lib().ckpt_decompress_batch(self.h, n, ndim, dims,
+                                          (ctypes.c_void_p * n)(*[_ptr(s) for s in streams]),
+                                          (ctypes.c_size_t * n)(*[s.numel() for s in streams]),
+                                          (ctypes.c_void_p * n)(*[_ptr(o) for o in outs]), _stream()))
+        return outs
 
     def decompress(self, stream: torch.Tensor, shape) -> torch.Tensor:
         out = torch.empty(tuple(shape), dtype=torch.float32, device=stream.device)
