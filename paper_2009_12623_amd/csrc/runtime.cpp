@@ -377,6 +377,7 @@ struct fwi_tape {
         }
     };
     std::vector<std::unique_ptr<Shot>> shots;
+    long long fwd_bytes = 0;         // batched: checkpoint bytes the forward stored
 };
 
 namespace {
@@ -2207,6 +2208,22 @@ static void check_batch_shots(int nshots, const fwi_grid *grids)
     }
 }
 
+// pool high-water mark (sum over the shots) and checkpoint bytes stored
+// so far on a batched tape: each shot's counters live in its own buffer
+static void tape_pool_totals(const fwi_tape *t, hipStream_t st, long long *high, long long *bytes)
+{
+    std::vector<unsigned long long> mc(4 * t->shots.size(), 0);
+    for (size_t i = 0; i < t->shots.size(); ++i)
+        HIPCHK(hipMemcpyAsync(&mc[4 * i], t->shots[i]->misc.p, 4 * sizeof(unsigned long long),
+                              hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *high = *bytes = 0;
+    for (size_t i = 0; i < t->shots.size(); ++i) {
+        *high += (long long)mc[4 * i + 1];
+        *bytes += (long long)mc[4 * i + 2];
+    }
+}
+
 int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const float *const *models,
                            const fwi_shot *shots, const fwi_ckpt_cfg *cfg, float *const *d_sim,
                            fwi_tape **tape, hipStream_t st)
@@ -2335,6 +2352,10 @@ int fwi_forward_ckpt_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const 
                                           hipMemcpyDeviceToDevice, st));
             HIPCHK(hipGetLastError());
             finish_status(c, st);
+            if (cfg->compress) {
+                tape_pool_totals(t.get(), st, &c->stats.pool_high, &c->stats.ckpt_bytes);
+                t->fwd_bytes = c->stats.ckpt_bytes;
+            }
             end_call(c, st);
         } catch (...) {
             for (auto &sh : t->shots) sh->release();
@@ -2421,6 +2442,11 @@ static int backward_batch_impl(fwi_ctx *c, fwi_tape *t, const float *const *dd, 
         if (c->graphs) finish_gradients(c, ex, grads, smaps, sk, gstack, st);
         HIPCHK(hipGetLastError());
         finish_status(c, st);
+        if (t->cfg.compress) {
+            long long total = 0;
+            tape_pool_totals(t, st, &c->stats.pool_high, &total);
+            c->stats.ckpt_bytes = total - t->fwd_bytes;
+        }
         t->used = true;
         end_call(c, st);
     });

@@ -307,6 +307,9 @@ class Context:
         h = ctypes.c_void_p()
         check(lib().fwi_ctx_create(ctypes.byref(h), device, int(pool_bytes)))
         self.h = h
+        # compressed pools that batched autograd calls needed, by shots and
+        # schedule (forward_modelling_batch starts there next time)
+        self.pool_hints = {}
 
     def close(self):
         if self.h:
@@ -678,17 +681,27 @@ class FwiBatchFunction(torch.autograd.Function):
 
 def forward_modelling_batch(context, m, shots, wavelet, nslots=40, compress=True, atol=1e-4,
                             pool_bytes=0):
-    """Differentiable traces of all shots of model m in one batched sweep."""
+    """Differentiable traces of all shots of model m in one batched sweep.
+
+    Compressed checkpoints start from pool_bytes (default a quarter of the
+    exact pool); on overflow the pool doubles and the forward pass is
+    repeated, and the context remembers the pool that sufficed for these
+    shots, so later calls start there."""
     exact = sum(ckpt_pool_bytes(s, nslots, False) for s in shots)
     if not compress:
         return FwiBatchFunction.apply(m, wavelet, context, list(shots), int(nslots), False,
                                       float(atol), int(pool_bytes or exact))
     worst = sum(ckpt_pool_bytes(s, nslots, True) for s in shots)
+    key = (tuple((s.ndim, tuple(s.shape), s.nbl, s.nt) for s in shots), int(nslots), float(atol),
+           int(pool_bytes))
     pool = int(pool_bytes or min(worst, max(exact // 4, 1 << 24)))
+    pool = max(pool, context.pool_hints.get(key, 0))
     while True:
         try:
-            return FwiBatchFunction.apply(m, wavelet, context, list(shots), int(nslots), True,
-                                          float(atol), pool)
+            d = FwiBatchFunction.apply(m, wavelet, context, list(shots), int(nslots), True,
+                                       float(atol), pool)
+            context.pool_hints[key] = pool
+            return d
         except FwiError as e:
             if e.code != FWI_ECAPACITY or pool >= worst:
                 raise
