@@ -107,22 +107,23 @@ def _deep_shot(so, zsrc, nt=30):
     return synth.Shot(3, shape, 10.0, so, nbl, nt, dt, 2500.0, 1500.0 / 80.0, (9, 10, zsrc), rec)
 
 
-@pytest.mark.parametrize("xchunk,rpl,remap,deep,vz", [(3, 2, 0, 0, 1), (7, 4, 1, 0, 1), (64, 2, 1, 0, 1),
-                                                      (16, 4, 0, 0, 1), (16, 2, 2, 0, 1), (7, 4, 2, 0, 1),
-                                                      (5, 2, 2, 1, 1), (3, 2, 0, 1, 1), (16, 2, 1, 1, 1),
-                                                      (64, 2, 0, 1, 1), (1, 2, 0, 1, 1), (2, 2, 0, 1, 1),
-                                                      (3, 2, 0, 0, 2), (7, 4, 1, 0, 2), (16, 2, 2, 0, 2),
-                                                      (64, 4, 2, 0, 2), (1, 4, 0, 0, 2), (5, 2, 1, 0, 2),
-                                                      (16, 2, 3, 0, 1), (7, 2, 4, 0, 1), (3, 4, 4, 0, 1),
-                                                      (5, 2, 3, 0, 2)])
-@pytest.mark.parametrize("so", [4, 8, 16])
-@pytest.mark.parametrize("grid", ["cube", "deep_mid", "deep_tail"])
+_SHAPES = [(3, 2, 0, 0, 1), (7, 4, 1, 0, 1), (64, 2, 1, 0, 1), (16, 4, 0, 0, 1), (16, 2, 2, 0, 1),
+           (7, 4, 2, 0, 1), (5, 2, 2, 1, 1), (3, 2, 0, 1, 1), (16, 2, 1, 1, 1), (64, 2, 0, 1, 1),
+           (1, 2, 0, 1, 1), (2, 2, 0, 1, 1), (3, 2, 0, 0, 2), (7, 4, 1, 0, 2), (16, 2, 2, 0, 2),
+           (64, 4, 2, 0, 2), (1, 4, 0, 0, 2), (5, 2, 1, 0, 2), (16, 2, 3, 0, 1), (7, 2, 4, 0, 1),
+           (3, 4, 4, 0, 1), (5, 2, 3, 0, 2)]
+# every shape on the cube grid at SO 4/8/16; the deep grids (several z tiles,
+# ragged tail) with SO 8/16 for the two-point lanes and three one-point shapes
+_SHAPE_CASES = [sh + (so, grid) for grid in ("cube", "deep_mid", "deep_tail") for so in (4, 8, 16)
+                for sh in _SHAPES
+                if grid == "cube" or (so != 4 and (sh[4] == 2 or (sh[0], sh[1]) in ((16, 2), (7, 4), (7, 2))))]
+
+
+@pytest.mark.parametrize("xchunk,rpl,remap,deep,vz,so,grid", _SHAPE_CASES)
 def test_3d_stencil_launch_shapes_match_oracle(xchunk, rpl, remap, deep, vz, so, grid, monkeypatch):
     """every launch shape (x planes per workgroup, rows per lane, tile order,
     loads of one or two planes in flight, one or two z points per lane); the
     deep grids span several 128-point z tiles with a ragged, odd tail"""
-    if grid != "cube" and (so == 4 or (vz == 1 and (xchunk, rpl) not in ((16, 2), (7, 4), (7, 2)))):
-        pytest.skip("the deep grids cover the two-point lanes and three one-point shapes")
     monkeypatch.setenv("FWI_XCHUNK", str(xchunk))
     monkeypatch.setenv("FWI_RPL", str(rpl))
     monkeypatch.setenv("FWI_REMAP", str(remap))
