@@ -143,6 +143,26 @@ def test_3d_stencil_launch_shapes_match_oracle(xchunk, rpl, remap, deep, vz, so,
     c.close()
 
 
+@pytest.mark.parametrize("xchunk", [1, 3, 4, 7, 16, 64])
+@pytest.mark.parametrize("so", [4, 8, 16])
+def test_2d_stencil_launch_shapes_match_oracle(xchunk, so, monkeypatch):
+    """2D launch shapes (x planes per workgroup) on a grid of two 256-point
+    z tiles with a ragged tail and x chunks that do not divide it: traces
+    and gradient against the oracle"""
+    monkeypatch.setenv("FWI_XCHUNK", str(xchunk))
+    shot = synth.tiny_shot(2, n=290, so=so, nbl=5, nt=35)
+    m0, mt, q = inputs(shot)
+    p0 = oracle_problem(shot, m0, q)
+    dobs = solver.forward(oracle_problem(shot, mt, q))
+    _, gref, dref = solver.gradient(p0, dobs)
+    c = F.Context(0, pool_bytes=1 << 27)
+    d = c.forward(shot, dev(m0), dev(q)).cpu().numpy()
+    _, g = c.gradient(shot, dev(m0), dev(q), dev(dobs.astype(np.float32)), nslots=3)
+    c.close()
+    assert metrics.rel_l2(d, dref) <= 1e-4
+    assert metrics.rel_l2(g.cpu().numpy(), gref) <= 1e-4
+
+
 @pytest.mark.parametrize("xchunk,rpl,remap,vz", [(16, 2, 2, 1), (7, 4, 0, 1), (3, 2, 0, 2), (7, 4, 1, 2),
                                                  (16, 2, 2, 2), (64, 4, 2, 2), (1, 4, 0, 2), (16, 2, 3, 1),
                                                  (3, 2, 4, 1), (7, 4, 4, 2)])
