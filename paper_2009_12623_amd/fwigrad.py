@@ -540,6 +540,8 @@ class Context:
         ndim, coded in one launch per pipeline stage (each stream equals
         compress() of its field)"""
         n = len(fields)
+        if n == 0:
+            raise ValueError("no fields")
         ndim = fields[0].dim()
         if any(f.dim() != ndim or not f.is_contiguous() or f.dtype != torch.float32 for f in fields):
             raise ValueError("fields must be contiguous float32 tensors of one ndim")
@@ -556,6 +558,8 @@ class Context:
         """ckpt_decompress_batch: decode several streams of one ndim in one
         launch into new tensors of the given shapes"""
         n = len(streams)
+        if n == 0 or len(shapes) != n:
+            raise ValueError("one shape per stream, at least one")
         ndim = len(shapes[0])
         if any(len(s) != ndim for s in shapes):
             raise ValueError("shapes must have one ndim")
