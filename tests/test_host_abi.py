@@ -63,6 +63,10 @@ def test_bad_arguments_are_status_codes():
     assert L.ckpt_bound(3, dims, ctypes.byref(out)) == F.FWI_EINVAL
     assert L.ckpt_bound(4, dims, ctypes.byref(out)) == F.FWI_EINVAL
     assert b"dims" in L.fwi_last_error() or len(L.fwi_last_error()) > 0
+    # batched codec calls: a null context or null arrays are refused before any device call
+    nb = (ctypes.c_size_t * 1)()
+    assert L.ckpt_compress_batch(None, 1, 3, dims, None, 1e-4, None, None, nb, None) == F.FWI_EINVAL
+    assert L.ckpt_decompress_batch(None, 1, 3, dims, None, nb, None, None) == F.FWI_EINVAL
 
 
 def test_context_creation_without_device_fails_cleanly():
