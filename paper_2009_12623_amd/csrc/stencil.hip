@@ -671,12 +671,14 @@ void step3w_kernel(StepParams p, int ntz, int nty, int nwg, int launched)
 }
 
 // ------------------------------------------------------------------- 2D
-// Workgroup = 256 lanes along z, one row each, streaming x with the same
-// pipelining; the z neighbours come from a double-buffered LDS row.
+// Workgroup = 256 lanes along z, one row each, streaming x two planes per
+// step of the loop: the z neighbours of both planes come from LDS rows
+// written together, so one barrier serves two planes; the x neighbours sit
+// in a register queue (planes x - R .. x + R + 1).
 template <int R, bool ADJ>
 __device__ __forceinline__ void step2d_body(const StepParams &p, int hw, int ntz, int nwg)
 {
-    __shared__ float row[2][TILE_Z2 + 2 * R];
+    __shared__ float row[2][2][TILE_Z2 + 2 * R];
     if (hw >= nwg) {
         gather_block(p, hw - nwg);
         return;
@@ -693,53 +695,94 @@ __device__ __forceinline__ void step2d_body(const StepParams &p, int hw, int ntz
     const unsigned srcb = p.src >= 0 ? org + 4u * (unsigned)p.src : 0xFFFFFFFFu;
     const float *__restrict__ u1 = p.u1;
     const bool hzl = tz < R, hzr = tz >= TILE_Z2 - R;
+    const bool halo = hzl || hzr;
+    const int hslot = hzl ? tz : tz + 2 * R;
     const unsigned hz_off = org + 4u * (unsigned)(hzl ? (z0 - R + tz) : (z + R));
     const unsigned col = org + 4u * z;
     const int dz = layer_depth(z, p.nz, p.nbl);
 
-    float q[2 * R + 1];
+    // q[i]: u1 on plane x - R + i (x the first plane of the pair); u2, b,
+    // (uk, g) of planes x and x + 1 in [0] and [1]
+    float q[2 * R + 2];
+    float u2v[2], bb[2], ukv[2], gv[2];
+    const bool two = xb + 1 < xe;
 #pragma unroll
     for (int i = 0; i <= 2 * R; ++i) q[i] = ld(u1, col + (unsigned)(xb - R + i) * bsx);
-    row[0][tz + R] = q[R];
-    if (hzl || hzr) row[0][hzl ? tz : tz + 2 * R] = ld(u1, (unsigned)xb * bsx + hz_off);
+    q[2 * R + 1] = two ? ld(u1, col + (unsigned)(xb + R + 1) * bsx) : 0.f;
     unsigned pa = col + (unsigned)xb * bsx;
-    float u2v = act ? ldnt(p.u2, pa) : 0.f, bb = act ? ldnt(p.b, pa) : 0.f, ukv = 0.f, gv = 0.f;
-    if (ADJ && act) { ukv = ldnt(p.uk, pa); gv = ldnt(p.g, pa); }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const bool in = j == 0 || two;
+        u2v[j] = in && act ? ldnt(p.u2, pa + (unsigned)j * bsx) : 0.f;
+        bb[j] = in && act ? ldnt(p.b, pa + (unsigned)j * bsx) : 0.f;
+        ukv[j] = ADJ && in && act ? ldnt(p.uk, pa + (unsigned)j * bsx) : 0.f;
+        gv[j] = ADJ && in && act ? ldnt(p.g, pa + (unsigned)j * bsx) : 0.f;
+    }
+    row[0][0][tz + R] = q[R];
+    row[0][1][tz + R] = q[R + 1];
+    if (halo) {
+        row[0][0][hslot] = ld(u1, (unsigned)xb * bsx + hz_off);
+        row[0][1][hslot] = two ? ld(u1, (unsigned)(xb + 1) * bsx + hz_off) : 0.f;
+    }
     __syncthreads();
-    for (int x = xb; x < xe; ++x) {
-        const int cur = (x - xb) & 1;
-        const bool nxt = x + 1 < xe;
-        float nq = 0.f, nh = 0.f, nu2 = 0.f, nbv = 0.f, nuk = 0.f, ng = 0.f;
-        if (nxt) {
-            if (hzl || hzr) nh = ld(u1, (unsigned)(x + 1) * bsx + hz_off);
-            nq = ld(u1, col + (unsigned)(x + 1 + R) * bsx);
+    for (int x = xb; x < xe; x += 2) {
+        const int cur = ((x - xb) >> 1) & 1;
+        // planes of the next pair that exist in the chunk
+        const bool n0 = x + 2 < xe, n1 = x + 3 < xe;
+        float nq0 = 0.f, nq1 = 0.f, nh0 = 0.f, nh1 = 0.f;
+        float nu2[2] = {0.f, 0.f}, nbv[2] = {0.f, 0.f}, nuk[2] = {0.f, 0.f}, ng[2] = {0.f, 0.f};
+        if (n0) {
+            if (halo) nh0 = ld(u1, (unsigned)(x + 2) * bsx + hz_off);
+            nq0 = ld(u1, col + (unsigned)(x + 2 + R) * bsx);
             if (act) {
-                nu2 = ldnt(p.u2, pa + bsx);
-                nbv = ldnt(p.b, pa + bsx);
-                if (ADJ) { nuk = ldnt(p.uk, pa + bsx); ng = ldnt(p.g, pa + bsx); }
+                nu2[0] = ldnt(p.u2, pa + 2 * bsx);
+                nbv[0] = ldnt(p.b, pa + 2 * bsx);
+                if (ADJ) { nuk[0] = ldnt(p.uk, pa + 2 * bsx); ng[0] = ldnt(p.g, pa + 2 * bsx); }
             }
         }
-        if (act) {
-            const float c = q[R];
-            float lap = 0.0f;
-#pragma unroll
-            for (int k = 1; k <= R; ++k)
-                lap = fmaf(p.w[k], pair2(q[R - k], q[R + k], c) +
-                                   pair2(row[cur][tz + R - k], row[cur][tz + R + k], c), lap);
-            const int dx = layer_depth(x, p.nx, p.nbl);
-            const float inc = increment<ADJ>(p, dx * dx + dz * dz, pa == srcb, c, lap, u2v, bb);
-            st(p.out, pa, c + inc);
-            if (ADJ) st(p.g, pa, gv - ukv * (inc - (c - u2v)) * p.inv_dt2);
+        if (n1) {
+            if (halo) nh1 = ld(u1, (unsigned)(x + 3) * bsx + hz_off);
+            nq1 = ld(u1, col + (unsigned)(x + 3 + R) * bsx);
+            if (act) {
+                nu2[1] = ldnt(p.u2, pa + 3 * bsx);
+                nbv[1] = ldnt(p.b, pa + 3 * bsx);
+                if (ADJ) { nuk[1] = ldnt(p.uk, pa + 3 * bsx); ng[1] = ldnt(p.g, pa + 3 * bsx); }
+            }
         }
-        if (!nxt) break;
 #pragma unroll
-        for (int i = 0; i < 2 * R; ++i) q[i] = q[i + 1];
-        q[2 * R] = nq;
-        row[cur ^ 1][tz + R] = q[R];
-        if (hzl || hzr) row[cur ^ 1][hzl ? tz : tz + 2 * R] = nh;
-        u2v = nu2; bb = nbv;
-        if (ADJ) { ukv = nuk; gv = ng; }
-        pa += bsx;
+        for (int j = 0; j < 2; ++j) {
+            if (j == 1 && x + 1 >= xe) break;
+            if (act) {
+                const float c = q[R + j];
+                float lap = 0.0f;
+#pragma unroll
+                for (int k = 1; k <= R; ++k)
+                    lap = fmaf(p.w[k], pair2(q[R + j - k], q[R + j + k], c) +
+                                       pair2(row[cur][j][tz + R - k], row[cur][j][tz + R + k], c), lap);
+                const int dx = layer_depth(x + j, p.nx, p.nbl);
+                const unsigned pj = pa + (unsigned)j * bsx;
+                const float inc = increment<ADJ>(p, dx * dx + dz * dz, pj == srcb, c, lap, u2v[j], bb[j]);
+                st(p.out, pj, c + inc);
+                if (ADJ) st(p.g, pj, gv[j] - ukv[j] * (inc - (c - u2v[j])) * p.inv_dt2);
+            }
+        }
+        if (!n0) break;
+#pragma unroll
+        for (int i = 0; i < 2 * R; ++i) q[i] = q[i + 2];
+        q[2 * R] = nq0;
+        q[2 * R + 1] = nq1;
+        row[cur ^ 1][0][tz + R] = q[R];
+        row[cur ^ 1][1][tz + R] = q[R + 1];
+        if (halo) {
+            row[cur ^ 1][0][hslot] = nh0;
+            row[cur ^ 1][1][hslot] = nh1;
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            u2v[j] = nu2[j]; bb[j] = nbv[j];
+            if (ADJ) { ukv[j] = nuk[j]; gv[j] = ng[j]; }
+        }
+        pa += 2 * bsx;
         __syncthreads();
     }
 }
