@@ -406,11 +406,15 @@ def run_c4(args, torch, F, dev):
     ctx = F.Context(0, pool_bytes=int(os.environ.get("FWI_POOL_BYTES", 64 << 30)))
     ctx.set_timing(True)
     tunes = {}
+    tune_batch = None
     if not args.no_autotune:
         for s, m in zip(shots, m0s):
             key = tuple(s.comp_shape)
             if key not in tunes:
                 tunes[key] = ctx.autotune(s, m, q, steps=2)
+        # the one launch per step for all 32 crops gets its own x chunk
+        tune_batch = ctx.autotune_batch(shots, m0s, q, steps=2)
+        log("batch autotune:", tune_batch)
     d_obs = [ctx.forward(s, m, q) for s, m in zip(shots, mts)]
     torch.cuda.synchronize()
     nslots = args.slots or 40
@@ -509,6 +513,8 @@ def run_c4(args, torch, F, dev):
         "kernel_ms": {k: round(st[k], 1) for k in ("ms_forward", "ms_adjoint", "ms_encode", "ms_decode", "ms_total")},
         "ckpt_compression_factor": round(st["ckpt_raw_bytes"] / max(st["ckpt_bytes"], 1), 2),
         "captured_schedule": graphs,
+        "batch_autotune": None if tune_batch is None else
+        {k: tune_batch[k] for k in ("fwd_xchunk", "adj_xchunk", "fwd_ms", "adj_ms", "ncand")},
         "model_gradient": {"dims": [401, 401, 201], "s": round(t_stack, 3),
                            "l2_norm": float("%.4g" % g_model.double().norm().item()),
                            "nonzero_points": covered,
@@ -538,6 +544,10 @@ def run_c5(args, torch, F, dev):
     tune = None if args.no_autotune else ctx.autotune(shots[0], m0, q, steps=8)
     if tune:
         log("autotune:", tune)
+    # the batched launches (16 shots per step) get their own x chunk
+    tune_batch = None if args.no_autotune else ctx.autotune_batch(shots, [m0] * len(shots), q, steps=4)
+    if tune_batch:
+        log("batch autotune:", tune_batch)
     d_obs = [ctx.forward(s, mt, q) for s in shots]
     nslots = args.slots or 40
 
@@ -706,6 +716,8 @@ def run_c5(args, torch, F, dev):
         "schedule_per_shot": {"forward": nf, "adjoint": nt, "encodes": nenc,
                               "restores_uk": rr, "restores_both": ra},
         "captured_schedules": graphs,
+        "batch_autotune": None if tune_batch is None else
+        {k: tune_batch[k] for k in ("fwd_xchunk", "adj_xchunk", "fwd_ms", "adj_ms", "ncand")},
         "measured_at_equal_slots": ["per_shot_autograd_s_per_shot", "batched_vs_per_shot_grad_rel_l2",
                                     "stencil_gpts_batched_backward", "schedule_per_shot", "captured_schedules"],
     }

@@ -417,6 +417,23 @@ int fwi_autotune(fwi_ctx *ctx, const fwi_grid *g, const float *m,
                  const fwi_shot *shot, int steps, fwi_tune_result *out,
                  hipStream_t stream);
 
+/* Autotuner for batched shots: times the batched stencil launches (one
+ * launch per step for all nshots shots, as fwi_gradient_batch and the
+ * batched tapes run them) with x planes per workgroup in {8,16,32,64} (3D)
+ * or {4,8,16,32,64} (2D), 2 rows per lane, round-robin tile order; every
+ * candidate `steps` forward and `steps` adjoint launches four times,
+ * interleaved, on non-zero fields.  Keeps the fastest (or the longest x
+ * chunk within 3 % of it) for later batched calls on the same shots' grids
+ * in the same order; single-shot calls keep their own shapes.  A batch has
+ * many more workgroups than one shot, so it often prefers longer chunks
+ * (fewer halo planes re-read) than fwi_autotune picks for one shot.
+ * grids, models [device], shots: nshots entries as fwi_gradient_batch
+ * takes them (shared ndim, space order, nt and dt).  Results [host];
+ * synchronises the stream; the batch working fields are cleared. */
+int fwi_autotune_batch(fwi_ctx *ctx, int nshots, const fwi_grid *grids,
+                       const float *const *models, const fwi_shot *shots,
+                       int steps, fwi_tune_result *out, hipStream_t stream);
+
 /* Times one stencil launch shape on grid g the way fwi_autotune times its
  * candidates (steps forward and steps adjoint launches on non-zero fields,
  * buffer roles alternating as in a sweep, after one untimed launch), without

@@ -263,6 +263,9 @@ struct fwi_ctx {
         int xchunk, rpl, remap, deep, vz;
     };
     std::map<std::vector<int>, std::pair<Shape, Shape>> tuned;   // grid key -> (forward, adjoint)
+    // fwi_autotune_batch: x planes per workgroup of the batched launches,
+    // keyed by the batch's grid keys in shot order -> (forward, adjoint)
+    std::map<std::vector<int>, std::pair<int, int>> tuned_batch;
     fwi_stats stats{};
     std::vector<hipEvent_t> evpool;
     size_t evused = 0;
@@ -1274,6 +1277,17 @@ int guarded(F &&f)
 // Walks one action list for several shots in lock step.  Every time step is
 // one launch of the batched stencil over all shots; checkpoint and
 // receiver work stays per shot (each shot has its own stream stack).
+// a batch's identity for its tuned launch shape: the shots' grid keys in order
+static std::vector<int> batch_key(const std::vector<Exec> &ex)
+{
+    std::vector<int> k;
+    for (const Exec &e : ex) {
+        const std::vector<int> g = e.grid_key();
+        k.insert(k.end(), g.begin(), g.end());
+    }
+    return k;
+}
+
 struct BatchExec {
     fwi_ctx *c;
     hipStream_t st;
@@ -1286,6 +1300,19 @@ struct BatchExec {
     // step, so working buffer i (W0 or W1) has the same role in every shot
     hipStream_t cs = nullptr;
     hipEvent_t wmain[2] = {nullptr, nullptr}, wcodec[2] = {nullptr, nullptr}, wdec[2] = {nullptr, nullptr};
+    int bx[2] = {-1, -1};      // tuned batch x chunk (forward, adjoint); 0: the shots' own
+    int batch_xchunk(bool adj)
+    {
+        if (bx[0] < 0) {
+            bx[0] = bx[1] = 0;
+            auto it = c->tuned_batch.find(batch_key(ex));
+            if (it != c->tuned_batch.end()) {
+                bx[0] = it->second.first;
+                bx[1] = it->second.second;
+            }
+        }
+        return bx[adj ? 1 : 0];
+    }
     int wslot(const float *p) const { return ex[0].wslot(p); }
     hipStream_t cst() const { return cs ? cs : st; }
     void main_wait(int i, bool writes)
@@ -1355,6 +1382,7 @@ struct BatchExec {
             // of the batched survey: forward 3.05-3.09 ms in order 0 against
             // 3.10-3.37 ms in orders 2-4)
             h[i].p.remap = 0;
+            if (const int xc = batch_xchunk(adj)) h[i].p.xchunk = xc;
             h[i].first = first;
             // every shot starts on a multiple of 8 workgroups, so that its
             // tile order sees the XCD a workgroup runs on (hardware deals
@@ -3097,6 +3125,120 @@ int fwi_time_shape(fwi_ctx *c, const fwi_grid *g, const float *m, const fwi_shot
         (void)hipEventDestroy(e1);
         HIPCHK(hipMemsetAsync(c->sb.arena.p, 0, c->sb.arena.n, st));
         HIPCHK(hipStreamSynchronize(st));
+    });
+}
+
+int fwi_autotune_batch(fwi_ctx *c, int nshots, const fwi_grid *grids, const float *const *models,
+                       const fwi_shot *shots, int steps, fwi_tune_result *out, hipStream_t st)
+{
+    return guarded([&] {
+        if (!c || nshots < 1 || !grids || !models || !shots || !out)
+            throw Error{FWI_EINVAL, "null argument or nshots < 1"};
+        if (steps < 1) throw Error{FWI_EINVAL, "steps must be >= 1"};
+        for (int i = 0; i < nshots; ++i) {
+            if (!models[i]) throw Error{FWI_EINVAL, "null model of shot " + std::to_string(i)};
+            const fwi_grid &a = grids[0], &b = grids[i];
+            if (b.ndim != a.ndim || b.space_order != a.space_order || b.nt != a.nt || b.dt != a.dt)
+                throw Error{FWI_EINVAL, "batched shots must share ndim, space order, nt and dt"};
+        }
+        HIPCHK(hipSetDevice(c->device));
+        std::vector<Setup> setups;
+        setups.reserve(nshots);
+        for (int i = 0; i < nshots; ++i) setups.push_back(make_setup(&grids[i], &shots[i], true));
+        while ((int)c->batch.size() < nshots) c->batch.push_back(std::make_unique<ShotBufs>());
+        std::vector<Exec> ex;
+        ex.reserve(nshots);
+        for (int i = 0; i < nshots; ++i) {
+            ShotBufs *b = c->batch[i].get();
+            ensure_fields(b, setups[i]);
+            ex.push_back(Exec{c, setups[i], st, models[i], &shots[i], b});
+            // non-zero data in every field the steps read, as fwi_autotune times
+            HIPCHK(hipMemsetAsync(b->arena.p, 0, b->arena.n, st));
+            ex.back().init_fields();
+            for (float *f : {b->fa.p, b->fb.p, b->la.p, b->lb.p, b->gacc.p})
+                launch_copy(f, b->coef.p, b->padded_elems, st);
+        }
+        const int ndim = setups[0].ndim, R = setups[0].R;
+        std::vector<int> cands = ndim == 3 ? std::vector<int>{8, 16, 32, 64} : std::vector<int>{4, 8, 16, 32, 64};
+        // two launch tables (buffer roles alternate from one launch to the next)
+        const size_t tb = ((size_t)nshots * sizeof(BatchEntry) + 255) & ~(size_t)255;
+        c->btab.ensure(2 * tb);
+        auto table = [&](int xc, bool adj, int parity, BatchEntry *h) {
+            int first = 0;
+            for (int i = 0; i < nshots; ++i) {
+                StepParams p = ex[i].params();
+                p.xchunk = xc;
+                p.rpl = 2;              // as the batched launches run
+                p.vz = 1;
+                p.remap = 0;
+                p.deep = 0;
+                ShotBufs *b = ex[i].B;
+                float *a = parity ? b->fb.p : b->fa.p, *o = parity ? b->fa.p : b->fb.p;
+                if (adj) {
+                    float *l1 = parity ? b->lb.p : b->la.p, *l2 = parity ? b->la.p : b->lb.p;
+                    p.u1 = l1; p.u2 = l2; p.out = l2; p.uk = a; p.g = b->gacc.p;
+                } else {
+                    p.u1 = a; p.u2 = o; p.out = o; p.wav = shots[i].wavelet; p.step = 0;
+                }
+                h[i] = BatchEntry{};
+                h[i].p = p;
+                h[i].first = first;
+                const int g = step_geometry(h[i], ndim, adj);
+                first += ndim == 3 ? (g + 7) & ~7 : g;
+            }
+            return first;
+        };
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        auto time_it = [&](int xc, bool adj) {
+            BatchEntry *h[2] = {(BatchEntry *)c->btab.host, (BatchEntry *)(c->btab.host + tb)};
+            BatchEntry *d[2] = {(BatchEntry *)c->btab.dev.p, (BatchEntry *)(c->btab.dev.p + tb)};
+            const int total = table(xc, adj, 0, h[0]);
+            table(xc, adj, 1, h[1]);
+            HIPCHK(hipMemcpyAsync(c->btab.dev.p, c->btab.host, 2 * tb, hipMemcpyHostToDevice, st));
+            launch_step_batch(d[0], h[0], nshots, total, ndim, R, adj, st);
+            HIPCHK(hipEventRecord(e0, st));
+            for (int i = 1; i <= steps; ++i) launch_step_batch(d[i & 1], h[i & 1], nshots, total, ndim, R, adj, st);
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));     // the host tables are rewritten for the next candidate
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            return (double)ms / steps;
+        };
+        // every candidate four times, interleaved; the fastest mean, or the
+        // longest x chunk within 3 % of it (fewer halo planes re-read)
+        std::vector<double> tf(cands.size(), 0.0), ta(cands.size(), 0.0);
+        for (int round = 0; round < 4; ++round)
+            for (size_t j = 0; j < cands.size(); ++j) {
+                tf[j] += time_it(cands[j], false);
+                ta[j] += time_it(cands[j], true);
+            }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        auto pick = [&](const std::vector<double> &t) {
+            size_t best = 0;
+            for (size_t j = 1; j < t.size(); ++j)
+                if (t[j] < t[best]) best = j;
+            size_t k = best;
+            for (size_t j = 0; j < t.size(); ++j)
+                if (t[j] <= 1.03 * t[best] && cands[j] > cands[k]) k = j;
+            return k;
+        };
+        const size_t kf = pick(tf), ka = pick(ta);
+        c->tuned_batch[batch_key(ex)] = {cands[kf], cands[ka]};
+        c->drop_graphs();
+        for (auto &up : c->batch) {
+            if (up->arena.p) HIPCHK(hipMemsetAsync(up->arena.p, 0, up->arena.n, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        *out = fwi_tune_result{};
+        out->ncand = (int)cands.size();
+        out->fwd_xchunk = cands[kf]; out->fwd_rows_per_lane = 2; out->fwd_xcd_order = 0;
+        out->adj_xchunk = cands[ka]; out->adj_rows_per_lane = 2; out->adj_xcd_order = 0;
+        out->fwd_ms = tf[kf] / 4;
+        out->adj_ms = ta[ka] / 4;
+        out->fwd_vz = out->adj_vz = 1;
     });
 }
 

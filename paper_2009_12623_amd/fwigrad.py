@@ -90,7 +90,8 @@ EXPORTS = ["fwi_ctx_create", "fwi_ctx_destroy", "fwi_ctx_set_timing", "fwi_ctx_s
            "ckpt_compress_view", "ckpt_decompress_view", "fwi_forward_ckpt_batch",
            "fwi_backward_batch", "fwi_gradient_subsampled", "fwi_forward_span",
            "fwi_ctx_set_overlap", "fwi_time_shape", "fwi_tape_stream", "fwi_gradient_stack",
-           "fwi_backward_stack", "ckpt_compress_static", "ckpt_compress_batch", "ckpt_decompress_batch"]
+           "fwi_backward_stack", "ckpt_compress_static", "ckpt_compress_batch", "ckpt_decompress_batch",
+           "fwi_autotune_batch"]
 
 
 def lib():
@@ -148,6 +149,8 @@ def lib():
                                       ctypes.POINTER(ctypes.c_size_t)]
     L.fwi_autotune.argtypes = [P, ctypes.POINTER(fwi_grid), P, ctypes.POINTER(fwi_shot), I,
                                ctypes.POINTER(fwi_tune_result), P]
+    L.fwi_autotune_batch.argtypes = [P, I, ctypes.POINTER(fwi_grid), ctypes.POINTER(P), ctypes.POINTER(fwi_shot), I,
+                                     ctypes.POINTER(fwi_tune_result), P]
     L.fwi_gradient_stack.argtypes = [P, I, ctypes.POINTER(fwi_grid), ctypes.POINTER(P),
                                      ctypes.POINTER(fwi_shot), ctypes.POINTER(P),
                                      ctypes.POINTER(fwi_ckpt_cfg), ctypes.POINTER(fwi_stack), P,
@@ -342,6 +345,22 @@ class Context:
         r = fwi_tune_result()
         check(lib().fwi_autotune(self.h, ctypes.byref(g), _ptr(m), ctypes.byref(sa.c), int(steps),
                                  ctypes.byref(r), _stream()))
+        return {k: getattr(r, k) for k, _ in fwi_tune_result._fields_}
+
+    def autotune_batch(self, shots, models, wavelets, steps=4) -> dict:
+        """fwi_autotune_batch: x planes per workgroup of the batched launches
+        for these shots (lists as gradient_batch takes them)"""
+        n = len(shots)
+        if n == 0 or len(models) != n:
+            raise ValueError("one model per shot, at least one shot")
+        if not isinstance(wavelets, (list, tuple)):
+            wavelets = [wavelets] * n
+        sas = [ShotArgs(s, w) for s, w in zip(shots, wavelets)]
+        grids = (fwi_grid * n)(*[grid_of(s) for s in shots])
+        cshots = (fwi_shot * n)(*[sa.c for sa in sas])
+        ms = (ctypes.c_void_p * n)(*[_ptr(m) for m in models])
+        r = fwi_tune_result()
+        check(lib().fwi_autotune_batch(self.h, n, grids, ms, cshots, int(steps), ctypes.byref(r), _stream()))
         return {k: getattr(r, k) for k, _ in fwi_tune_result._fields_}
 
     def time_shape(self, shot, m, wavelet, shape, steps=4):

@@ -158,6 +158,49 @@ def test_batch_tile_orders(xchunk, remap, monkeypatch):
     c.close()
 
 
+@pytest.mark.parametrize("ndim,widths,depth,so", CASES)
+def test_batch_autotune_keeps_gradients(ndim, widths, depth, so):
+    """fwi_autotune_batch picks a listed x chunk for the batched launches;
+    the batch's gradients afterwards equal those before tuning and the
+    single-shot gradients bit for bit (per point the arithmetic does not
+    depend on the chunk), and a tuned batch replays as a captured schedule"""
+    c = F.Context(0, pool_bytes=1 << 28)
+    shots, q32 = cropped_shots(ndim, widths, depth, so)
+    q = dev(q32)
+    models = [dev(m0) for _, m0, _ in shots]
+    dobs = [c.forward(s, dev(mt), q) for s, _, mt in shots]
+    ss = [s for s, _, _ in shots]
+    phis0, g0 = c.gradient_batch(ss, models, q, dobs, nslots=4, compress=True, atol=1e-4)
+    r = c.autotune_batch(ss, models, q, steps=2)
+    allowed = (8, 16, 32, 64) if ndim == 3 else (4, 8, 16, 32, 64)
+    assert r["ncand"] == len(allowed)
+    assert r["fwd_xchunk"] in allowed and r["adj_xchunk"] in allowed and r["fwd_ms"] > 0 and r["adj_ms"] > 0
+    phis, g = c.gradient_batch(ss, models, q, dobs, nslots=4, compress=True, atol=1e-4)
+    assert phis == phis0
+    for a, b in zip(g, g0):
+        assert torch.equal(a, b)
+    for s, m, d, gb in zip(ss, models, dobs, g):
+        _, g1 = c.gradient(s, m, q, d, nslots=4, compress=True, atol=1e-4)
+        assert torch.equal(gb, g1)
+    c.set_graphs(True)
+    for _ in range(2):
+        phis, g = c.gradient_batch(ss, models, q, dobs, nslots=4, compress=True, atol=1e-4)
+        assert phis == phis0
+        for a, b in zip(g, g0):
+            assert torch.equal(a, b)
+    c.close()
+
+
+def test_batch_autotune_rejects_mixed_shots(ctx):
+    shots, q32 = cropped_shots(2, (40, 71), 48, 8)
+    other, _ = cropped_shots(2, (40,), 48, 8, nt=30)
+    ss = [shots[0][0], other[0][0]]
+    models = [dev(shots[0][1]), dev(other[0][1])]
+    with pytest.raises(F.FwiError) as e:
+        ctx.autotune_batch(ss, models, dev(q32))
+    assert e.value.code == F.FWI_EINVAL
+
+
 def crops_with_origins(ndim, widths, depth, so, nbl=5, nt=50, seed=4, amp=3.0):
     """Uneven crops of one model with their origins in the model's physical
     grid: (model shape, [(shot, m0, mt, origin)], wavelet)"""
