@@ -426,7 +426,10 @@ int fwi_autotune(fwi_ctx *ctx, const fwi_grid *g, const float *m,
  * chunk within 3 % of it) for later batched calls on the same shots' grids
  * in the same order; single-shot calls keep their own shapes.  A batch has
  * many more workgroups than one shot, so it often prefers longer chunks
- * (fewer halo planes re-read) than fwi_autotune picks for one shot.
+ * (fewer halo planes re-read) than fwi_autotune picks for one shot.  The
+ * launches are timed alone: where the checkpoint codec runs beside them
+ * (compressed sweeps of large 3D fields) the pick can be slower than the
+ * shots' own shapes, so measure before relying on it there.
  * grids, models [device], shots: nshots entries as fwi_gradient_batch
  * takes them (shared ndim, space order, nt and dt).  Results [host];
  * synchronises the stream; the batch working fields are cleared. */
