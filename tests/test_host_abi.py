@@ -67,6 +67,8 @@ def test_bad_arguments_are_status_codes():
     nb = (ctypes.c_size_t * 1)()
     assert L.ckpt_compress_batch(None, 1, 3, dims, None, 1e-4, None, None, nb, None) == F.FWI_EINVAL
     assert L.ckpt_decompress_batch(None, 1, 3, dims, None, nb, None, None) == F.FWI_EINVAL
+    tr = F.fwi_tune_result()
+    assert L.fwi_autotune_batch(None, 1, None, None, None, 2, ctypes.byref(tr), None) == F.FWI_EINVAL
 
 
 def test_context_creation_without_device_fails_cleanly():
