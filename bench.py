@@ -836,6 +836,8 @@ def run_fwi_loop(args, torch, F, dev):
     ctx = F.Context(0, pool_bytes=8 << 30)
     if not args.no_autotune:
         ctx.autotune(shots[0], m0, q, steps=8)
+        # the 16 shots run batched: their launches get the batch's own x chunk
+        log("batch autotune:", ctx.autotune_batch(shots, [m0] * len(shots), q, steps=4))
     d_obs = [ctx.forward(s, mt, q) for s in shots]
     phys = (slice(nbl, -nbl), slice(nbl, -nbl))
     err0 = rel_l2(m0[phys], mt[phys])
